@@ -1,0 +1,300 @@
+"""Pins for the CPU oracle against things other than itself: the paper's worked
+examples (Figures 1 and 2), hand-derived closed forms, brute-force greatest
+fixpoints and exhaustive partition search on tiny LTSs, the iteration bounds
+of Theorems 2 and 3, Lemma 1, and planted quotients."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_11788_amd import gen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _lts_from(tr, n, K, init=None):
+    src, lab, dst = (np.array(c, np.int32) for c in zip(*tr)) if tr else (np.zeros(0, np.int32),) * 3
+    return gen.LTS(n, K, src, lab, dst, None if init is None else np.array(init, np.int32))
+
+
+# --------------------------------------------------------------------------
+# Figure 2 (section 4.1): the printed preprocessing arrays
+# --------------------------------------------------------------------------
+def test_figure2_preprocessing_arrays():
+    g = _load("figure2.json")
+    L = _lts_from(g["transitions"], g["n"], g["K"])
+    pp = oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst)
+    assert pp["s_src"].tolist() == g["sorted_source"]
+    assert pp["s_lab"].tolist() == g["sorted_action"]
+    assert pp["action_switch"].tolist() == g["action_switch"]
+    assert pp["order"].tolist() == g["order"]
+    assert pp["nr_marks"].tolist() == g["nr_marks"]
+    assert pp["off"].tolist() == g["off_start"]
+    assert (pp["off"] + pp["nr_marks"]).tolist() == g["off_end_printed"]
+    assert pp["mark_length"] == g["mark_length"]
+    assert pp["pre_block"].tolist() == g["final_partition"]
+
+
+def test_figure2_result_and_iterations():
+    g = _load("figure2.json")
+    L = _lts_from(g["transitions"], g["n"], g["K"])
+    r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, trace_cap=16)
+    assert r["block"].tolist() == g["final_partition"]
+    assert r["iters"] == g["iterations_alg3"]
+    b, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst)
+    assert b.tolist() == g["final_partition"] and nb == 3
+    # the generator's figure2() is the same LTS
+    F = gen.figure2()
+    assert sorted(zip(F.src.tolist(), F.lab.tolist(), F.dst.tolist())) == \
+        sorted(map(tuple, g["transitions"]))
+
+
+# --------------------------------------------------------------------------
+# Figure 1 (section 3.2): one iteration with the drawn splitter, then the rest
+# --------------------------------------------------------------------------
+def test_figure1_single_iteration():
+    g = _load("figure1.json")
+    L = _lts_from(g["transitions"], g["n"], 1, g["init"])
+    for variant in (2, 3):
+        r = oracle.alg3_trace(L.n, 1, L.src, L.lab, L.dst, L.init, trace_cap=16,
+                              keep_blocks=True, force_first_C=g["forced_first_splitter"],
+                              variant=variant)
+        assert r["blocks"][0].tolist() == g["after_one_iteration"]
+        assert r["block"].tolist() == g["final_partition"]
+
+
+def test_figure1_full_runs():
+    g = _load("figure1.json")
+    L = _lts_from(g["transitions"], g["n"], 1, g["init"])
+    r3 = oracle.alg3_trace(L.n, 1, L.src, L.lab, L.dst, L.init, trace_cap=16)
+    assert r3["iters"] == g["alg3_iterations"]
+    assert r3["C"].tolist() == g["alg3_splitters"]
+    r2 = oracle.alg3_trace(L.n, 1, L.src, L.lab, L.dst, L.init, trace_cap=16, variant=2)
+    assert r2["iters"] == g["alg2_iterations"]
+    assert r2["block"].tolist() == g["final_partition"]
+    assert oracle.ks_coarsest(L.n, 1, L.src, L.lab, L.dst, L.init)[0].tolist() == g["final_partition"]
+    assert oracle.bruteforce_gfp(L.n, L.src, L.lab, L.dst, L.init).tolist() == g["final_partition"]
+    assert oracle.enumerate_coarsest(L.n, L.src, L.lab, L.dst, L.init).tolist() == g["final_partition"]
+
+
+# --------------------------------------------------------------------------
+# Closed forms
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 10, 33, 100, 700])
+def test_fan_out_closed_form(n):
+    F = gen.fan_out(n)
+    assert F.m == 3 * n - 3
+    r = oracle.alg3_trace(F.n, F.K, F.src, F.lab, F.dst)
+    assert r["iters"] == 2 * n - 4
+    b, nb = oracle.ks_coarsest(F.n, F.K, F.src, F.lab, F.dst)
+    assert nb == n - 1
+    expect = np.arange(n, dtype=np.int32)
+    expect[1] = 0
+    assert b.tolist() == expect.tolist()
+    assert r["block"].tolist() == expect.tolist()
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 17, 200, 1000])
+def test_chain_closed_form(n):
+    C = gen.chain_tail(n)
+    r = oracle.alg3_trace(C.n, C.K, C.src, C.lab, C.dst)
+    assert r["iters"] == 2 * n - 2
+    b, nb = oracle.ks_coarsest(C.n, C.K, C.src, C.lab, C.dst)
+    assert nb == n and b.tolist() == list(range(n))
+
+
+def test_chain_permuted_ids_same_blocks():
+    C = gen.chain_tail(300, permute_seed=5)
+    b, nb = oracle.ks_coarsest(C.n, C.K, C.src, C.lab, C.dst)
+    assert nb == 300
+    r = oracle.alg3_trace(C.n, C.K, C.src, C.lab, C.dst)
+    assert (r["block"] == b).all()
+    assert r["iters"] <= 3 * C.n - 3 + 1
+
+
+def test_trivial_structures():
+    # one action, every state has a successor, pi_0 = {S}: one block
+    L = gen.random_lts(50, 400, 1, seed=3)
+    succ = np.zeros(50, bool)
+    succ[L.src] = True
+    keep = succ
+    assert keep.all()
+    b, nb = oracle.ks_coarsest(L.n, 1, L.src, L.lab, L.dst)
+    assert nb == 1 and (b == 0).all()
+    # empty LTS
+    b, nb = oracle.ks_coarsest(0, 1, [], [], [])
+    assert nb == 0
+    # no transitions: pi_0 is already stable
+    init = np.array([0, 0, 2, 2, 0], np.int32)
+    r = oracle.alg3_trace(5, 1, np.zeros(0), np.zeros(0), np.zeros(0), init)
+    assert r["block"].tolist() == [0, 0, 2, 2, 0] and r["iters"] == 3
+
+
+# --------------------------------------------------------------------------
+# Exhaustive tiny LTSs: definition-level references agree with both oracles
+# --------------------------------------------------------------------------
+def _all_inits(n):
+    """Every partition of {0..n-1}, as init arrays of smallest members."""
+    for part in oracle._set_partitions(list(range(n))):
+        init = np.empty(n, np.int32)
+        for b in part:
+            init[b] = min(b)
+        yield init
+
+
+def _agree(L, enumerate_too=False):
+    ref = oracle.bruteforce_gfp(L.n, L.src, L.lab, L.dst, L.init)
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    r3 = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    assert ks.tolist() == ref.tolist(), L.name
+    assert r3["block"].tolist() == ref.tolist(), L.name
+    assert nb == len(set(ref.tolist()))
+    assert r3["iters"] >= nb + 1
+    assert r3["iters"] <= 3 * L.n - r3["pre_blocks"] + 1
+    if L.K == 1:
+        r2 = oracle.alg3_trace(L.n, 1, L.src, L.lab, L.dst, L.init, variant=2)
+        assert r2["block"].tolist() == ref.tolist()
+        n0 = len(set((L.init if L.init is not None else np.zeros(L.n)).tolist()))
+        assert r2["iters"] <= 2 * L.n - n0 + 1
+    if enumerate_too:
+        assert oracle.enumerate_coarsest(L.n, L.src, L.lab, L.dst, L.init).tolist() == ref.tolist()
+
+
+def test_exhaustive_n2_k2():
+    trans = [(s, a, t) for s in range(2) for a in range(2) for t in range(2)]
+    for mask in range(1 << len(trans)):
+        tr = [trans[i] for i in range(len(trans)) if mask >> i & 1]
+        for init in _all_inits(2):
+            _agree(_lts_from(tr, 2, 2, init), enumerate_too=True)
+
+
+def test_exhaustive_n3_k1():
+    trans = [(s, 0, t) for s in range(3) for t in range(3)]
+    for mask in range(1 << len(trans)):
+        tr = [trans[i] for i in range(len(trans)) if mask >> i & 1]
+        for init in _all_inits(3):
+            _agree(_lts_from(tr, 3, 1, init), enumerate_too=(mask % 7 == 0))
+
+
+def test_random_tiny_against_definitions():
+    rng = np.random.default_rng(2024)
+    for k in range(1500):
+        n = int(rng.integers(1, 8))
+        K = int(rng.integers(1, 4))
+        m = int(rng.integers(0, 15))
+        L = gen.random_lts(n, m, K, seed=10_000 + k, init_blocks=int(rng.integers(0, 3)))
+        _agree(L, enumerate_too=(n <= 6 and k % 5 == 0))
+
+
+# --------------------------------------------------------------------------
+# Invariants on medium random LTSs
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(8))
+def test_invariants_medium(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(20, 300))
+    m = int(rng.integers(0, 4 * n))
+    K = int(rng.integers(1, 6))
+    L = gen.random_lts(n, m, K, seed=seed, init_blocks=int(rng.integers(0, 4)))
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    assert oracle.check_stable(L.n, L.src, L.lab, L.dst, ks)
+    assert oracle.check_canonical(L.n, ks)
+    if L.init is not None:
+        assert oracle.check_refines(L.n, ks, L.init)
+    cap = 3 * n + 2
+    r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init, trace_cap=cap, keep_blocks=True)
+    assert (r["block"] == ks).all()
+    # Theorem 3 bound (plus the final pass) and the #Blocks + 1 lower bound
+    assert nb + 1 <= r["iters"] <= 3 * n - r["pre_blocks"] + 1
+    # Lemma 1: the final partition refines every intermediate one, and every
+    # intermediate partition is canonical under the priority reading
+    for k in range(r["iters"]):
+        assert oracle.check_refines(n, ks, r["blocks"][k])
+        assert oracle.check_canonical(n, r["blocks"][k])
+    # splitters are block labels that exist at the time, and the sequence ends
+    # with the single pass that finds none
+    assert r["C"][-1] == -1 and (r["C"][:-1] >= 0).all()
+    # section 4.1: after preprocessing, the members of a block share their
+    # outgoing action sets
+    pp = oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    acts = [set() for _ in range(n)]
+    for s, a in zip(L.src.tolist(), L.lab.tolist()):
+        acts[s].add(a)
+    for s in range(n):
+        assert acts[s] == acts[pp["pre_block"][s]]
+    assert pp["mark_length"] == sum(len(x) for x in acts) <= max(m, 0)
+
+
+def test_stability_checker_detects_unstable():
+    L = gen.figure1()
+    assert oracle.check_stable(L.n, L.src, L.lab, L.dst, np.array([0, 1, 2, 3, 3]))
+    assert not oracle.check_stable(L.n, L.src, L.lab, L.dst, np.array([0, 0, 2, 3, 3]))
+    assert not oracle.check_canonical(5, np.array([1, 1, 2, 3, 3]))
+    assert not oracle.check_refines(5, np.array([0, 0, 0, 0, 0]), L.init)
+
+
+# --------------------------------------------------------------------------
+# Constructions with a known quotient
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,K", [(1, 1), (2, 4), (3, 16)])
+def test_planted_quotient_lift(seed, K):
+    P = gen.planted_quotient(q=400, deg_mean=3.0, K=K, seed=seed)
+    Q, s2q = P.meta["Q"], P.meta["state_to_q"]
+    qb, qn = oracle.ks_coarsest(Q.n, Q.K, Q.src, Q.lab, Q.dst)
+    pb, pn = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
+    assert pn == qn
+    # states are equivalent iff their quotient nodes are
+    lifted = oracle.canonical_from_classes(P.n, qb[s2q].tolist())
+    assert (pb == lifted).all()
+    r = oracle.alg3_trace(P.n, P.K, P.src, P.lab, P.dst)
+    assert (r["block"] == pb).all()
+
+
+def test_disjoint_union_copies_bisimilar():
+    L = gen.random_lts(40, 120, 3, seed=9)
+    n = L.n
+    U = gen.LTS(2 * n, 3, np.concatenate([L.src, L.src + n]), np.concatenate([L.lab, L.lab]),
+                np.concatenate([L.dst, L.dst + n]))
+    b, _ = oracle.ks_coarsest(U.n, U.K, U.src, U.lab, U.dst)
+    assert (b[:n] == b[n:]).all()
+    single, _ = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst)
+    assert (b[:n] == single).all()
+
+
+def test_product_congruence_one_sided():
+    # bisimilarity is a congruence for this parallel composition: states whose
+    # per-process components are pairwise bisimilar (inside each component
+    # process) are bisimilar in the product.
+    P = gen.sync_product(procs=2, length=6, K=4, shared=(3,), p_shared=0.3, seed=4)
+    b, _ = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
+    lam = P.meta["lam"]
+    comp = []
+    for p in range(2):
+        # component process p alone, as a cycle labelled lam[p]
+        s = np.arange(6)
+        cb, _ = oracle.ks_coarsest(6, 4, s, lam[p], (s + 1) % 6)
+        comp.append(cb)
+    n = P.n
+    st = np.arange(n)
+    key = comp[0][st % 6] * 6 + comp[1][st // 6]
+    for s in range(n):
+        for t in range(s + 1, n):
+            if key[s] == key[t]:
+                assert b[s] == b[t]
+
+
+def test_error_paths():
+    with pytest.raises(oracle.OracleError):
+        oracle.ks_coarsest(3, 1, [0], [0], [3])
+    with pytest.raises(oracle.OracleError):
+        oracle.ks_coarsest(3, 1, [0], [1], [2])
+    with pytest.raises(oracle.OracleError):
+        oracle.alg3_trace(3, 1, [0], [0], [1], init=np.array([0, 0, 5]))
