@@ -1,0 +1,165 @@
+/*
+ * bisim.h — C ABI of the MI355X (gfx950) strong-bisimulation library.
+ *
+ * The library computes the relational coarsest partition of a labelled
+ * transition system: the coarsest refinement of an initial partition pi_0
+ * whose induced relation is a strong bisimulation (section 2, the BCRP and
+ * RCPP problem statements; Definition 2).  It runs the labelled PRAM
+ * refinement of section 4 (Algorithm 3) on the GPU: preprocessing
+ * (section 4.1: per-state action slots, Algorithm 4's split by outgoing
+ * action sets), then repeated iterations of
+ *     select splitter C  ->  mark (state, action) slots whose transition
+ *     targets C  ->  tag states whose marks differ from their block leader's
+ *     ->  elect the smallest tagged state per block as the new leader  ->
+ *     relabel tagged states and update the unstable set,
+ * until no block is unstable.
+ *
+ * Concurrent writes are resolved by priority (section 2.1's priority CRCW
+ * rule): the splitter is the smallest unstable block label and the new leader
+ * of a split-off part is its smallest state.  Under that rule every block
+ * label is the smallest member of its block, so results are canonical
+ * (block id = smallest member) and the iteration count is deterministic.
+ *
+ * Conventions
+ *   - Pointers documented as "device" are GPU global-memory pointers on the
+ *     device that is current when the call is made; "host" pointers are CPU
+ *     memory.  Nothing crosses the ABI as an exception.
+ *   - All work is enqueued on the hip_stream given at load time (NULL = the
+ *     default stream).  Calls that return results to the host synchronise
+ *     that stream.
+ *   - The caller owns every buffer it passes.  Input buffers may be freed once
+ *     the loading call has returned.  A handle owns its device working set
+ *     until it is freed.
+ *   - On error a negative status is returned, outputs are unspecified, a
+ *     failed load leaves *out == NULL, and bisim_last_error() describes the
+ *     failure.  A handle stays usable after a failed call on it.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef BISIM_H
+#define BISIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bisim_status;
+#define BISIM_OK 0
+#define BISIM_E_INVALID -1     /* NULL pointer where one is required, n < 0, m < 0,
+                                  num_actions < 1, unknown option */
+#define BISIM_E_RANGE -2       /* src/dst outside [0,n), label outside [0,K),
+                                  init_partition value outside [0,n) */
+#define BISIM_E_NOMEM -3       /* device or host allocation failed */
+#define BISIM_E_DEVICE -4      /* HIP runtime error */
+#define BISIM_E_ITERCAP -5     /* iteration count exceeded 3n - |pi_pre| + 1, the bound of
+                                  section 4.2's complexity theorem plus the final pass;
+                                  reachable only through the test hook below */
+#define BISIM_E_UNSUPPORTED -6 /* sizes beyond the documented limits */
+
+typedef struct bisim_lts bisim_lts;
+
+typedef struct {
+  int64_t iterations;  /* executions of the while-loop body, counting the final pass
+                          that finds no splitter (Table 1's #It) */
+  int64_t blocks;      /* blocks of the result */
+  int64_t pre_blocks;  /* blocks after preprocessing (the partition the loop starts from) */
+  int64_t mark_length; /* total number of (state, action) mark slots (section 4.1) */
+  double t_pre_ms;     /* lts_load device time: validation, preprocessing, layout */
+  double t_alg_ms;     /* refinement-loop device time of the last coarsest_partition */
+} bisim_stats;
+
+/*
+ * lts_load — validate an LTS and build its device working set
+ * (section 4.1 preprocessing).
+ *   src, label, dst   device, m entries each: transition i is
+ *                     src[i] -label[i]-> dst[i]; any order, duplicates and
+ *                     self-loops allowed (section 2, Definition 1).
+ *   n                 number of states, 0 <= n < 2^31 - 1.
+ *   m                 number of transitions, 0 <= m < 2^32 - 1.
+ *   num_actions       K >= 1; labels lie in [0, K).
+ *   init_partition    device, n entries, or NULL for pi_0 = {S}.  States with
+ *                     equal values share an initial block; values must lie in
+ *                     [0, n) (block labels are state indices, section 3.2).
+ *                     A Kripke structure is num_actions = 1 plus the
+ *                     partition by atomic propositions.
+ *   hip_stream        hipStream_t to enqueue on, or NULL.
+ *   out               host; receives the handle, or NULL on failure.
+ * Errors: BISIM_E_INVALID, BISIM_E_RANGE, BISIM_E_NOMEM, BISIM_E_DEVICE,
+ * BISIM_E_UNSUPPORTED.
+ */
+bisim_status lts_load(const int32_t* src, const int32_t* label, const int32_t* dst, int32_t n,
+                      int64_t m, int32_t num_actions, const int32_t* init_partition,
+                      void* hip_stream, bisim_lts** out);
+
+/*
+ * coarsest_partition — run the refinement loop (Algorithm 3) from the
+ * preprocessed partition to the fixpoint and write the result.
+ *   block_id   device, n entries: block_id[s] = smallest state bisimilar to s
+ *              (within the same initial block).
+ *   st         host, nullable: statistics of this run.
+ * May be called repeatedly on one handle; every call restarts from the
+ * preprocessed partition and gives identical results.
+ * Errors: BISIM_E_INVALID, BISIM_E_DEVICE, BISIM_E_ITERCAP.
+ */
+bisim_status coarsest_partition(bisim_lts* h, int32_t* block_id, bisim_stats* st);
+
+/* lts_free — release a handle and its device memory (NULL is a no-op). */
+void lts_free(bisim_lts* h);
+
+/* bisim_last_error — text for the last failure on the calling thread; valid
+   until the next library call on that thread.  Never NULL. */
+const char* bisim_last_error(void);
+
+/*
+ * bisim_set_option — per-handle settings.
+ *   BISIM_OPT_ENGINE        0 = automatic, 1 = one cooperative persistent
+ *                           launch per fixpoint (grid barriers between
+ *                           phases), 2 = one kernel per phase, launched in
+ *                           batches with a device-side done flag.
+ *   BISIM_OPT_FIRST_SPLITTER  -1 (default) or a block label of the
+ *                           preprocessed partition to use as the first
+ *                           splitter instead of the smallest (test hook, used
+ *                           to replay Figure 1).
+ *   BISIM_OPT_ITER_LIMIT    0 (default: 3n - |pi_pre| + 1) or a smaller cap
+ *                           (test hook for the BISIM_E_ITERCAP path).
+ *   BISIM_OPT_GRID          0 (default: fill the device) or a workgroup count
+ *                           for the persistent engine / per-phase kernels.
+ * Errors: BISIM_E_INVALID.
+ */
+#define BISIM_OPT_ENGINE 1
+#define BISIM_OPT_FIRST_SPLITTER 2
+#define BISIM_OPT_ITER_LIMIT 3
+#define BISIM_OPT_GRID 4
+bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
+
+/*
+ * bisim_set_trace — record, for each iteration k < cap of subsequent
+ * coarsest_partition calls:
+ *   trace_C[k]        the splitter label (-1 for the final pass);
+ *   trace_nsplit[k]   the number of states split off (nullable);
+ *   trace_work[4k..]  (nullable) the members of the splitter, its
+ *                     in-transitions, the states they touch, and whether a
+ *                     touched state was a block leader (0/1) — the
+ *                     data-dependent terms of the iteration's memory traffic.
+ * All device buffers with cap (trace_work: 4 * cap) entries.  cap = 0
+ * disables tracing.
+ * Errors: BISIM_E_INVALID.
+ */
+bisim_status bisim_set_trace(bisim_lts* h, int32_t* trace_C, int64_t* trace_nsplit,
+                             int64_t* trace_work, int64_t cap);
+
+/*
+ * bisim_get_preprocessed — copy the preprocessed partition pi_pre
+ * (section 4.1, Algorithm 4: pi_0 split by outgoing action sets, canonical)
+ * into block_id (device, n entries), and optionally nr_marks (device, n
+ * entries: number of distinct outgoing actions per state).
+ * Errors: BISIM_E_INVALID, BISIM_E_DEVICE.
+ */
+bisim_status bisim_get_preprocessed(bisim_lts* h, int32_t* block_id, int32_t* nr_marks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BISIM_H */

@@ -1,0 +1,288 @@
+"""Python binding of libbisim.so (include/bisim.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module moves
+arrays between host and device and turns status codes into exceptions.
+There is no CPU fallback: if the library is not built or no GPU is present,
+calls fail.
+
+Device buffers are plain HIP allocations made through the same HIP runtime
+that libbisim.so links (ROCm's libamdhip64.so.7), so the library never shares
+a process with a second, differently versioned HIP runtime.  Any object with
+an integer `ptr` attribute (a device address) can be passed where a
+DeviceArray is expected.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbisim.so")
+
+OK = 0
+E_INVALID = -1
+E_RANGE = -2
+E_NOMEM = -3
+E_DEVICE = -4
+E_ITERCAP = -5
+E_UNSUPPORTED = -6
+
+OPT_ENGINE = 1
+OPT_FIRST_SPLITTER = 2
+OPT_ITER_LIMIT = 3
+OPT_GRID = 4
+
+ENGINE_AUTO = 0
+ENGINE_PERSISTENT = 1
+ENGINE_PHASES = 2
+
+EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
+           "bisim_set_option", "bisim_set_trace", "bisim_get_preprocessed"]
+
+
+class BisimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bisim status {status}: {msg}")
+        self.status = status
+
+
+class bisim_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("blocks", ctypes.c_int64),
+                ("pre_blocks", ctypes.c_int64), ("mark_length", ctypes.c_int64),
+                ("t_pre_ms", ctypes.c_double), ("t_alg_ms", ctypes.c_double)]
+
+
+_lib = None
+_hip = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbisim.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2105_11788_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    L = ctypes.CDLL(path)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.lts_load.argtypes = [P, P, P, i32, i64, i32, P, P, ctypes.POINTER(P)]
+    L.lts_load.restype = i32
+    L.coarsest_partition.argtypes = [P, P, ctypes.POINTER(bisim_stats)]
+    L.coarsest_partition.restype = i32
+    L.lts_free.argtypes = [P]
+    L.lts_free.restype = None
+    L.bisim_last_error.argtypes = []
+    L.bisim_last_error.restype = ctypes.c_char_p
+    L.bisim_set_option.argtypes = [P, i32, i64]
+    L.bisim_set_option.restype = i32
+    L.bisim_set_trace.argtypes = [P, P, P, P, i64]
+    L.bisim_set_trace.restype = i32
+    L.bisim_get_preprocessed.argtypes = [P, P, P]
+    L.bisim_get_preprocessed.restype = i32
+    _lib = L
+    return L
+
+
+def hip():
+    """The HIP runtime libbisim.so is linked against (already loaded by it)."""
+    global _hip
+    if _hip is None:
+        load_library()
+        H = ctypes.CDLL("libamdhip64.so.7")
+        P, sz = ctypes.c_void_p, ctypes.c_size_t
+        H.hipMalloc.argtypes = [ctypes.POINTER(P), sz]
+        H.hipFree.argtypes = [P]
+        H.hipMemcpy.argtypes = [P, P, sz, ctypes.c_int]
+        H.hipMemset.argtypes = [P, ctypes.c_int, sz]
+        H.hipGetDeviceCount.argtypes = [ctypes.POINTER(ctypes.c_int)]
+        H.hipDeviceSynchronize.argtypes = []
+        H.hipGetErrorString.argtypes = [ctypes.c_int]
+        H.hipGetErrorString.restype = ctypes.c_char_p
+        for f in ("hipMalloc", "hipFree", "hipMemcpy", "hipMemset", "hipGetDeviceCount",
+                  "hipDeviceSynchronize"):
+            getattr(H, f).restype = ctypes.c_int
+        _hip = H
+    return _hip
+
+
+def _hip_check(rc: int, what: str):
+    if rc != 0:
+        raise BisimError(E_DEVICE, f"{what}: {hip().hipGetErrorString(rc).decode()}")
+
+
+def device_count() -> int:
+    c = ctypes.c_int(0)
+    rc = hip().hipGetDeviceCount(ctypes.byref(c))
+    return c.value if rc == 0 else 0
+
+
+def synchronize():
+    _hip_check(hip().hipDeviceSynchronize(), "hipDeviceSynchronize")
+
+
+_H2D, _D2H, _D2D = 1, 2, 3
+
+
+class DeviceArray:
+    """A 1-D device buffer of a numpy dtype."""
+
+    def __init__(self, count: int, dtype=np.int32):
+        self.dtype = np.dtype(dtype)
+        self.count = int(count)
+        self.nbytes = self.count * self.dtype.itemsize
+        p = ctypes.c_void_p()
+        _hip_check(hip().hipMalloc(ctypes.byref(p), max(self.nbytes, 1)), "hipMalloc")
+        self.ptr = p.value
+
+    @classmethod
+    def from_numpy(cls, a: np.ndarray, dtype=None) -> "DeviceArray":
+        a = np.ascontiguousarray(a, dtype=dtype if dtype is not None else a.dtype)
+        d = cls(a.size, a.dtype)
+        if d.nbytes:
+            _hip_check(hip().hipMemcpy(ctypes.c_void_p(d.ptr), a.ctypes.data_as(ctypes.c_void_p),
+                                       d.nbytes, _H2D), "hipMemcpy H2D")
+        return d
+
+    def numpy(self) -> np.ndarray:
+        out = np.empty(self.count, self.dtype)
+        if self.nbytes:
+            _hip_check(hip().hipMemcpy(out.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(self.ptr),
+                                       self.nbytes, _D2H), "hipMemcpy D2H")
+        return out
+
+    def fill(self, byte: int):
+        _hip_check(hip().hipMemset(ctypes.c_void_p(self.ptr), byte, self.nbytes), "hipMemset")
+        return self
+
+    def free(self):
+        if getattr(self, "ptr", None):
+            hip().hipFree(ctypes.c_void_p(self.ptr))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _check(status: int):
+    if status != OK:
+        raise BisimError(status, _lib.bisim_last_error().decode(errors="replace"))
+
+
+def _dptr(a, name, count=None):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        raise TypeError(f"{name}: pass a DeviceArray (device memory), not a host array")
+    p = getattr(a, "ptr", None)
+    if not isinstance(p, int):
+        raise TypeError(f"{name} must be a DeviceArray or expose an integer device `ptr`")
+    if count is not None and getattr(a, "count", count) != count:
+        raise ValueError(f"{name} must have {count} entries")
+    return ctypes.c_void_p(p)
+
+
+@dataclass
+class Stats:
+    iterations: int
+    blocks: int
+    pre_blocks: int
+    mark_length: int
+    t_pre_ms: float
+    t_alg_ms: float
+
+
+class LTS:
+    """A loaded LTS (lts_load).  src/lab/dst (m entries) and init (n entries
+    or None) are int32 DeviceArrays; numpy arrays are uploaded first."""
+
+    def __init__(self, src, lab, dst, n: int, num_actions: int, init=None,
+                 stream: Optional[int] = None):
+        L = load_library()
+        self._L = L
+        self.n = int(n)
+        self.K = int(num_actions)
+        up = lambda a: DeviceArray.from_numpy(a, np.int32) if isinstance(a, np.ndarray) else a
+        src, lab, dst, init = up(src), up(lab), up(dst), (None if init is None else up(init))
+        self.m = int(getattr(src, "count"))
+        ps, pl, pd = (_dptr(x, nm, self.m) if self.m else None
+                      for x, nm in ((src, "src"), (lab, "label"), (dst, "dst")))
+        pi = _dptr(init, "init_partition", self.n) if (init is not None and self.n) else None
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(L.lts_load(ps, pl, pd, self.n, self.m, self.K, pi,
+                          ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
+        self._h = h
+        self._trace = None
+
+    def set_option(self, option: int, value: int):
+        _check(self._L.bisim_set_option(self._h, option, int(value)))
+
+    def set_trace(self, cap: int, work: bool = False):
+        """Record splitter and split count (and, with work=True, the per-iteration
+        work counters) of the first `cap` iterations of later runs; returns
+        DeviceArrays (trace_C, trace_nsplit[, trace_work of cap*4])."""
+        if cap <= 0:
+            _check(self._L.bisim_set_trace(self._h, None, None, None, 0))
+            self._trace = None
+            return None
+        tc = DeviceArray(cap, np.int32).fill(0xFF)
+        ts = DeviceArray(cap, np.int64).fill(0xFF)
+        tw = DeviceArray(cap * 4, np.int64).fill(0) if work else None
+        _check(self._L.bisim_set_trace(self._h, ctypes.c_void_p(tc.ptr), ctypes.c_void_p(ts.ptr),
+                                       ctypes.c_void_p(tw.ptr) if work else None, cap))
+        self._trace = (tc, ts, tw) if work else (tc, ts)
+        return self._trace
+
+    def run(self, out: Optional[DeviceArray] = None):
+        """coarsest_partition: returns (block_id DeviceArray, Stats)."""
+        if out is None:
+            out = DeviceArray(self.n, np.int32)
+        st = bisim_stats()
+        po = _dptr(out, "block_id", self.n) if self.n else None
+        _check(self._L.coarsest_partition(self._h, po, ctypes.byref(st)))
+        return out, Stats(st.iterations, st.blocks, st.pre_blocks, st.mark_length,
+                          st.t_pre_ms, st.t_alg_ms)
+
+    def preprocessed(self):
+        """(pi_pre block ids, nr_marks) as numpy arrays."""
+        b = DeviceArray(self.n, np.int32)
+        nm = DeviceArray(self.n, np.int32)
+        if self.n:
+            _check(self._L.bisim_get_preprocessed(self._h, ctypes.c_void_p(b.ptr),
+                                                  ctypes.c_void_p(nm.ptr)))
+        return b.numpy(), nm.numpy()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lts_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def coarsest_partition(src, lab, dst, n: int, num_actions: int, init=None,
+                       engine: int = ENGINE_AUTO):
+    """One-shot: load, refine, free.  Returns (block ids as numpy, Stats)."""
+    with LTS(src, lab, dst, n, num_actions, init) as h:
+        if engine:
+            h.set_option(OPT_ENGINE, engine)
+        out, st = h.run()
+        return out.numpy(), st

@@ -1,0 +1,188 @@
+// extern "C" entry points declared in include/bisim.h: argument validation,
+// handle lifetime, error text, options.
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "internal.h"
+
+namespace bisim {
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+static void free_handle(bisim_lts* h) {
+  if (!h) return;
+  hipStream_t s = h->stream;
+  void* ptrs[] = {h->pre_block, h->nr_marks, h->in_ptr, h->in_src, h->in_ord, h->woff,
+                  h->block,     h->mw,       h->tb,     h->lt,     h->ub,     h->nlw,
+                  h->tlist,     h->slist,    h->ctl};
+  for (void* p : ptrs)
+    if (p) (void)hipFreeAsync(p, s);
+  (void)hipStreamSynchronize(s);
+  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete h;
+}
+}  // namespace bisim
+
+using namespace bisim;
+
+extern "C" {
+
+const char* bisim_last_error(void) { return g_err; }
+
+bisim_status lts_load(const int32_t* src, const int32_t* label, const int32_t* dst, int32_t n,
+                      int64_t m, int32_t num_actions, const int32_t* init_partition,
+                      void* hip_stream, bisim_lts** out) {
+  g_err[0] = 0;
+  if (!out) {
+    set_error("lts_load: out is NULL");
+    return BISIM_E_INVALID;
+  }
+  *out = nullptr;
+  if (n < 0 || m < 0 || num_actions < 1) {
+    set_error("lts_load: need n >= 0, m >= 0, num_actions >= 1 (got %d, %lld, %d)", n,
+              (long long)m, num_actions);
+    return BISIM_E_INVALID;
+  }
+  if (m > 0 && (!src || !label || !dst)) {
+    set_error("lts_load: NULL transition array");
+    return BISIM_E_INVALID;
+  }
+  if (m >= 0xFFFFFFFFll || n >= 0x7FFFFFFF) {
+    set_error("lts_load: sizes beyond n < 2^31-1, m < 2^32-1");
+    return BISIM_E_UNSUPPORTED;
+  }
+  bisim_lts* h = new (std::nothrow) bisim_lts;
+  if (!h) {
+    set_error("lts_load: host allocation failed");
+    return BISIM_E_NOMEM;
+  }
+  h->n = n;
+  h->m = m;
+  h->K = num_actions;
+  h->stream = (hipStream_t)hip_stream;
+  bisim_status st = BISIM_OK;
+  do {
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess)
+      e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+    if (e != hipSuccess) {
+      set_error("lts_load: no usable HIP device (%s)", hipGetErrorString(e));
+      st = BISIM_E_DEVICE;
+      break;
+    }
+    if (hipEventRecord(h->ev0, h->stream) != hipSuccess) {
+      st = BISIM_E_DEVICE;
+      break;
+    }
+    st = setup_load(h, src, label, dst, init_partition);
+    if (st != BISIM_OK) break;
+    st = refine_alloc(h);
+    if (st != BISIM_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(h->ev1, h->stream) != hipSuccess ||
+        hipEventSynchronize(h->ev1) != hipSuccess ||
+        hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) {
+      set_error("lts_load: %s", hipGetErrorString(hipGetLastError()));
+      st = BISIM_E_DEVICE;
+      break;
+    }
+    h->t_pre_ms = ms;
+  } while (0);
+  if (st != BISIM_OK) {
+    free_handle(h);
+    return st;
+  }
+  *out = h;
+  return BISIM_OK;
+}
+
+bisim_status coarsest_partition(bisim_lts* h, int32_t* block_id, bisim_stats* st) {
+  g_err[0] = 0;
+  if (!h || (!block_id && h->n > 0)) {
+    set_error("coarsest_partition: NULL handle or output");
+    return BISIM_E_INVALID;
+  }
+  bisim_status rc = refine_run(h, block_id);
+  if (st) {
+    st->iterations = h->last_iters;
+    st->blocks = h->last_blocks;
+    st->pre_blocks = h->pre_blocks;
+    st->mark_length = h->mark_length;
+    st->t_pre_ms = h->t_pre_ms;
+    st->t_alg_ms = h->t_alg_ms;
+  }
+  return rc;
+}
+
+void lts_free(bisim_lts* h) { free_handle(h); }
+
+bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value) {
+  if (!h) {
+    set_error("bisim_set_option: NULL handle");
+    return BISIM_E_INVALID;
+  }
+  switch (option) {
+    case BISIM_OPT_ENGINE:
+      if (value < 0 || value > 2) break;
+      h->engine = (int)value;
+      return BISIM_OK;
+    case BISIM_OPT_FIRST_SPLITTER:
+      if (value < -1 || value >= h->n) break;
+      h->first_splitter = value;
+      return BISIM_OK;
+    case BISIM_OPT_ITER_LIMIT:
+      if (value < 0) break;
+      h->iter_limit = value;
+      return BISIM_OK;
+    case BISIM_OPT_GRID:
+      if (value < 0 || value > (1 << 20)) break;
+      h->grid = (int)value;
+      return BISIM_OK;
+    default:
+      break;
+  }
+  set_error("bisim_set_option: bad option %d or value %lld", option, (long long)value);
+  return BISIM_E_INVALID;
+}
+
+bisim_status bisim_set_trace(bisim_lts* h, int32_t* trace_C, int64_t* trace_nsplit,
+                             int64_t* trace_work, int64_t cap) {
+  if (!h || cap < 0 || (cap > 0 && !trace_C)) {
+    set_error("bisim_set_trace: bad arguments");
+    return BISIM_E_INVALID;
+  }
+  h->trace_C = cap ? trace_C : nullptr;
+  h->trace_nsplit = cap ? trace_nsplit : nullptr;
+  h->trace_work = cap ? trace_work : nullptr;
+  h->trace_cap = cap;
+  return BISIM_OK;
+}
+
+bisim_status bisim_get_preprocessed(bisim_lts* h, int32_t* block_id, int32_t* nr_marks) {
+  if (!h || (!block_id && h->n > 0)) {
+    set_error("bisim_get_preprocessed: NULL handle or output");
+    return BISIM_E_INVALID;
+  }
+  if (h->n > 0) {
+    BISIM_TRY_HIP(hipMemcpyAsync(block_id, h->pre_block, sizeof(int32_t) * (size_t)h->n,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    if (nr_marks)
+      BISIM_TRY_HIP(hipMemcpyAsync(nr_marks, h->nr_marks, sizeof(int32_t) * (size_t)h->n,
+                                   hipMemcpyDeviceToDevice, h->stream));
+  }
+  BISIM_TRY_HIP(hipStreamSynchronize(h->stream));
+  return BISIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Internal declarations shared by the library's translation units: the
+// handle layout, the device control block, wave-level helpers for wave64
+// (CDNA4), and the host entry points of each stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bisim.h"
+
+namespace bisim {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no splitter" / +infinity for labels
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+
+#define BISIM_TRY_HIP(expr)                                                                    \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      ::bisim::set_error("%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return BISIM_E_DEVICE;                                                                   \
+    }                                                                                          \
+  } while (0)
+
+#define BISIM_TRY(expr)                \
+  do {                                 \
+    bisim_status s_ = (expr);          \
+    if (s_ != BISIM_OK) return s_;     \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device control block of one refinement run.  Fields written by atomics from
+// many workgroups sit on their own 128-byte lines.
+// ---------------------------------------------------------------------------
+struct alignas(128) Line {
+  uint32_t v[32];
+};
+struct Ctl {
+  Line cand[2];   // v[0]: splitter for iterations of this parity (min-reduced)
+  Line cntT[2];   // v[0]: touched-state list length
+  Line cntS[2];   // v[0]: split-state list length
+  Line ltany[2];  // v[0]: some block leader was touched
+  Line work[2];   // traced runs only: v[0] members of C, v[1] in-transitions of C
+  Line state;     // v[0] iterations done, v[1] done flag, v[2] error, v[3] current splitter
+  Line bar;       // v[0] arrivals, v[1] generation, v[2] abort
+};
+
+// ---------------------------------------------------------------------------
+// wave helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t t = (uint32_t)__shfl_up((int)v, d, kWave);
+    if ((int)lane() >= d) v += t;
+  }
+  return v;
+}
+
+// Append `val` to list for every lane with pred; one atomic per wave.  Must
+// be reached by all active lanes of the wave.
+__device__ __forceinline__ void wave_push(int32_t* list, uint32_t* counter, int32_t val,
+                                          bool pred) {
+  uint64_t bal = __ballot(pred);
+  if (bal == 0) return;
+  int leader = __ffsll((unsigned long long)bal) - 1;
+  uint32_t base = 0;
+  if ((int)lane() == leader) base = atomicAdd(counter, (uint32_t)__popcll(bal));
+  base = (uint32_t)__shfl((int)base, leader, kWave);
+  if (pred) list[base + __popcll(bal & ((1ull << lane()) - 1ull))] = val;
+}
+
+__device__ __forceinline__ bool test_bit(const uint64_t* bm, uint32_t i) {
+  return (bm[i >> 6] >> (i & 63)) & 1ull;
+}
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+}  // namespace bisim
+
+struct bisim_lts {
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t K = 1;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cu = 0;
+
+  // preprocessed, immutable after load
+  int32_t* pre_block = nullptr;  // [n] pi_pre, canonical
+  int32_t* nr_marks = nullptr;   // [n] distinct outgoing actions per state
+  uint32_t* in_ptr = nullptr;    // [n+1] transitions grouped by target
+  int32_t* in_src = nullptr;     // [m] source of each grouped transition
+  int32_t* in_ord = nullptr;     // [m] its action's rank among the source's actions
+  uint32_t* woff = nullptr;      // [n+1] mark-word offsets (only when !uniform)
+  int uniform = 1;               // every state has <= 64 actions: word index = state
+  uint64_t nwords = 0;
+  int64_t pre_blocks = 0;
+  int64_t mark_length = 0;
+
+  // per-run working set
+  int32_t* block = nullptr;  // [n]
+  uint64_t* mw = nullptr;    // [nwords] packed marks
+  uint64_t* tb = nullptr;    // [ceil(n/64)] touched states
+  uint64_t* lt = nullptr;    // [ceil(n/64)] touched leaders
+  uint64_t* ub = nullptr;    // [ceil(n/64)] unstable block labels
+  uint64_t* nlw = nullptr;   // [n] (epoch << 32) | ~state, max-reduced
+  int32_t* tlist = nullptr;  // [n]
+  int32_t* slist = nullptr;  // [n]
+  bisim::Ctl* ctl = nullptr;
+  bisim::Ctl* ctl_host = nullptr;  // pinned mirror
+
+  // options
+  int engine = 0;
+  int64_t first_splitter = -1;
+  int64_t iter_limit = 0;
+  int grid = 0;
+  int32_t* trace_C = nullptr;
+  int64_t* trace_nsplit = nullptr;
+  int64_t* trace_work = nullptr;
+  int64_t trace_cap = 0;
+
+  double t_pre_ms = 0.0;
+  double t_alg_ms = 0.0;
+  int64_t last_iters = 0;
+  int64_t last_blocks = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace bisim {
+// scan.hip: out[0..count] = exclusive prefix sums of in[0..count), out[count] = total
+bisim_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count,
+                                hipStream_t stream);
+// setup.hip
+bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
+                        const int32_t* dst, const int32_t* init);
+// refine.hip
+bisim_status refine_run(bisim_lts* h, int32_t* block_id);
+bisim_status refine_alloc(bisim_lts* h);
+}  // namespace bisim

@@ -1,0 +1,361 @@
+// Loading and preprocessing (section 4.1), all on the device:
+//   1. validate ranges;
+//   2. bucket transitions by action (LDS-privatised counting for K <= 4096);
+//   3. leaders of pi_0: the smallest state of each initial class;
+//   4. Algorithm 4, one round per action a that occurs: mark the sources of
+//      a-transitions, split states whose mark differs from their leader's,
+//      the smallest such state leading the split-off part.  The same round
+//      hands every a-transition its slot rank order_i = the number of
+//      distinct actions of its source below a (the rank that the
+//      (source, action) sort plus Algorithm 5's segmented scan computes);
+//   5. nr_marks, mark_length, and the packing of mark slots into 64-bit words;
+//   6. transitions regrouped by target (CSR), carrying (source, order), so
+//      that the mark step can visit the in-transitions of the splitter's
+//      members instead of testing all m targets.
+#include <vector>
+
+#include "internal.h"
+
+namespace bisim {
+
+namespace {
+constexpr int kT = 256;
+constexpr int kLdsLabels = 4096;
+constexpr int kChunk = kT * 16;
+
+inline unsigned grid_for(int64_t work, int num_cu) {
+  int64_t g = (work + kT - 1) / kT;
+  int64_t cap = (int64_t)num_cu * 16;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+#define GSTRIDE(i, count)                                                        \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (count); \
+       i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void k_validate(const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
+                           const int32_t* __restrict__ dst, int64_t m, int32_t n, int32_t K,
+                           const int32_t* __restrict__ init, uint32_t* err) {
+  bool bad = false;
+  GSTRIDE(i, m) {
+    bad |= (uint32_t)src[i] >= (uint32_t)n || (uint32_t)dst[i] >= (uint32_t)n ||
+           (uint32_t)lab[i] >= (uint32_t)K;
+  }
+  if (init) {
+    GSTRIDE(s, (int64_t)n) { bad |= (uint32_t)init[s] >= (uint32_t)n; }
+  }
+  if (bad) atomicOr(err, 1u);
+}
+
+__global__ void __launch_bounds__(kT) k_lab_hist(const int32_t* __restrict__ lab, int64_t m,
+                                                 int32_t K, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t h[kLdsLabels];
+  const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+  const int64_t c1 = min(c0 + kChunk, m);
+  if (K <= kLdsLabels) {
+    for (int a = threadIdx.x; a < K; a += kT) h[a] = 0;
+    __syncthreads();
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kT) atomicAdd(&h[lab[i]], 1u);
+    __syncthreads();
+    for (int a = threadIdx.x; a < K; a += kT)
+      if (h[a]) atomicAdd(&cnt[a], h[a]);
+  } else {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kT) atomicAdd(&cnt[lab[i]], 1u);
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_lab_scatter(const int32_t* __restrict__ lab, int64_t m,
+                                                    int32_t K, uint32_t* __restrict__ cursor,
+                                                    uint32_t* __restrict__ idx) {
+  __shared__ uint32_t h[kLdsLabels];
+  const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+  const int64_t c1 = min(c0 + kChunk, m);
+  if (K <= kLdsLabels) {
+    for (int a = threadIdx.x; a < K; a += kT) h[a] = 0;
+    __syncthreads();
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kT) atomicAdd(&h[lab[i]], 1u);
+    __syncthreads();
+    for (int a = threadIdx.x; a < K; a += kT)
+      if (h[a]) h[a] = atomicAdd(&cursor[a], h[a]);
+    __syncthreads();
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kT) {
+      uint32_t p = atomicAdd(&h[lab[i]], 1u);
+      idx[p] = (uint32_t)i;
+    }
+  } else {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kT) {
+      uint32_t p = atomicAdd(&cursor[lab[i]], 1u);
+      idx[p] = (uint32_t)i;
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
+  GSTRIDE(i, count) { p[i] = v; }
+}
+
+// new_leader[I_s] := s, the smallest s winning
+__global__ void k_init_leaders_min(int32_t n, const int32_t* __restrict__ init,
+                                   uint32_t* __restrict__ newl) {
+  GSTRIDE(s, (int64_t)n) { atomicMin(&newl[init[s]], (uint32_t)s); }
+}
+__global__ void k_init_leaders_set(int32_t n, const int32_t* __restrict__ init,
+                                   const uint32_t* __restrict__ newl,
+                                   int32_t* __restrict__ block) {
+  GSTRIDE(s, (int64_t)n) { block[s] = init ? (int32_t)newl[init[s]] : 0; }
+}
+
+// Algorithm 4, round a: mark sources of a-transitions and rank the action.
+__global__ void k_round_mark(const uint32_t* __restrict__ idx, uint32_t beg, uint32_t end,
+                             const int32_t* __restrict__ src, const int32_t* __restrict__ cnt,
+                             int32_t* __restrict__ ord, uint8_t* __restrict__ has) {
+  GSTRIDE(j, (int64_t)(end - beg)) {
+    uint32_t i = idx[beg + j];
+    int32_t s = src[i];
+    ord[i] = cnt[s];
+    has[s] = 1;
+  }
+}
+// ... tag states whose mark differs from their leader's and elect (max of
+// (epoch, ~s) == smallest s of this round)
+__global__ void k_round_split(int32_t n, const int32_t* __restrict__ block,
+                              const uint8_t* __restrict__ has, uint64_t* __restrict__ nlw,
+                              uint8_t* __restrict__ flag, uint64_t epoch) {
+  GSTRIDE(s, (int64_t)n) {
+    int32_t b = block[s];
+    if (has[s] != has[b]) {
+      atomicMax((unsigned long long*)&nlw[b],
+                (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
+      flag[s] = 1;
+    }
+  }
+}
+// ... relabel, and advance every marked state's action count
+__global__ void k_round_relabel(int32_t n, int32_t* __restrict__ block,
+                                const uint64_t* __restrict__ nlw, uint8_t* __restrict__ flag,
+                                uint8_t* __restrict__ has, int32_t* __restrict__ cnt) {
+  GSTRIDE(s, (int64_t)n) {
+    if (flag[s]) {
+      block[s] = (int32_t)(kNone - (uint32_t)nlw[block[s]]);
+      flag[s] = 0;
+    }
+    if (has[s]) {
+      cnt[s] += 1;
+      has[s] = 0;
+    }
+  }
+}
+
+// red[0] = max nr_marks, red[1] = #leaders; red64 = sum nr_marks
+__global__ void k_reduce(int32_t n, const int32_t* __restrict__ cnt,
+                         const int32_t* __restrict__ block, uint32_t* red,
+                         unsigned long long* red64) {
+  uint32_t mx = 0, leaders = 0;
+  unsigned long long sum = 0;
+  GSTRIDE(s, (int64_t)n) {
+    uint32_t c = (uint32_t)cnt[s];
+    mx = max(mx, c);
+    sum += c;
+    leaders += (block[s] == (int32_t)s);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+    leaders += (uint32_t)__shfl_xor((int)leaders, d, kWave);
+    sum += (unsigned long long)__shfl_xor((long long)sum, d, kWave);
+  }
+  if (lane() == 0) {
+    atomicMax(&red[0], mx);
+    atomicAdd(&red[1], leaders);
+    atomicAdd(red64, sum);
+  }
+}
+
+__global__ void k_words(int32_t n, const int32_t* __restrict__ cnt, uint32_t* __restrict__ w) {
+  GSTRIDE(s, (int64_t)n) { w[s] = ((uint32_t)cnt[s] + 63u) >> 6; }
+}
+
+__global__ void k_indeg(const int32_t* __restrict__ dst, int64_t m, uint32_t* __restrict__ deg) {
+  GSTRIDE(i, m) { atomicAdd(&deg[dst[i]], 1u); }
+}
+
+__global__ void k_in_scatter(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                             const int32_t* __restrict__ ord, int64_t m,
+                             uint32_t* __restrict__ cursor, int32_t* __restrict__ in_src,
+                             int32_t* __restrict__ in_ord) {
+  GSTRIDE(i, m) {
+    uint32_t p = atomicAdd(&cursor[dst[i]], 1u);
+    in_src[p] = src[i];
+    in_ord[p] = ord[i];
+  }
+}
+
+template <class T>
+bisim_status dalloc(T** p, size_t count, hipStream_t s) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMallocAsync((void**)p, sizeof(T) * count, s);
+  if (e != hipSuccess) {
+    set_error("device allocation of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
+    return BISIM_E_NOMEM;
+  }
+  return BISIM_OK;
+}
+
+struct Temps {
+  hipStream_t s = nullptr;
+  std::vector<void*> ptrs;
+  template <class T>
+  bisim_status get(T** p, size_t count) {
+    BISIM_TRY(dalloc(p, count, s));
+    ptrs.push_back((void*)*p);
+    return BISIM_OK;
+  }
+  ~Temps() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+};
+}  // namespace
+
+bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
+                        const int32_t* dst, const int32_t* init) {
+  const int32_t n = h->n;
+  const int64_t m = h->m;
+  const int32_t K = h->K;
+  hipStream_t st = h->stream;
+  const int cu = h->num_cu;
+  Temps tmp;
+  tmp.s = st;
+
+  // 1. validation
+  uint32_t* err;
+  BISIM_TRY(tmp.get(&err, 1));
+  BISIM_TRY_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), st));
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(m > n ? m : n, cu)), dim3(kT), 0, st, src, lab,
+                     dst, m, n, K, init, err);
+  BISIM_TRY_HIP(hipGetLastError());
+  uint32_t err_h = 0;
+  BISIM_TRY_HIP(hipMemcpyAsync(&err_h, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  BISIM_TRY_HIP(hipStreamSynchronize(st));
+  if (err_h) {
+    set_error("lts_load: a source/target is outside [0,n), a label outside [0,K), or an "
+              "init_partition value outside [0,n)");
+    return BISIM_E_RANGE;
+  }
+
+  // persistent preprocessed arrays
+  BISIM_TRY(dalloc(&h->pre_block, (size_t)n, st));
+  BISIM_TRY(dalloc(&h->nr_marks, (size_t)n, st));
+  BISIM_TRY(dalloc(&h->in_ptr, (size_t)n + 1, st));
+  BISIM_TRY(dalloc(&h->in_src, (size_t)m, st));
+  BISIM_TRY(dalloc(&h->in_ord, (size_t)m, st));
+
+  int32_t* ord;
+  uint32_t *lab_cnt, *lab_ptr, *cursor, *idx, *newl, *red;
+  uint8_t *has, *flag;
+  uint64_t* nlw;
+  unsigned long long* red64;
+  BISIM_TRY(tmp.get(&ord, (size_t)m));
+  BISIM_TRY(tmp.get(&lab_cnt, (size_t)K));
+  BISIM_TRY(tmp.get(&lab_ptr, (size_t)K + 1));
+  BISIM_TRY(tmp.get(&cursor, (size_t)(K > n ? K : n) + 1));
+  BISIM_TRY(tmp.get(&idx, (size_t)m));
+  BISIM_TRY(tmp.get(&newl, (size_t)n));
+  BISIM_TRY(tmp.get(&red, 4));
+  BISIM_TRY(tmp.get(&red64, 1));
+  BISIM_TRY(tmp.get(&has, (size_t)n));
+  BISIM_TRY(tmp.get(&flag, (size_t)n));
+  BISIM_TRY(tmp.get(&nlw, (size_t)n));
+
+  // 2. bucket transitions by action
+  BISIM_TRY_HIP(hipMemsetAsync(lab_cnt, 0, sizeof(uint32_t) * K, st));
+  const unsigned chunks = (unsigned)((m + kChunk - 1) / kChunk);
+  if (m > 0) {
+    hipLaunchKernelGGL(k_lab_hist, dim3(chunks), dim3(kT), 0, st, lab, m, K, lab_cnt);
+    BISIM_TRY_HIP(hipGetLastError());
+  }
+  BISIM_TRY(exclusive_scan_u32(lab_cnt, lab_ptr, K, st));
+  BISIM_TRY_HIP(hipMemcpyAsync(cursor, lab_ptr, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, st));
+  if (m > 0) {
+    hipLaunchKernelGGL(k_lab_scatter, dim3(chunks), dim3(kT), 0, st, lab, m, K, cursor, idx);
+    BISIM_TRY_HIP(hipGetLastError());
+  }
+  std::vector<uint32_t> lp((size_t)K + 1);
+  BISIM_TRY_HIP(hipMemcpyAsync(lp.data(), lab_ptr, sizeof(uint32_t) * (K + 1),
+                               hipMemcpyDeviceToHost, st));
+
+  // 3. leaders of pi_0
+  const unsigned gn = grid_for(n, cu);
+  if (init) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(gn), dim3(kT), 0, st, newl, kNone, (int64_t)n);
+    hipLaunchKernelGGL(k_init_leaders_min, dim3(gn), dim3(kT), 0, st, n, init, newl);
+  }
+  hipLaunchKernelGGL(k_init_leaders_set, dim3(gn), dim3(kT), 0, st, n, init, newl, h->pre_block);
+  BISIM_TRY_HIP(hipGetLastError());
+
+  // 4. Algorithm 4 rounds, fused with the action ranking
+  BISIM_TRY_HIP(hipMemsetAsync(has, 0, (size_t)n, st));
+  BISIM_TRY_HIP(hipMemsetAsync(flag, 0, (size_t)n, st));
+  BISIM_TRY_HIP(hipMemsetAsync(h->nr_marks, 0, sizeof(int32_t) * (size_t)n, st));
+  BISIM_TRY_HIP(hipMemsetAsync(nlw, 0, sizeof(uint64_t) * (size_t)n, st));
+  BISIM_TRY_HIP(hipStreamSynchronize(st));  // lp is ready
+  uint64_t epoch = 0;
+  for (int32_t a = 0; a < K; ++a) {
+    const uint32_t b0 = lp[a], b1 = lp[a + 1];
+    if (b1 == b0) continue;
+    ++epoch;
+    hipLaunchKernelGGL(k_round_mark, dim3(grid_for(b1 - b0, cu)), dim3(kT), 0, st, idx, b0, b1,
+                       src, h->nr_marks, ord, has);
+    hipLaunchKernelGGL(k_round_split, dim3(gn), dim3(kT), 0, st, n, h->pre_block, has, nlw, flag,
+                       epoch << 32);
+    hipLaunchKernelGGL(k_round_relabel, dim3(gn), dim3(kT), 0, st, n, h->pre_block, nlw, flag, has,
+                       h->nr_marks);
+    BISIM_TRY_HIP(hipGetLastError());
+  }
+
+  // 5. slot statistics and mark-word layout
+  BISIM_TRY_HIP(hipMemsetAsync(red, 0, sizeof(uint32_t) * 4, st));
+  BISIM_TRY_HIP(hipMemsetAsync(red64, 0, sizeof(unsigned long long), st));
+  hipLaunchKernelGGL(k_reduce, dim3(gn), dim3(kT), 0, st, n, h->nr_marks, h->pre_block, red,
+                     red64);
+  BISIM_TRY_HIP(hipGetLastError());
+  uint32_t red_h[4];
+  unsigned long long red64_h = 0;
+  BISIM_TRY_HIP(hipMemcpyAsync(red_h, red, sizeof(red_h), hipMemcpyDeviceToHost, st));
+  BISIM_TRY_HIP(hipMemcpyAsync(&red64_h, red64, sizeof(red64_h), hipMemcpyDeviceToHost, st));
+  BISIM_TRY_HIP(hipStreamSynchronize(st));
+  h->pre_blocks = red_h[1];
+  h->mark_length = (int64_t)red64_h;
+  h->uniform = red_h[0] <= 64;
+  if (h->uniform) {
+    h->nwords = (uint64_t)n;
+  } else {
+    uint32_t* words;
+    BISIM_TRY(tmp.get(&words, (size_t)n));
+    BISIM_TRY(dalloc(&h->woff, (size_t)n + 1, st));
+    hipLaunchKernelGGL(k_words, dim3(gn), dim3(kT), 0, st, n, h->nr_marks, words);
+    BISIM_TRY(exclusive_scan_u32(words, h->woff, n, st));
+    uint32_t nw = 0;
+    BISIM_TRY_HIP(hipMemcpyAsync(&nw, h->woff + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    BISIM_TRY_HIP(hipStreamSynchronize(st));
+    h->nwords = nw;
+  }
+
+  // 6. transitions grouped by target
+  uint32_t* deg;
+  BISIM_TRY(tmp.get(&deg, (size_t)n));
+  BISIM_TRY_HIP(hipMemsetAsync(deg, 0, sizeof(uint32_t) * (size_t)n, st));
+  if (m > 0) hipLaunchKernelGGL(k_indeg, dim3(grid_for(m, cu)), dim3(kT), 0, st, dst, m, deg);
+  BISIM_TRY(exclusive_scan_u32(deg, h->in_ptr, n, st));
+  BISIM_TRY_HIP(hipMemcpyAsync(cursor, h->in_ptr, sizeof(uint32_t) * (size_t)n,
+                               hipMemcpyDeviceToDevice, st));
+  if (m > 0)
+    hipLaunchKernelGGL(k_in_scatter, dim3(grid_for(m, cu)), dim3(kT), 0, st, src, dst, ord, m,
+                       cursor, h->in_src, h->in_ord);
+  BISIM_TRY_HIP(hipGetLastError());
+  return BISIM_OK;
+}
+
+}  // namespace bisim

@@ -1,0 +1,44 @@
+"""CPU-side checks of the C ABI: the library loads without a GPU and exports
+every function that include/bisim.h declares."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "bisim.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b([a-z_][a-z0-9_]*)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_header_declares_expected():
+    from paper_2105_11788_amd import bisim
+    assert set(bisim.EXPORTS) <= set(header_functions())
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2105_11788_amd import bisim
+    if not os.path.exists(bisim.LIB_PATH):
+        pytest.skip("libbisim.so not built")
+    L = bisim.load_library()
+    for name in header_functions():
+        assert hasattr(L, name), name
+
+
+def test_last_error_without_gpu():
+    from paper_2105_11788_amd import bisim
+    if not os.path.exists(bisim.LIB_PATH):
+        pytest.skip("libbisim.so not built")
+    L = bisim.load_library()
+    assert isinstance(L.bisim_last_error(), bytes)
+    # argument validation happens before any device call
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.lts_load(None, None, None, -1, 0, 1, None, None, ctypes.byref(h)) == bisim.E_INVALID
+    assert b"n >= 0" in L.bisim_last_error()
+    assert L.lts_load(None, None, None, 1, 0, 0, None, None, ctypes.byref(h)) == bisim.E_INVALID
+    assert L.bisim_set_option(None, 1, 0) == bisim.E_INVALID

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP refinement (through the C ABI) against the CPU oracle.
+
+Bar: bit-exact block ids (canonical, smallest member), identical iteration
+counts, and identical splitter / split-count traces, on both engines."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_11788_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ENGINES = [1, 2]
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2105_11788_amd import bisim
+    bisim.load_library()
+    assert bisim.device_count() > 0, "GPU tests need a GPU"
+    return bisim
+
+
+def dev(L):
+    from paper_2105_11788_amd.bisim import DeviceArray
+    t = lambda a: DeviceArray.from_numpy(a, np.int32)
+    return t(L.src), t(L.lab), t(L.dst), (None if L.init is None else t(L.init))
+
+
+def run_gpu(B, L, engine=1, trace=0, first=-1, grid=0):
+    src, lab, dst, init = dev(L)
+    with B.LTS(src, lab, dst, L.n, L.K, init) as h:
+        h.set_option(B.OPT_ENGINE, engine)
+        if first >= 0:
+            h.set_option(B.OPT_FIRST_SPLITTER, first)
+        if grid:
+            h.set_option(B.OPT_GRID, grid)
+        tr = h.set_trace(trace) if trace else None
+        blk, st = h.run()
+        out = {"block": blk.numpy(), "stats": st}
+        if tr is not None:
+            k = min(st.iterations, trace)
+            out["C"] = tr[0].numpy()[:k]
+            out["nsplit"] = tr[1].numpy()[:k]
+        return out
+
+
+def assert_parity(B, L, engines=ENGINES, trace=True):
+    cap = 3 * L.n + 2 if trace else 0
+    ref = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init, trace_cap=cap)
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    assert (ref["block"] == ks).all()
+    for e in engines:
+        g = run_gpu(B, L, engine=e, trace=cap)
+        assert (g["block"] == ks).all(), (L.name, e)
+        st = g["stats"]
+        assert st.iterations == ref["iters"], (L.name, e, st.iterations, ref["iters"])
+        assert st.blocks == nb and st.pre_blocks == ref["pre_blocks"]
+        if trace:
+            assert (g["C"] == ref["C"]).all(), (L.name, e)
+            assert (g["nsplit"] == ref["nsplit"]).all(), (L.name, e)
+
+
+def test_library_loads(B):
+    assert B.load_library() is not None
+
+
+def test_figure2(B):
+    g = json.load(open(os.path.join(GOLD, "figure2.json")))
+    L = gen.figure2()
+    src, lab, dst, _ = dev(L)
+    with B.LTS(src, lab, dst, L.n, L.K) as h:
+        pb, nm = h.preprocessed()
+        assert pb.tolist() == g["final_partition"]
+        assert nm.tolist() == g["nr_marks"]
+        blk, st = h.run()
+    assert blk.numpy().tolist() == g["final_partition"]
+    assert st.iterations == g["iterations_alg3"] and st.mark_length == g["mark_length"]
+    assert_parity(B, L)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_figure1(B, engine):
+    g = json.load(open(os.path.join(GOLD, "figure1.json")))
+    L = gen.figure1()
+    r = run_gpu(B, L, engine=engine, trace=16)
+    assert r["block"].tolist() == g["final_partition"]
+    assert r["stats"].iterations == g["alg3_iterations"]
+    assert r["C"].tolist() == g["alg3_splitters"]
+    # the iteration drawn in the figure: splitter B_s4 forced first
+    ref = oracle.alg3_trace(L.n, 1, L.src, L.lab, L.dst, L.init, trace_cap=16, keep_blocks=True,
+                            force_first_C=g["forced_first_splitter"])
+    assert ref["blocks"][0].tolist() == g["after_one_iteration"]
+    r2 = run_gpu(B, L, engine=engine, trace=16, first=g["forced_first_splitter"])
+    assert r2["C"].tolist() == ref["C"].tolist()
+    assert r2["stats"].iterations == ref["iters"]
+    assert r2["block"].tolist() == g["final_partition"]
+
+
+@pytest.mark.parametrize("n", [4, 5, 9, 64, 65, 700, 5000])
+def test_fan_out(B, n):
+    L = gen.fan_out(n)
+    for e in ENGINES:
+        r = run_gpu(B, L, engine=e)
+        assert r["stats"].iterations == 2 * n - 4
+        exp = np.arange(n)
+        exp[1] = 0
+        assert (r["block"] == exp).all()
+
+
+@pytest.mark.parametrize("n", [3, 1000, 20000])
+def test_chain(B, n):
+    L = gen.chain_tail(n)
+    for e in ENGINES:
+        r = run_gpu(B, L, engine=e)
+        assert r["stats"].iterations == 2 * n - 2
+        assert (r["block"] == np.arange(n)).all()
+
+
+def test_kripke_uniform_1000(B):
+    """The n=1000, m=5000 Kripke structure: full trace parity."""
+    assert_parity(B, gen.kripke_uniform(1000, 5000, seed=1))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_medium_trace(B, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(50, 3000))
+    m = int(rng.integers(0, 6 * n))
+    K = int(rng.integers(1, 20))
+    L = gen.random_lts(n, m, K, seed=seed, init_blocks=int(rng.integers(0, 5)))
+    assert_parity(B, L)
+
+
+def test_many_tiny(B):
+    rng = np.random.default_rng(7)
+    for k in range(150):
+        n = int(rng.integers(1, 9))
+        L = gen.random_lts(n, int(rng.integers(0, 16)), int(rng.integers(1, 4)), seed=500 + k,
+                           init_blocks=int(rng.integers(0, 3)))
+        assert_parity(B, L, engines=[1 + (k % 2)])
+
+
+def test_more_than_64_actions_per_state(B):
+    """States with > 64 distinct outgoing actions use multi-word mark slots."""
+    rng = np.random.default_rng(3)
+    n, K = 300, 200
+    src = np.repeat(np.arange(n), 90)
+    lab = rng.integers(0, K, size=src.size)
+    dst = rng.integers(0, n, size=src.size)
+    L = gen.LTS(n, K, src, lab, dst)
+    pp = oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst)
+    assert pp["nr_marks"].max() > 64
+    assert_parity(B, L)
+    # a planted quotient whose copies share >64-action sets
+    Q = gen.LTS(20, 150, np.repeat(np.arange(20), 100), rng.integers(0, 150, 2000),
+                rng.integers(0, 20, 2000))
+    P, s2q = gen.expand_quotient(Q, np.random.default_rng(1), 1, 6)
+    assert_parity(B, P)
+
+
+def test_planted_quotient_medium(B):
+    P = gen.planted_quotient(q=2000, deg_mean=8.0, K=16, seed=2)
+    assert_parity(B, P, trace=False)
+    r = run_gpu(B, P, engine=1, trace=200)
+    ref = oracle.alg3_trace(P.n, P.K, P.src, P.lab, P.dst, trace_cap=200)
+    assert (r["C"] == ref["C"]).all() and (r["nsplit"] == ref["nsplit"]).all()
+
+
+def test_empty_and_degenerate(B):
+    c = lambda v: B.DeviceArray.from_numpy(np.array(v, np.int32))
+    z = c([])
+    with B.LTS(z, z, z, 0, 1) as h:
+        blk, st = h.run()
+        assert blk.count == 0 and st.iterations == 1 and st.blocks == 0
+    # no transitions, an initial partition: already stable
+    with B.LTS(z, z, z, 5, 3, c([0, 0, 2, 2, 0])) as h:
+        blk, st = h.run()
+        assert blk.numpy().tolist() == [0, 0, 2, 2, 0] and st.iterations == 3
+    # one state with a self-loop
+    o = c([0])
+    with B.LTS(o, o, o, 1, 1) as h:
+        blk, st = h.run()
+        assert blk.numpy().tolist() == [0] and st.iterations == 2
+
+
+def test_errors(B):
+    c = lambda v: B.DeviceArray.from_numpy(np.array(v, np.int32))
+    with pytest.raises(B.BisimError) as e:
+        B.LTS(c([0]), c([0]), c([3]), 3, 1)
+    assert e.value.status == B.E_RANGE
+    with pytest.raises(B.BisimError) as e:
+        B.LTS(c([0]), c([1]), c([2]), 3, 1)
+    assert e.value.status == B.E_RANGE
+    with pytest.raises(B.BisimError) as e:
+        B.LTS(c([0]), c([0]), c([1]), 3, 1, init=c([0, 0, 7]))
+    assert e.value.status == B.E_RANGE
+    with pytest.raises(B.BisimError) as e:
+        B.LTS(c([0]), c([0]), c([1]), 3, 0)
+    assert e.value.status == B.E_INVALID
+    # iteration cap hook: the chain needs 2n-2 passes
+    L = gen.chain_tail(50)
+    src, lab, dst, _ = dev(L)
+    for eng in ENGINES:
+        with B.LTS(src, lab, dst, L.n, L.K) as h:
+            h.set_option(B.OPT_ENGINE, eng)
+            h.set_option(B.OPT_ITER_LIMIT, 10)
+            with pytest.raises(B.BisimError) as e:
+                h.run()
+            assert e.value.status == B.E_ITERCAP
+            h.set_option(B.OPT_ITER_LIMIT, 0)  # handle stays usable
+            blk, st = h.run()
+            assert st.iterations == 98
+        with pytest.raises(B.BisimError):
+            B.LTS(src, lab, dst, L.n, L.K).set_option(B.OPT_FIRST_SPLITTER, 10**6)
+
+
+def test_repeat_runs_and_grids_deterministic(B):
+    L = gen.planted_quotient(q=1500, deg_mean=6.0, K=8, seed=9)
+    src, lab, dst, _ = dev(L)
+    res = []
+    with B.LTS(src, lab, dst, L.n, L.K) as h:
+        for eng, grid in [(1, 0), (1, 7), (2, 0), (2, 3), (1, 0)]:
+            h.set_option(B.OPT_ENGINE, eng)
+            h.set_option(B.OPT_GRID, grid)
+            tr = h.set_trace(4096)
+            blk, st = h.run()
+            res.append((blk.numpy(), st.iterations, tr[0].numpy()))
+    for b, it, t in res[1:]:
+        assert (b == res[0][0]).all() and it == res[0][1] and (t == res[0][2]).all()
+
+
+# --------------------------------------------------------------------------
+# full-size workloads
+# --------------------------------------------------------------------------
+def test_planted_quotient_1m_full(B):
+    """~1M states, ~8.2M transitions, 16 actions (Zipf 1.1), copies U{1..40}:
+    whole partition vs the Kanellakis-Smolka oracle and the lifted quotient;
+    the first 64 iterations' trace vs the lock-step oracle; Theorem 3 bounds."""
+    P = gen.planted_quotient(q=50_000, deg_mean=8.0, K=16, seed=1)
+    ks, nb = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
+    Q = P.meta["Q"]
+    qb, qn = oracle.ks_coarsest(Q.n, Q.K, Q.src, Q.lab, Q.dst)
+    assert nb == qn
+    r = run_gpu(B, P, engine=1, trace=64)
+    assert (r["block"] == ks).all()
+    st = r["stats"]
+    assert nb + 1 <= st.iterations <= 3 * P.n - st.pre_blocks + 1
+    ref = oracle.alg3_trace(P.n, P.K, P.src, P.lab, P.dst, trace_cap=64, max_iters=64)
+    assert (r["C"] == ref["C"]).all() and (r["nsplit"] == ref["nsplit"]).all()
+
+
+def test_chain_100k_full(B):
+    L = gen.chain_tail(100_000)
+    r = run_gpu(B, L, engine=1)
+    assert r["stats"].iterations == 199_998
+    assert (r["block"] == np.arange(100_000)).all()
+
+
+def test_sync_product_full(B):
+    P = gen.sync_product(seed=1)
+    ks, nb = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
+    r = run_gpu(B, P, engine=1)
+    assert (r["block"] == ks).all()
+    assert r["stats"].iterations <= 3 * P.n - r["stats"].pre_blocks + 1
