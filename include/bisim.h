@@ -158,6 +158,81 @@ bisim_status bisim_set_trace(bisim_lts* h, int32_t* trace_C, int64_t* trace_nspl
  */
 bisim_status bisim_get_preprocessed(bisim_lts* h, int32_t* block_id, int32_t* nr_marks);
 
+/* ------------------------------------------------------------------------ */
+/* Batched refinement: many independent LTSs in one launch                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * The refinement of each instance is the same Algorithm 3 run as above (same
+ * preprocessing, splitter order and iteration count as a single-instance
+ * run of that instance); instances are refined concurrently, one workgroup
+ * per instance, with per-instance fixpoint detection.
+ */
+typedef struct bisim_batch bisim_batch;
+
+typedef struct {
+  int64_t max_iterations;   /* largest per-instance #It */
+  int64_t sum_iterations;   /* sum of per-instance #It */
+  int64_t lds_instances;    /* instances refined with LDS-resident state */
+  int64_t global_instances; /* instances refined with state in global memory */
+  int32_t workgroup_size;   /* threads per workgroup used */
+  int32_t grid;             /* workgroups launched */
+  double t_pre_ms;          /* lts_batch_load device time */
+  double t_alg_ms;          /* device time of the last coarsest_partition_batch */
+} bisim_batch_stats;
+
+/*
+ * lts_batch_load — validate and preprocess `count` LTSs stored back to back.
+ *   count           number of instances, >= 1.
+ *   n_off, m_off    host, count + 1 entries each, non-decreasing from 0:
+ *                   instance k owns states [n_off[k], n_off[k+1]) of the
+ *                   concatenation and transitions [m_off[k], m_off[k+1]).
+ *                   Totals: n_off[count] < 2^31 - 1, m_off[count] < 2^32 - 1.
+ *   src, label, dst device, m_off[count] entries: instance-local ids
+ *                   (src, dst in [0, n_k), label in [0, num_actions[k])).
+ *   num_actions     host, count entries, each >= 1.
+ *   init_partition  device, n_off[count] entries of instance-local values in
+ *                   [0, n_k), or NULL for pi_0 = {S_k} in every instance.
+ *   hip_stream, out as for lts_load.
+ * Errors: BISIM_E_INVALID, BISIM_E_RANGE, BISIM_E_NOMEM, BISIM_E_DEVICE,
+ * BISIM_E_UNSUPPORTED (a state with more than 64 distinct outgoing actions).
+ */
+bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* m_off,
+                            const int32_t* src, const int32_t* label, const int32_t* dst,
+                            const int32_t* num_actions, const int32_t* init_partition,
+                            void* hip_stream, bisim_batch** out);
+
+/*
+ * coarsest_partition_batch — refine every instance to its fixpoint.
+ *   block_id    device, n_off[count] entries: instance-local canonical ids
+ *               (block_id[n_off[k] + s] = smallest state of instance k
+ *               bisimilar to s).
+ *   iterations  host, nullable, count entries: each instance's #It.
+ *   st          host, nullable.
+ * Errors: BISIM_E_INVALID, BISIM_E_DEVICE, BISIM_E_ITERCAP.
+ */
+bisim_status coarsest_partition_batch(bisim_batch* b, int32_t* block_id, int64_t* iterations,
+                                      bisim_batch_stats* st);
+
+/* lts_batch_free — release a batch handle (NULL is a no-op). */
+void lts_batch_free(bisim_batch* b);
+
+/*
+ * bisim_batch_set_option — per-batch settings.
+ *   BISIM_BOPT_WG_SIZE     0 (default: autotuned) or 256, 512, 1024.
+ *   BISIM_BOPT_GRID        0 (default: autotuned) or a workgroup count.
+ *   BISIM_BOPT_LDS_LIMIT   0 (default: the device's per-workgroup LDS) or a
+ *                          smaller byte budget; instances whose state does
+ *                          not fit are refined from global memory.
+ *   BISIM_BOPT_TUNE        1 = re-run the autotuner on the next call even if
+ *                          a cached choice exists.
+ * Errors: BISIM_E_INVALID.
+ */
+#define BISIM_BOPT_WG_SIZE 1
+#define BISIM_BOPT_GRID 2
+#define BISIM_BOPT_LDS_LIMIT 3
+#define BISIM_BOPT_TUNE 4
+bisim_status bisim_batch_set_option(bisim_batch* b, int32_t option, int64_t value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,7 +41,9 @@ ENGINE_PERSISTENT = 1
 ENGINE_PHASES = 2
 
 EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
-           "bisim_set_option", "bisim_set_trace", "bisim_get_preprocessed"]
+           "bisim_set_option", "bisim_set_trace", "bisim_get_preprocessed",
+           "lts_batch_load", "coarsest_partition_batch", "lts_batch_free",
+           "bisim_batch_set_option"]
 
 
 class BisimError(RuntimeError):
@@ -263,6 +265,107 @@ class LTS:
     def close(self):
         if getattr(self, "_h", None):
             self._L.lts_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class bisim_batch_stats(ctypes.Structure):
+    _fields_ = [("max_iterations", ctypes.c_int64), ("sum_iterations", ctypes.c_int64),
+                ("lds_instances", ctypes.c_int64), ("global_instances", ctypes.c_int64),
+                ("workgroup_size", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("t_pre_ms", ctypes.c_double), ("t_alg_ms", ctypes.c_double)]
+
+
+BOPT_WG_SIZE = 1
+BOPT_GRID = 2
+BOPT_LDS_LIMIT = 3
+BOPT_TUNE = 4
+
+
+def _declare_batch(L):
+    if getattr(L, "_batch_declared", False):
+        return
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.lts_batch_load.argtypes = [i32, P, P, P, P, P, P, P, P, ctypes.POINTER(P)]
+    L.lts_batch_load.restype = i32
+    L.coarsest_partition_batch.argtypes = [P, P, P, ctypes.POINTER(bisim_batch_stats)]
+    L.coarsest_partition_batch.restype = i32
+    L.lts_batch_free.argtypes = [P]
+    L.lts_batch_free.restype = None
+    L.bisim_batch_set_option.argtypes = [P, i32, i64]
+    L.bisim_batch_set_option.restype = i32
+    L._batch_declared = True
+
+
+class Batch:
+    """Many LTSs refined in one launch (lts_batch_load / coarsest_partition_batch).
+    `instances` is a sequence of objects with n, K, src, lab, dst, init
+    (numpy, instance-local ids); they are concatenated and uploaded."""
+
+    def __init__(self, instances, stream: Optional[int] = None):
+        L = load_library()
+        _declare_batch(L)
+        self._L = L
+        self.count = len(instances)
+        n_off = np.zeros(self.count + 1, np.int64)
+        m_off = np.zeros(self.count + 1, np.int64)
+        for k, x in enumerate(instances):
+            n_off[k + 1] = n_off[k] + int(x.n)
+            m_off[k + 1] = m_off[k] + int(np.asarray(x.src).size)
+        self.n_off, self.m_off = n_off, m_off
+        self.N = int(n_off[-1])
+        K = np.array([int(x.K) for x in instances], np.int32)
+        cat = lambda f: np.concatenate([np.asarray(f(x), np.int32) for x in instances]) \
+            if self.count else np.zeros(0, np.int32)
+        src = DeviceArray.from_numpy(cat(lambda x: x.src), np.int32)
+        lab = DeviceArray.from_numpy(cat(lambda x: x.lab), np.int32)
+        dst = DeviceArray.from_numpy(cat(lambda x: x.dst), np.int32)
+        has_init = any(x.init is not None for x in instances)
+        init = None
+        if has_init:
+            init = DeviceArray.from_numpy(np.concatenate(
+                [np.asarray(x.init if x.init is not None else np.zeros(x.n), np.int32)
+                 for x in instances]), np.int32)
+        h = ctypes.c_void_p()
+        p = lambda a: ctypes.c_void_p(a.ptr) if (a is not None and a.count) else None
+        _check(L.lts_batch_load(self.count, n_off.ctypes.data_as(ctypes.c_void_p),
+                                m_off.ctypes.data_as(ctypes.c_void_p), p(src), p(lab), p(dst),
+                                K.ctypes.data_as(ctypes.c_void_p), p(init),
+                                ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
+        self._h = h
+
+    def set_option(self, option: int, value: int):
+        _check(self._L.bisim_batch_set_option(self._h, option, int(value)))
+
+    def run(self, out: Optional[DeviceArray] = None):
+        """Returns (block ids DeviceArray, per-instance #It int64 array, stats dict)."""
+        if out is None:
+            out = DeviceArray(self.N, np.int32)
+        its = np.zeros(self.count, np.int64)
+        st = bisim_batch_stats()
+        _check(self._L.coarsest_partition_batch(self._h, ctypes.c_void_p(out.ptr),
+                                                its.ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.byref(st)))
+        return out, its, {f: getattr(st, f) for f, _ in bisim_batch_stats._fields_}
+
+    def split(self, flat: np.ndarray):
+        """Per-instance views of a concatenated result."""
+        return [flat[self.n_off[k]:self.n_off[k + 1]] for k in range(self.count)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lts_batch_free(self._h)
             self._h = None
 
     def __del__(self):

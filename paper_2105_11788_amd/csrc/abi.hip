@@ -30,17 +30,10 @@ static void free_handle(bisim_lts* h) {
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   delete h;
 }
-}  // namespace bisim
-
-using namespace bisim;
-
-extern "C" {
-
-const char* bisim_last_error(void) { return g_err; }
-
-bisim_status lts_load(const int32_t* src, const int32_t* label, const int32_t* dst, int32_t n,
-                      int64_t m, int32_t num_actions, const int32_t* init_partition,
-                      void* hip_stream, bisim_lts** out) {
+static bisim_status load_impl(const int32_t* src, const int32_t* label, const int32_t* dst,
+                              int32_t n, int64_t m, int32_t num_actions,
+                              const int32_t* init_partition, void* hip_stream, bisim_lts** out,
+                              bool with_run_state) {
   g_err[0] = 0;
   if (!out) {
     set_error("lts_load: out is NULL");
@@ -87,8 +80,10 @@ bisim_status lts_load(const int32_t* src, const int32_t* label, const int32_t* d
     }
     st = setup_load(h, src, label, dst, init_partition);
     if (st != BISIM_OK) break;
-    st = refine_alloc(h);
-    if (st != BISIM_OK) break;
+    if (with_run_state) {
+      st = refine_alloc(h);
+      if (st != BISIM_OK) break;
+    }
     float ms = 0.f;
     if (hipEventRecord(h->ev1, h->stream) != hipSuccess ||
         hipEventSynchronize(h->ev1) != hipSuccess ||
@@ -105,6 +100,27 @@ bisim_status lts_load(const int32_t* src, const int32_t* label, const int32_t* d
   }
   *out = h;
   return BISIM_OK;
+}
+
+// preprocessing only (used by the batched loader for the union of instances)
+bisim_status lts_create_union(int32_t n, int64_t m, int32_t K, const int32_t* src,
+                              const int32_t* lab, const int32_t* dst, const int32_t* init,
+                              hipStream_t stream, bisim_lts** out) {
+  return load_impl(src, lab, dst, n, m, K, init, stream, out, false);
+}
+void lts_destroy(bisim_lts* h) { free_handle(h); }
+}  // namespace bisim
+
+using namespace bisim;
+
+extern "C" {
+
+const char* bisim_last_error(void) { return g_err; }
+
+bisim_status lts_load(const int32_t* src, const int32_t* label, const int32_t* dst, int32_t n,
+                      int64_t m, int32_t num_actions, const int32_t* init_partition,
+                      void* hip_stream, bisim_lts** out) {
+  return load_impl(src, label, dst, n, m, num_actions, init_partition, hip_stream, out, true);
 }
 
 bisim_status coarsest_partition(bisim_lts* h, int32_t* block_id, bisim_stats* st) {

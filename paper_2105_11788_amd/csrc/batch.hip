@@ -1,0 +1,850 @@
+// Batched refinement of many independent LTSs in one launch.
+//
+// Loading: the instances are shifted into one id space (instance k's states
+// start at n_off[k]; its initial blocks stay separate) and preprocessed
+// together by the single-instance loader: the preprocessing is per state and
+// per transition, and no block ever spans two instances, so the result is
+// every instance's own preprocessing side by side.
+//
+// Refinement: one launch of a kernel whose workgroups claim instances from a
+// device queue (largest first).  A workgroup runs the whole Algorithm 3 loop
+// of its instance with workgroup barriers between the phases (select+mark,
+// compare+elect, relabel), exactly as the single-instance engines do with grid
+// barriers, so every instance gets the same splitter sequence and #It as a
+// single-instance run.  Instance state (block ids, mark words, new-leader
+// bids, unstable/touched/leader-touched bitmaps) lives in LDS when it fits the
+// workgroup's LDS budget and in a global-memory slice otherwise.  The
+// workgroup size, LDS budget and grid are chosen by an autotuner that times
+// candidate configurations and caches the winner per device and batch shape.
+// The queue reset and the launch are captured once into a hipGraph and
+// replayed.
+#include <sys/stat.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct bisim_batch {
+  int32_t count = 0;
+  int64_t N = 0, M = 0;
+  int32_t Kmax = 1;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  int device = 0, num_cu = 0;
+  int lds_max = 0;
+  bisim_lts* u = nullptr;  // the preprocessed union
+  std::vector<int64_t> n_off;
+  uint32_t* n_off_d = nullptr;  // [count+1]
+  uint32_t* bw_off_d = nullptr; // [count+1] bitmap word offsets
+  int32_t* order_d = nullptr;   // instance ids, largest first
+  int mask64 = 1;               // 64-bit mark words (else 32-bit)
+  // global-tier scratch
+  int32_t* blk = nullptr;
+  uint64_t* mw = nullptr;
+  uint64_t* nlb = nullptr;
+  uint64_t* ub = nullptr;
+  uint64_t* tb = nullptr;
+  uint64_t* lt = nullptr;
+  int32_t* tl = nullptr;
+  int32_t* sl = nullptr;
+  uint32_t* iters_d = nullptr;  // [count]
+  uint32_t* ctl_d = nullptr;    // [0] queue head, [1] error
+  // options / tuning
+  int opt_wg = 0, opt_grid = 0, opt_lds = 0, opt_retune = 0;
+  int wg = 0, grid = 0, lds_bytes = 0;
+  bool tuned = false;
+  hipGraphExec_t gexec = nullptr;
+  int g_wg = -1, g_grid = -1, g_lds = -1;
+  int32_t* g_out = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_pre_ms = 0, t_alg_ms = 0;
+  int64_t lds_inst = 0, glob_inst = 0;
+};
+
+namespace bisim {
+bisim_status lts_create_union(int32_t n, int64_t m, int32_t K, const int32_t* src,
+                              const int32_t* lab, const int32_t* dst, const int32_t* init,
+                              hipStream_t stream, bisim_lts** out);
+void lts_destroy(bisim_lts* h);
+
+namespace {
+constexpr int kT = 256;
+
+struct BArgs {
+  int32_t count;
+  const uint32_t* __restrict__ n_off;
+  const uint32_t* __restrict__ bw_off;
+  const int32_t* __restrict__ order;
+  const int32_t* __restrict__ pre_block;
+  const uint32_t* __restrict__ in_ptr;
+  const int32_t* __restrict__ in_src;
+  const int32_t* __restrict__ in_ord;
+  int32_t* blk;
+  void* mw;
+  uint64_t* nlb;
+  uint64_t* ub;
+  uint64_t* tb;
+  uint64_t* lt;
+  int32_t* tl;
+  int32_t* sl;
+  int32_t* out;
+  uint32_t* iters;
+  uint32_t* ctl;
+  uint32_t lds_bytes;
+};
+
+__device__ __forceinline__ uint32_t atomic_or(uint32_t* p, uint32_t v) { return atomicOr(p, v); }
+__device__ __forceinline__ uint64_t atomic_or(uint64_t* p, uint64_t v) {
+  return atomicOr((unsigned long long*)p, (unsigned long long)v);
+}
+
+template <class MaskT>
+struct WArr {
+  int32_t* blk;
+  MaskT* mw;
+  uint64_t* nlb;
+  uint64_t* ub;
+  uint64_t* tb;
+  uint64_t* lt;
+};
+
+template <class MaskT>
+__host__ __device__ inline uint64_t lds_need(uint32_t n) {
+  const uint64_t nw = (n + 63u) / 64u;
+  return 8ull * 3 * nw + 8ull * n + ((sizeof(MaskT) * (uint64_t)n + 7) & ~7ull) + 4ull * n;
+}
+
+struct Shared {
+  uint32_t cand[2];
+  uint32_t nT[2];
+  uint32_t nS[2];
+  uint32_t ltany[2];
+  uint32_t job;
+};
+
+__device__ __forceinline__ void wg_min(uint32_t* dst, uint32_t v) {
+  v = wave_min_u32(v);
+  if (lane() == 0 && v != kNone) atomicMin(dst, v);
+}
+
+// Append for lanes with pred; one LDS atomic per wave.  Wave-uniform call.
+__device__ __forceinline__ void push(int32_t* list, uint32_t* cnt, int32_t v, bool pred) {
+  uint64_t bal = __ballot(pred);
+  if (!bal) return;
+  int leader = __ffsll((unsigned long long)bal) - 1;
+  uint32_t base = 0;
+  if ((int)lane() == leader) base = atomicAdd(cnt, (uint32_t)__popcll(bal));
+  base = (uint32_t)__shfl((int)base, leader, kWave);
+  if (pred) list[base + __popcll(bal & ((1ull << lane()) - 1ull))] = v;
+}
+
+// The whole refinement loop of one instance by one workgroup.
+template <class MaskT>
+__device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<MaskT> w,
+                                              int32_t* T, int32_t* S, uint32_t s0, uint32_t n) {
+  const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+  const uint32_t wid = tid / kWave, nwav = nthr / kWave;
+  const uint32_t nw = (n + 63u) >> 6;
+  for (uint32_t s = tid; s < n; s += nthr) {
+    w.blk[s] = a.pre_block[s0 + s] - (int32_t)s0;
+    w.mw[s] = 0;
+    w.nlb[s] = 0;
+  }
+  for (uint32_t q = tid; q < nw; q += nthr) {
+    uint64_t bits = 0;
+    for (uint32_t j = 0; j < 64 && (q << 6) + j < n; ++j)
+      if ((uint32_t)(a.pre_block[s0 + (q << 6) + j] - (int32_t)s0) == (q << 6) + j)
+        bits |= 1ull << j;
+    w.ub[q] = bits;
+    w.tb[q] = 0;
+    w.lt[q] = 0;
+  }
+  if (tid == 0) {
+    sh.cand[0] = n ? 0u : kNone;
+    sh.cand[1] = kNone;
+    sh.nT[0] = sh.nT[1] = sh.nS[0] = sh.nS[1] = 0;
+    sh.ltany[0] = sh.ltany[1] = 0;
+  }
+  __syncthreads();
+  const uint32_t cap = 3u * n + 1u;
+  uint32_t it = 0;
+  for (;; ++it) {
+    const uint32_t par = it & 1;
+    const uint32_t C = sh.cand[par];
+    if (C == kNone) break;
+    if (it + 1 > cap) {
+      if (tid == 0) atomicOr(&a.ctl[1], 1u);
+      break;
+    }
+    const uint64_t epoch = (uint64_t)(it + 1) << 32;
+    // ---- A: select next candidate, mark
+    {
+      uint32_t best = kNone;
+      for (uint32_t q = tid; q < nw; q += nthr) {
+        uint64_t bits = w.ub[q];
+        if (q == (C >> 6)) {
+          bits &= ~(1ull << (C & 63));
+          w.ub[q] = bits;
+        }
+        if (bits) best = min(best, (q << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1));
+      }
+      wg_min(&sh.cand[par ^ 1], best);
+      if (tid == 0) {
+        sh.nT[par ^ 1] = 0;
+        sh.nS[par ^ 1] = 0;
+        sh.ltany[par ^ 1] = 0;
+      }
+      for (uint32_t base = wid * kWave; base < n; base += nwav * kWave) {
+        const uint32_t t = base + lane();
+        const bool hit = t < n && (uint32_t)w.blk[t] == C;
+        if (__ballot(hit) == 0) continue;
+        uint32_t beg = 0, deg = 0;
+        if (hit) {
+          beg = a.in_ptr[s0 + t];
+          deg = a.in_ptr[s0 + t + 1] - beg;
+        }
+        const uint32_t incl = wave_incl_scan_u32(deg);
+        const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
+          const uint32_t e = e0 + lane();
+          const bool valid = e < total;
+          const uint32_t ee = valid ? e : total - 1;
+          uint32_t j = 0;
+#pragma unroll
+          for (uint32_t step = 32; step >= 1; step >>= 1) {
+            const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
+            if (probe <= ee) j += step;
+          }
+          const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
+          const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
+          const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
+          bool first = false;
+          int32_t s = 0;
+          if (valid) {
+            const uint32_t edge = jb + (ee - (ji - jd));
+            s = a.in_src[edge] - (int32_t)s0;
+            const int32_t o = a.in_ord[edge];
+            const MaskT bit = (MaskT)1 << (o & (int)(sizeof(MaskT) * 8 - 1));
+            const MaskT old = atomic_or(&w.mw[s], bit);
+            first = (old == 0);
+            if (first) {
+              const uint64_t tbit = 1ull << (s & 63);
+              atomicOr((unsigned long long*)&w.tb[s >> 6], (unsigned long long)tbit);
+              if (w.blk[s] == s) {
+                atomicOr((unsigned long long*)&w.lt[s >> 6], (unsigned long long)tbit);
+                sh.ltany[par] = 1;
+              }
+            }
+          }
+          push(T, &sh.nT[par], s, first);
+        }
+      }
+    }
+    __syncthreads();
+    // ---- B: compare with the leader, elect
+    {
+      const uint32_t nT = sh.nT[par];
+      for (uint32_t i0 = wid * kWave; i0 < nT; i0 += nwav * kWave) {
+        const uint32_t i = i0 + lane();
+        bool sp = false;
+        int32_t s = 0, b = 0;
+        if (i < nT) {
+          s = T[i];
+          b = w.blk[s];
+          sp = (s != b) && (w.mw[s] != w.mw[b]);
+        }
+        if (sp)
+          atomicMax((unsigned long long*)&w.nlb[b],
+                    (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
+        push(S, &sh.nS[par], s, sp);
+      }
+      if (sh.ltany[par]) {
+        for (uint32_t base = wid * kWave; base < n; base += nwav * kWave) {
+          const uint32_t s = base + lane();
+          bool sp = false;
+          int32_t b = 0;
+          if (s < n) {
+            b = w.blk[s];
+            sp = test_bit(w.lt, (uint32_t)b) && !test_bit(w.tb, s);
+          }
+          if (sp)
+            atomicMax((unsigned long long*)&w.nlb[b],
+                      (unsigned long long)(epoch | (uint64_t)(kNone - s)));
+          push(S, &sh.nS[par], (int32_t)s, sp);
+        }
+      }
+    }
+    __syncthreads();
+    // ---- C: relabel, unstable updates, clear marks
+    {
+      const uint32_t nS = sh.nS[par], nT = sh.nT[par];
+      uint32_t best = kNone;
+      for (uint32_t i = tid; i < nS; i += nthr) {
+        const int32_t s = S[i];
+        const int32_t old = w.blk[s];
+        const int32_t nl = (int32_t)(kNone - (uint32_t)w.nlb[old]);
+        w.blk[s] = nl;
+        if (s == nl) {
+          atomicOr((unsigned long long*)&w.ub[old >> 6], 1ull << (old & 63));
+          atomicOr((unsigned long long*)&w.ub[nl >> 6], 1ull << (nl & 63));
+          best = min(best, (uint32_t)old);
+        }
+      }
+      for (uint32_t i = tid; i < nT; i += nthr) {
+        const int32_t s = T[i];
+        w.mw[s] = 0;
+        w.tb[s >> 6] = 0;
+        w.lt[s >> 6] = 0;
+      }
+      wg_min(&sh.cand[par ^ 1], best);
+      if (tid == 0) {
+        if (nS > 0) {
+          atomicOr((unsigned long long*)&w.ub[C >> 6], 1ull << (C & 63));
+          atomicMin(&sh.cand[par ^ 1], C);
+        }
+        sh.cand[par] = kNone;
+      }
+    }
+    __syncthreads();
+  }
+  for (uint32_t s = tid; s < n; s += nthr) a.out[s0 + s] = w.blk[s];
+  return it + 1;
+}
+
+template <class MaskT>
+__global__ void k_batch(BArgs a) {
+  extern __shared__ uint64_t lds[];
+  __shared__ Shared sh;
+  for (;;) {
+    if (threadIdx.x == 0) sh.job = atomicAdd(&a.ctl[0], 1u);
+    __syncthreads();
+    const uint32_t job = sh.job;
+    if (job >= (uint32_t)a.count) break;
+    const int32_t k = a.order[job];
+    const uint32_t s0 = a.n_off[k], n = a.n_off[k + 1] - s0;
+    int32_t* T = a.tl + s0;
+    int32_t* S = a.sl + s0;
+    uint32_t its;
+    if (lds_need<MaskT>(n) <= a.lds_bytes) {
+      const uint32_t nw = (n + 63u) >> 6;
+      WArr<MaskT> w;
+      w.ub = lds;
+      w.tb = lds + nw;
+      w.lt = lds + 2 * nw;
+      w.nlb = lds + 3 * nw;
+      w.mw = reinterpret_cast<MaskT*>(lds + 3 * nw + n);
+      w.blk = reinterpret_cast<int32_t*>(lds + 3 * nw + n + (sizeof(MaskT) * n + 7) / 8);
+      its = wg_refine<MaskT>(a, sh, w, T, S, s0, n);
+    } else {
+      const uint32_t b0 = a.bw_off[k];
+      WArr<MaskT> w;
+      w.blk = a.blk + s0;
+      w.mw = reinterpret_cast<MaskT*>(a.mw) + s0;
+      w.nlb = a.nlb + s0;
+      w.ub = a.ub + b0;
+      w.tb = a.tb + b0;
+      w.lt = a.lt + b0;
+      its = wg_refine<MaskT>(a, sh, w, T, S, s0, n);
+    }
+    if (threadIdx.x == 0) a.iters[k] = its;
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_queue(uint32_t* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+  }
+}
+
+// shift instance-local ids into the union's id space, validating ranges
+__device__ __forceinline__ int32_t find_instance(const uint32_t* off, int32_t count, uint64_t x) {
+  int32_t lo = 0, hi = count;  // off[lo] <= x < off[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((uint64_t)off[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_globalize(int32_t count, const uint32_t* __restrict__ n_off,
+                            const uint32_t* __restrict__ m_off, const int32_t* __restrict__ K,
+                            const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
+                            const int32_t* __restrict__ dst, const int32_t* __restrict__ init,
+                            uint64_t M, uint64_t N, int32_t* __restrict__ gsrc,
+                            int32_t* __restrict__ gdst, int32_t* __restrict__ ginit,
+                            uint32_t* err) {
+  bool bad = false;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += stride) {
+    const int32_t k = find_instance(m_off, count, i);
+    const uint32_t nk = n_off[k + 1] - n_off[k];
+    const int32_t s = src[i], d = dst[i], l = lab[i];
+    bad |= (uint32_t)s >= nk || (uint32_t)d >= nk || (uint32_t)l >= (uint32_t)K[k];
+    gsrc[i] = (int32_t)n_off[k] + ((uint32_t)s < nk ? s : 0);
+    gdst[i] = (int32_t)n_off[k] + ((uint32_t)d < nk ? d : 0);
+  }
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < N; s += stride) {
+    const int32_t k = find_instance(n_off, count, s);
+    const uint32_t nk = n_off[k + 1] - n_off[k];
+    int32_t v = 0;
+    if (init) {
+      v = init[s];
+      bad |= (uint32_t)v >= nk;
+      if ((uint32_t)v >= nk) v = 0;
+    }
+    ginit[s] = (int32_t)n_off[k] + v;
+  }
+  if (bad) atomicOr(err, 1u);
+}
+
+template <class T>
+bisim_status dmalloc(T** p, size_t count) {
+  *p = nullptr;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * (count ? count : 1));
+  if (e != hipSuccess) {
+    set_error("device allocation of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
+    return BISIM_E_NOMEM;
+  }
+  return BISIM_OK;
+}
+
+void free_batch(bisim_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  void* ptrs[] = {b->n_off_d, b->bw_off_d, b->order_d, b->blk, b->mw, b->nlb, b->ub,
+                  b->tb,      b->lt,       b->tl,      b->sl,  b->iters_d, b->ctl_d};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (b->u) lts_destroy(b->u);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+  delete b;
+}
+
+BArgs make_args(bisim_batch* b, int32_t* out) {
+  BArgs a{};
+  a.count = b->count;
+  a.n_off = b->n_off_d;
+  a.bw_off = b->bw_off_d;
+  a.order = b->order_d;
+  a.pre_block = b->u->pre_block;
+  a.in_ptr = b->u->in_ptr;
+  a.in_src = b->u->in_src;
+  a.in_ord = b->u->in_ord;
+  a.blk = b->blk;
+  a.mw = b->mw;
+  a.nlb = b->nlb;
+  a.ub = b->ub;
+  a.tb = b->tb;
+  a.lt = b->lt;
+  a.tl = b->tl;
+  a.sl = b->sl;
+  a.out = out;
+  a.iters = b->iters_d;
+  a.ctl = b->ctl_d;
+  a.lds_bytes = (uint32_t)b->lds_bytes;
+  return a;
+}
+
+bisim_status launch_once(bisim_batch* b, int32_t* out, int wg, int grid, int lds) {
+  BArgs a = make_args(b, out);
+  a.lds_bytes = (uint32_t)lds;
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, b->stream, b->ctl_d);
+  if (b->mask64)
+    hipLaunchKernelGGL(k_batch<uint64_t>, dim3(grid), dim3(wg), lds, b->stream, a);
+  else
+    hipLaunchKernelGGL(k_batch<uint32_t>, dim3(grid), dim3(wg), lds, b->stream, a);
+  BISIM_TRY_HIP(hipGetLastError());
+  return BISIM_OK;
+}
+
+int max_resident(bisim_batch* b, int wg, int lds) {
+  int per_cu = 0;
+  hipError_t e = b->mask64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<uint64_t>, wg, lds)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<uint32_t>, wg, lds);
+  if (e != hipSuccess || per_cu < 1) return 0;
+  return per_cu * b->num_cu;
+}
+
+std::string tune_key(bisim_batch* b) {
+  hipDeviceProp_t p;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&p, b->device) == hipSuccess) arch = p.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  int lc = 0, ln = 0, lm = 0;
+  for (int64_t v = b->count; v > 1; v >>= 1) ++lc;
+  for (int64_t v = b->N; v > 1; v >>= 1) ++ln;
+  for (int64_t v = b->M; v > 1; v >>= 1) ++lm;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s_cu%d_c%d_n%d_m%d_k%d", arch.c_str(), b->num_cu, lc, ln, lm,
+           b->mask64);
+  return buf;
+}
+
+std::string tune_path() {
+  const char* e = getenv("BISIM_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = getenv("HOME");
+  return std::string(h && *h ? h : "/tmp") + "/.cache/bisim_tune.txt";
+}
+
+bool tune_lookup(const std::string& key, int* wg, int* grid, int* lds) {
+  FILE* f = fopen(tune_path().c_str(), "r");
+  if (!f) return false;
+  char k[256];
+  int a, g, l;
+  float ms;
+  bool found = false;
+  while (fscanf(f, "%255s %d %d %d %f", k, &a, &g, &l, &ms) == 5)
+    if (key == k) {
+      *wg = a;
+      *grid = g;
+      *lds = l;
+      found = true;
+    }
+  fclose(f);
+  return found;
+}
+
+void tune_store(const std::string& key, int wg, int grid, int lds, float ms) {
+  std::string path = tune_path();
+  std::string dir = path.substr(0, path.find_last_of('/'));
+  if (!dir.empty()) {
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %d %.4f\n", key.c_str(), wg, grid, lds, ms);
+  fclose(f);
+}
+
+// Autotuner: time each candidate (workgroup size, LDS budget, grid = as many
+// workgroups as stay resident) on the batch itself and keep the fastest.
+bisim_status autotune(bisim_batch* b, int32_t* out) {
+  const int wgs[] = {256, 512, 1024};
+  std::vector<int> budgets;
+  for (int l = b->lds_max; l >= 16384 && budgets.size() < 4; l /= 2) budgets.push_back(l);
+  float best = 1e30f;
+  int bw = 0, bg = 0, bl = 0;
+  for (int wg : wgs) {
+    for (int lds : budgets) {
+      const int grid = max_resident(b, wg, lds);
+      if (grid < 1) continue;
+      BISIM_TRY_HIP(hipEventRecord(b->ev0, b->stream));
+      BISIM_TRY(launch_once(b, out, wg, grid, lds));
+      BISIM_TRY_HIP(hipEventRecord(b->ev1, b->stream));
+      BISIM_TRY_HIP(hipEventSynchronize(b->ev1));
+      float ms = 0;
+      BISIM_TRY_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+      if (ms < best) {
+        best = ms;
+        bw = wg;
+        bg = grid;
+        bl = lds;
+      }
+    }
+  }
+  if (!bw) {
+    set_error("batched kernel: no launch configuration is resident");
+    return BISIM_E_DEVICE;
+  }
+  b->wg = bw;
+  b->grid = bg;
+  b->lds_bytes = bl;
+  tune_store(tune_key(b), bw, bg, bl, best);
+  return BISIM_OK;
+}
+}  // namespace
+}  // namespace bisim
+
+using namespace bisim;
+
+extern "C" {
+
+bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* m_off,
+                            const int32_t* src, const int32_t* label, const int32_t* dst,
+                            const int32_t* num_actions, const int32_t* init_partition,
+                            void* hip_stream, bisim_batch** out) {
+  if (!out) {
+    set_error("lts_batch_load: out is NULL");
+    return BISIM_E_INVALID;
+  }
+  *out = nullptr;
+  if (count < 1 || !n_off || !m_off || !num_actions) {
+    set_error("lts_batch_load: need count >= 1 and host offset/action arrays");
+    return BISIM_E_INVALID;
+  }
+  if (n_off[0] != 0 || m_off[0] != 0) {
+    set_error("lts_batch_load: offsets must start at 0");
+    return BISIM_E_INVALID;
+  }
+  int32_t Kmax = 1;
+  for (int32_t k = 0; k < count; ++k) {
+    if (n_off[k + 1] < n_off[k] || m_off[k + 1] < m_off[k] || num_actions[k] < 1) {
+      set_error("lts_batch_load: offsets must be non-decreasing and num_actions >= 1");
+      return BISIM_E_INVALID;
+    }
+    Kmax = std::max(Kmax, num_actions[k]);
+  }
+  const int64_t N = n_off[count], M = m_off[count];
+  if (N >= 0x7FFFFFFF || M >= 0xFFFFFFFFll) {
+    set_error("lts_batch_load: totals beyond 2^31-1 states / 2^32-1 transitions");
+    return BISIM_E_UNSUPPORTED;
+  }
+  if (M > 0 && (!src || !label || !dst)) {
+    set_error("lts_batch_load: NULL transition array");
+    return BISIM_E_INVALID;
+  }
+  bisim_batch* b = new (std::nothrow) bisim_batch;
+  if (!b) return BISIM_E_NOMEM;
+  b->count = count;
+  b->N = N;
+  b->M = M;
+  b->Kmax = Kmax;
+  b->n_off.assign(n_off, n_off + count + 1);
+  bisim_status st = BISIM_OK;
+  int32_t *gsrc = nullptr, *gdst = nullptr, *ginit = nullptr, *Kd = nullptr;
+  uint32_t *m_off_d = nullptr, *err = nullptr;
+  do {
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess)
+      e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess)
+      e = hipDeviceGetAttribute(&b->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+    if (e == hipSuccess && !hip_stream) e = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      set_error("lts_batch_load: %s", hipGetErrorString(e));
+      st = BISIM_E_DEVICE;
+      break;
+    }
+    b->lds_max -= (int)sizeof(Shared) + 64;
+    b->stream = hip_stream ? (hipStream_t)hip_stream : b->own_stream;
+    hipStream_t s = b->stream;
+    if (hipEventRecord(b->ev0, s) != hipSuccess) { st = BISIM_E_DEVICE; break; }
+    std::vector<uint32_t> no(count + 1), mo(count + 1), bo(count + 1);
+    bo[0] = 0;
+    for (int32_t k = 0; k <= count; ++k) {
+      no[k] = (uint32_t)n_off[k];
+      mo[k] = (uint32_t)m_off[k];
+      if (k < count) bo[k + 1] = bo[k] + (uint32_t)((n_off[k + 1] - n_off[k] + 63) / 64);
+    }
+    std::vector<int32_t> order(count);
+    for (int32_t k = 0; k < count; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      return n_off[x + 1] - n_off[x] > n_off[y + 1] - n_off[y];
+    });
+    if ((st = dmalloc(&b->n_off_d, count + 1)) || (st = dmalloc(&b->bw_off_d, count + 1)) ||
+        (st = dmalloc(&b->order_d, count)) || (st = dmalloc(&m_off_d, count + 1)) ||
+        (st = dmalloc(&Kd, count)) || (st = dmalloc(&err, 1)) ||
+        (st = dmalloc(&gsrc, (size_t)M)) || (st = dmalloc(&gdst, (size_t)M)) ||
+        (st = dmalloc(&ginit, (size_t)N)))
+      break;
+    e = hipMemcpyAsync(b->n_off_d, no.data(), 4 * (count + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(m_off_d, mo.data(), 4 * (count + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->bw_off_d, bo.data(), 4 * (count + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->order_d, order.data(), 4 * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(Kd, num_actions, 4 * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(err, 0, 4, s);
+    if (e != hipSuccess) {
+      set_error("lts_batch_load: %s", hipGetErrorString(e));
+      st = BISIM_E_DEVICE;
+      break;
+    }
+    int64_t g = (std::max(N, M) + kT - 1) / kT;
+    g = std::min<int64_t>(std::max<int64_t>(g, 1), (int64_t)b->num_cu * 16);
+    hipLaunchKernelGGL(k_globalize, dim3((unsigned)g), dim3(kT), 0, s, count, b->n_off_d, m_off_d,
+                       Kd, src, label, dst, init_partition, (uint64_t)M, (uint64_t)N, gsrc, gdst,
+                       ginit, err);
+    uint32_t err_h = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&err_h, err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      set_error("lts_batch_load: %s", hipGetErrorString(e));
+      st = BISIM_E_DEVICE;
+      break;
+    }
+    if (err_h) {
+      set_error("lts_batch_load: an instance-local id, label or init value is out of range");
+      st = BISIM_E_RANGE;
+      break;
+    }
+    st = lts_create_union((int32_t)N, M, Kmax, gsrc, label, gdst, ginit, s, &b->u);
+    if (st != BISIM_OK) break;
+    if (!b->u->uniform) {
+      set_error("lts_batch_load: a state has more than 64 distinct outgoing actions");
+      st = BISIM_E_UNSUPPORTED;
+      break;
+    }
+    // 32-bit mark words suffice when no state has more than 32 actions
+    b->mask64 = Kmax > 32;
+    const size_t BW = bo[count];
+    if ((st = dmalloc(&b->blk, (size_t)N)) || (st = dmalloc(&b->mw, (size_t)N)) ||
+        (st = dmalloc(&b->nlb, (size_t)N)) || (st = dmalloc(&b->ub, BW)) ||
+        (st = dmalloc(&b->tb, BW)) || (st = dmalloc(&b->lt, BW)) ||
+        (st = dmalloc(&b->tl, (size_t)N)) || (st = dmalloc(&b->sl, (size_t)N)) ||
+        (st = dmalloc(&b->iters_d, count)) || (st = dmalloc(&b->ctl_d, 2)))
+      break;
+    float ms = 0;
+    if (hipEventRecord(b->ev1, s) != hipSuccess || hipEventSynchronize(b->ev1) != hipSuccess ||
+        hipEventElapsedTime(&ms, b->ev0, b->ev1) != hipSuccess) {
+      st = BISIM_E_DEVICE;
+      break;
+    }
+    b->t_pre_ms = ms;
+  } while (0);
+  if (gsrc) (void)hipFree(gsrc);
+  if (gdst) (void)hipFree(gdst);
+  if (ginit) (void)hipFree(ginit);
+  if (Kd) (void)hipFree(Kd);
+  if (m_off_d) (void)hipFree(m_off_d);
+  if (err) (void)hipFree(err);
+  if (st != BISIM_OK) {
+    free_batch(b);
+    return st;
+  }
+  *out = b;
+  return BISIM_OK;
+}
+
+bisim_status coarsest_partition_batch(bisim_batch* b, int32_t* block_id, int64_t* iterations,
+                                      bisim_batch_stats* st) {
+  if (!b || (!block_id && b->N > 0)) {
+    set_error("coarsest_partition_batch: NULL handle or output");
+    return BISIM_E_INVALID;
+  }
+  // configuration: explicit options, else the cached or freshly tuned choice
+  if (!b->tuned || b->opt_retune) {
+    int wg = 0, grid = 0, lds = 0;
+    const bool fixed = b->opt_wg || b->opt_grid || b->opt_lds;
+    if (fixed) {
+      wg = b->opt_wg ? b->opt_wg : 1024;
+      lds = b->opt_lds ? std::min(b->opt_lds, b->lds_max) : b->lds_max;
+      grid = b->opt_grid ? b->opt_grid : max_resident(b, wg, lds);
+      b->wg = wg;
+      b->grid = grid;
+      b->lds_bytes = lds;
+    } else if (!b->opt_retune && tune_lookup(tune_key(b), &wg, &grid, &lds) && wg && grid &&
+               lds <= b->lds_max && max_resident(b, wg, lds) >= grid) {
+      b->wg = wg;
+      b->grid = grid;
+      b->lds_bytes = lds;
+    } else {
+      BISIM_TRY(autotune(b, block_id));
+    }
+    if (b->grid < 1) {
+      set_error("coarsest_partition_batch: configuration not resident");
+      return BISIM_E_DEVICE;
+    }
+    b->tuned = true;
+    b->opt_retune = 0;
+  }
+  // graph of (queue reset, batched kernel); the configuration and the output
+  // pointer are baked into it, so it is re-captured when either changes
+  const bool need_graph = !b->gexec || b->g_wg != b->wg || b->g_grid != b->grid ||
+                          b->g_lds != b->lds_bytes || b->g_out != block_id;
+  if (need_graph) {
+    if (b->gexec) {
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    BISIM_TRY_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    bisim_status ls = launch_once(b, block_id, b->wg, b->grid, b->lds_bytes);
+    hipError_t ec = hipStreamEndCapture(b->stream, &graph);
+    if (ls != BISIM_OK) return ls;
+    BISIM_TRY_HIP(ec);
+    hipError_t ei = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    BISIM_TRY_HIP(ei);
+    b->g_wg = b->wg;
+    b->g_grid = b->grid;
+    b->g_lds = b->lds_bytes;
+    b->g_out = block_id;
+  }
+  BISIM_TRY_HIP(hipEventRecord(b->ev0, b->stream));
+  BISIM_TRY_HIP(hipGraphLaunch(b->gexec, b->stream));
+  BISIM_TRY_HIP(hipEventRecord(b->ev1, b->stream));
+  std::vector<uint32_t> its(b->count);
+  uint32_t ctl_h[2] = {0, 0};
+  BISIM_TRY_HIP(hipMemcpyAsync(its.data(), b->iters_d, 4 * b->count, hipMemcpyDeviceToHost, b->stream));
+  BISIM_TRY_HIP(hipMemcpyAsync(ctl_h, b->ctl_d, 8, hipMemcpyDeviceToHost, b->stream));
+  BISIM_TRY_HIP(hipStreamSynchronize(b->stream));
+  float ms = 0;
+  BISIM_TRY_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  b->t_alg_ms = ms;
+  if (ctl_h[1]) {
+    set_error("coarsest_partition_batch: an instance exceeded its iteration cap");
+    return BISIM_E_ITERCAP;
+  }
+  int64_t mx = 0, sum = 0, nl = 0, ng = 0;
+  for (int32_t k = 0; k < b->count; ++k) {
+    mx = std::max<int64_t>(mx, its[k]);
+    sum += its[k];
+    if (iterations) iterations[k] = its[k];
+    const uint32_t n = (uint32_t)(b->n_off[k + 1] - b->n_off[k]);
+    const uint64_t need = b->mask64 ? lds_need<uint64_t>(n) : lds_need<uint32_t>(n);
+    (need <= (uint64_t)b->lds_bytes ? nl : ng) += 1;
+  }
+  if (st) {
+    st->max_iterations = mx;
+    st->sum_iterations = sum;
+    st->lds_instances = nl;
+    st->global_instances = ng;
+    st->workgroup_size = b->wg;
+    st->grid = b->grid;
+    st->t_pre_ms = b->t_pre_ms;
+    st->t_alg_ms = b->t_alg_ms;
+  }
+  return BISIM_OK;
+}
+
+void lts_batch_free(bisim_batch* b) { free_batch(b); }
+
+bisim_status bisim_batch_set_option(bisim_batch* b, int32_t option, int64_t value) {
+  if (!b) {
+    set_error("bisim_batch_set_option: NULL handle");
+    return BISIM_E_INVALID;
+  }
+  switch (option) {
+    case BISIM_BOPT_WG_SIZE:
+      if (value != 0 && value != 256 && value != 512 && value != 1024) break;
+      b->opt_wg = (int)value;
+      b->tuned = false;
+      return BISIM_OK;
+    case BISIM_BOPT_GRID:
+      if (value < 0 || value > (1 << 20)) break;
+      b->opt_grid = (int)value;
+      b->tuned = false;
+      return BISIM_OK;
+    case BISIM_BOPT_LDS_LIMIT:
+      if (value < 0 || value > (1 << 22)) break;
+      b->opt_lds = (int)value;
+      b->tuned = false;
+      return BISIM_OK;
+    case BISIM_BOPT_TUNE:
+      if (value != 0 && value != 1) break;
+      b->opt_retune = (int)value;
+      return BISIM_OK;
+    default:
+      break;
+  }
+  set_error("bisim_batch_set_option: bad option %d or value %lld", option, (long long)value);
+  return BISIM_E_INVALID;
+}
+
+}  // extern "C"

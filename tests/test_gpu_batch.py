@@ -1,0 +1,119 @@
+"""GPU parity for the batched engine: every instance of a batch equals the
+oracle (partition bit-exact, #It equal to the lock-step oracle's), in both
+storage tiers (LDS-resident and global), for several workgroup sizes."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_11788_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2105_11788_amd import bisim
+    bisim.load_library()
+    assert bisim.device_count() > 0, "GPU tests need a GPU"
+    return bisim
+
+
+def mixed_instances():
+    out = [gen.figure1(), gen.figure2(), gen.fan_out(40), gen.chain_tail(300),
+           gen.LTS(0, 1, [], [], []),                                   # empty
+           gen.LTS(7, 2, [], [], [], np.array([0, 0, 2, 2, 0, 5, 5])),   # no transitions
+           gen.kripke_uniform(1000, 5000, seed=3),
+           gen.planted_quotient(q=120, deg_mean=4.0, K=8, seed=4)]
+    rng = np.random.default_rng(11)
+    for k in range(40):
+        n = int(rng.integers(1, 400))
+        out.append(gen.random_lts(n, int(rng.integers(0, 5 * n)), int(rng.integers(1, 30)),
+                                  seed=900 + k, init_blocks=int(rng.integers(0, 4))))
+    return out
+
+
+def check(B, insts, blocks, its, trace_every=1):
+    for k, L in enumerate(insts):
+        ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        assert (blocks[k] == ks).all(), (k, L.name)
+        if k % trace_every == 0:
+            r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init)
+            assert its[k] == r["iters"], (k, L.name, its[k], r["iters"])
+
+
+@pytest.mark.parametrize("wg,lds", [(1024, 0), (256, 0), (512, 1024), (1024, 1 << 14)])
+def test_mixed_batch_tiers(B, wg, lds):
+    insts = mixed_instances()
+    with B.Batch(insts) as b:
+        b.set_option(B.BOPT_WG_SIZE, wg)
+        if lds:
+            b.set_option(B.BOPT_LDS_LIMIT, lds)
+        out, its, st = b.run()
+        blocks = b.split(out.numpy())
+    check(B, insts, blocks, its)
+    if lds == 1024:
+        assert st["lds_instances"] <= 2  # only empty / one-state instances fit 1 KiB
+    assert st["max_iterations"] == its.max() and st["sum_iterations"] == its.sum()
+
+
+def test_batch_autotuned_and_repeatable(B, tmp_path, monkeypatch):
+    monkeypatch.setenv("BISIM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    insts = mixed_instances()
+    with B.Batch(insts) as b:
+        out1, its1, st1 = b.run()
+        r1 = out1.numpy()
+        out2, its2, st2 = b.run()
+        assert (out2.numpy() == r1).all() and (its1 == its2).all()
+        blocks = b.split(r1)
+    check(B, insts, blocks, its1)
+    assert (tmp_path / "tune.txt").exists()
+    # a second handle reads the cached choice
+    with B.Batch(insts) as b2:
+        out3, its3, st3 = b2.run()
+        assert (out3.numpy() == r1).all()
+        assert (st3["workgroup_size"], st3["grid"]) == (st1["workgroup_size"], st1["grid"])
+
+
+def test_batch_matches_single_instance_runs(B):
+    insts = [gen.planted_quotient(q=300, deg_mean=6.0, K=12, seed=s) for s in range(4)]
+    with B.Batch(insts) as b:
+        out, its, _ = b.run()
+        blocks = b.split(out.numpy())
+    for k, L in enumerate(insts):
+        t = lambda a: B.DeviceArray.from_numpy(a, np.int32)
+        with B.LTS(t(L.src), t(L.lab), t(L.dst), L.n, L.K) as h:
+            blk, st = h.run()
+        assert (blk.numpy() == blocks[k]).all() and st.iterations == its[k]
+
+
+def test_batch_many_small(B):
+    insts = gen.batch(count=1024, n_lo=10, n_hi=2000, seed=5)
+    with B.Batch(insts) as b:
+        out, its, st = b.run()
+        blocks = b.split(out.numpy())
+    check(B, insts, blocks, its, trace_every=16)
+
+
+def test_batch_errors(B):
+    bad = gen.LTS(3, 2, [0], [1], [3])  # target outside the instance
+    with pytest.raises(B.BisimError) as e:
+        B.Batch([gen.figure2(), bad])
+    assert e.value.status == B.E_RANGE
+    lab_bad = gen.LTS(3, 1, [0], [1], [2])  # label >= K of its instance
+    with pytest.raises(B.BisimError) as e:
+        B.Batch([lab_bad])
+    assert e.value.status == B.E_RANGE
+    wide = gen.LTS(2, 100, np.zeros(70, np.int32), np.arange(70), np.ones(70, np.int32))
+    with pytest.raises(B.BisimError) as e:
+        B.Batch([wide])
+    assert e.value.status == B.E_UNSUPPORTED
+
+
+def test_batch_4096_up_to_10k_full(B):
+    """4096 instances, log-uniform 100..10k states, Poisson(6), K ~ U{1..32},
+    half planted: every instance's partition vs the oracle, #It on a sample."""
+    insts = gen.batch(count=4096, n_lo=100, n_hi=10_000, seed=1)
+    with B.Batch(insts) as b:
+        out, its, st = b.run()
+        blocks = b.split(out.numpy())
+    check(B, insts, blocks, its, trace_every=64)
