@@ -233,6 +233,93 @@ void lts_batch_free(bisim_batch* b);
 #define BISIM_BOPT_TUNE 4
 bisim_status bisim_batch_set_option(bisim_batch* b, int32_t option, int64_t value);
 
+/* ------------------------------------------------------------------------ */
+/* Learned splitter priority                                                 */
+/* ------------------------------------------------------------------------ */
+/*
+ * Algorithm 3 is correct for any choice of the unstable splitter C (the
+ * concurrent write of section 3.2 may be won by any block; Theorem 1 and the
+ * labelled argument of section 4.2 do not depend on it), so the splitter
+ * order can be chosen to cut the iteration count without changing the
+ * result.  The learned policy picks C = the unstable block with the highest
+ * score (ties: the smallest label), where the score is a small network
+ *     y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3,   hidden width 64,
+ * evaluated on per-block features x (18 values, each log1p-scaled):
+ *     x[0]      block size
+ *     x[1..8]   outgoing transitions of the members, by label mod 8
+ *     x[9..16]  incoming transitions of the members, by label mod 8
+ *     x[17]     iterations since the block was created or last split.
+ * Parameters are fp32 masters with bf16 copies used by the forward pass
+ * (inputs also rounded to bf16, fp32 accumulation).  Scores are refreshed for
+ * every block created or split in an iteration, and for all unstable blocks
+ * every R iterations.
+ */
+typedef struct bisim_mlp bisim_mlp;
+
+/* parameter count for `in_features` inputs (1..32), or -1 */
+int64_t mlp_num_params(int32_t in_features);
+
+/*
+ * mlp_create — a network on the current device.
+ *   init_fp32   host, mlp_num_params(in_features) values in the order
+ *               W1 (row-major [64][F]), b1 [64], W2 ([64][64]), b2 [64],
+ *               w3 [64], b3; or NULL for He-normal weights (seeded by `seed`)
+ *               and zero biases.
+ * Errors: BISIM_E_INVALID, BISIM_E_NOMEM, BISIM_E_DEVICE.
+ */
+bisim_status mlp_create(int32_t in_features, const float* init_fp32, uint64_t seed,
+                        bisim_mlp** out);
+void mlp_free(bisim_mlp* w);
+/* copy the fp32 master parameters to host memory (mlp_num_params floats) */
+bisim_status mlp_get_params(const bisim_mlp* w, float* host_fp32);
+
+/*
+ * mlp_forward — y[r] = network(x[r]) for r < rows.
+ *   x device fp32 [rows][F] (row-major); y device fp32 [rows].
+ * Synchronises hip_stream.  Errors: BISIM_E_INVALID, BISIM_E_DEVICE.
+ */
+bisim_status mlp_forward(const bisim_mlp* w, const float* x, int64_t rows, float* y,
+                         void* hip_stream);
+
+/*
+ * mlp_train_step — one full-batch step on rows (x, target):
+ * loss = mean over rows of (y - target)^2; gradients w.r.t. the bf16
+ * parameter copies; then an Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * learning rate lr; lr = 0 computes gradients only) on the fp32 masters and
+ * a refresh of the bf16 copies.
+ *   x device fp32 [rows][F]; target device fp32 [rows];
+ *   loss_out host, nullable: the loss before the update;
+ *   grad_out device, nullable: the gradient (mlp_num_params floats).
+ * Synchronises hip_stream.  Errors: BISIM_E_INVALID, BISIM_E_DEVICE.
+ */
+bisim_status mlp_train_step(bisim_mlp* w, const float* x, const float* target, int64_t rows,
+                            float lr, float* loss_out, float* grad_out, void* hip_stream);
+
+/*
+ * bisim_set_splitter_policy — 0: the smallest unstable label (default);
+ * 1: the learned score (`w` must have 18 inputs and outlive the handle's
+ * runs).  rescore_every: full re-scoring period R (>= 1).
+ * Errors: BISIM_E_INVALID.
+ */
+bisim_status bisim_set_splitter_policy(bisim_lts* h, int32_t policy, const bisim_mlp* w,
+                                       int32_t rescore_every);
+
+/*
+ * bisim_collect_training — run the plain policy to the fixpoint and, before
+ * every `sample_every`-th iteration, evaluate up to `max_cands` unstable
+ * blocks (evenly spaced in label order): their 18 features (as above) and
+ * the counterfactual target log(1 + number of blocks that would split if
+ * that block were the splitter now).
+ *   feat device fp32 [cap][18]; target device fp32 [cap];
+ *   meta device int32 [cap][2], nullable: (iteration, block label) per row;
+ *   rows host: rows written (<= cap).
+ * Supports states with at most 64 distinct outgoing actions and
+ * n <= 16384.  Errors: BISIM_E_INVALID, BISIM_E_UNSUPPORTED, BISIM_E_DEVICE.
+ */
+bisim_status bisim_collect_training(bisim_lts* h, int64_t sample_every, int32_t max_cands,
+                                    float* feat, float* target, int32_t* meta, int64_t cap,
+                                    int64_t* rows);
+
 #ifdef __cplusplus
 }
 #endif

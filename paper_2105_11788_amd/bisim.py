@@ -43,7 +43,9 @@ ENGINE_PHASES = 2
 EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
            "bisim_set_option", "bisim_set_trace", "bisim_get_preprocessed",
            "lts_batch_load", "coarsest_partition_batch", "lts_batch_free",
-           "bisim_batch_set_option"]
+           "bisim_batch_set_option", "mlp_num_params", "mlp_create", "mlp_free",
+           "mlp_get_params", "mlp_forward", "mlp_train_step", "bisim_set_splitter_policy",
+           "bisim_collect_training"]
 
 
 class BisimError(RuntimeError):
@@ -379,6 +381,130 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+POLICY_PLAIN = 0
+POLICY_LEARNED = 1
+POLICY_FEATURES = 18
+
+
+def _declare_learned(L):
+    if getattr(L, "_learned_declared", False):
+        return
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.mlp_num_params.argtypes = [i32]
+    L.mlp_num_params.restype = i64
+    L.mlp_create.argtypes = [i32, P, ctypes.c_uint64, ctypes.POINTER(P)]
+    L.mlp_create.restype = i32
+    L.mlp_free.argtypes = [P]
+    L.mlp_free.restype = None
+    L.mlp_get_params.argtypes = [P, P]
+    L.mlp_get_params.restype = i32
+    L.mlp_forward.argtypes = [P, P, i64, P, P]
+    L.mlp_forward.restype = i32
+    L.mlp_train_step.argtypes = [P, P, P, i64, ctypes.c_float, ctypes.POINTER(ctypes.c_float), P, P]
+    L.mlp_train_step.restype = i32
+    L.bisim_set_splitter_policy.argtypes = [P, i32, P, i32]
+    L.bisim_set_splitter_policy.restype = i32
+    L.bisim_collect_training.argtypes = [P, i64, i32, P, P, P, i64, ctypes.POINTER(i64)]
+    L.bisim_collect_training.restype = i32
+    L._learned_declared = True
+
+
+class _View:
+    """A device pointer range inside another DeviceArray (no ownership)."""
+
+    def __init__(self, base: "DeviceArray", start: int, count: int):
+        self.ptr = base.ptr + start * base.dtype.itemsize
+        self.count = count
+        self.dtype = base.dtype
+        self._base = base
+
+
+class MLP:
+    """The splitter-scoring network (mlp_create / mlp_forward / mlp_train_step)."""
+
+    def __init__(self, in_features: int = POLICY_FEATURES, init: Optional[np.ndarray] = None,
+                 seed: int = 0):
+        L = load_library()
+        _declare_learned(L)
+        self._L = L
+        self.F = int(in_features)
+        self.P = int(L.mlp_num_params(self.F))
+        if self.P < 0:
+            raise ValueError("in_features must be 1..32")
+        h = ctypes.c_void_p()
+        pinit = None
+        if init is not None:
+            init = np.ascontiguousarray(init, np.float32)
+            if init.size != self.P:
+                raise ValueError(f"init must have {self.P} values")
+            pinit = init.ctypes.data_as(ctypes.c_void_p)
+        _check(L.mlp_create(self.F, pinit, int(seed), ctypes.byref(h)))
+        self._h = h
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.P, np.float32)
+        _check(self._L.mlp_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def forward(self, x) -> np.ndarray:
+        xd = x if not isinstance(x, np.ndarray) else DeviceArray.from_numpy(x, np.float32)
+        rows = xd.count // self.F
+        y = DeviceArray(rows, np.float32)
+        _check(self._L.mlp_forward(self._h, ctypes.c_void_p(xd.ptr), rows, ctypes.c_void_p(y.ptr),
+                                   None))
+        return y.numpy()
+
+    def train_step(self, x, t, lr: float, want_grad: bool = False):
+        """One Adam step on (x, t); returns the loss before the step (and the
+        gradient when want_grad)."""
+        xd = x if not isinstance(x, np.ndarray) else DeviceArray.from_numpy(x, np.float32)
+        td = t if not isinstance(t, np.ndarray) else DeviceArray.from_numpy(t, np.float32)
+        rows = td.count
+        g = DeviceArray(self.P, np.float32) if want_grad else None
+        loss = ctypes.c_float(0)
+        _check(self._L.mlp_train_step(self._h, ctypes.c_void_p(xd.ptr), ctypes.c_void_p(td.ptr),
+                                      rows, float(lr), ctypes.byref(loss),
+                                      ctypes.c_void_p(g.ptr) if g else None, None))
+        return (loss.value, g.numpy()) if want_grad else loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_splitter_policy(lts: "LTS", policy: int, mlp: Optional[MLP] = None,
+                        rescore_every: int = 64):
+    L = load_library()
+    _declare_learned(L)
+    _check(L.bisim_set_splitter_policy(lts._h, int(policy), mlp._h if mlp is not None else None,
+                                       int(rescore_every)))
+    lts._policy_mlp = mlp  # keep the network alive while the handle uses it
+
+
+def collect_training(lts: "LTS", sample_every: int = 1, max_cands: int = 64, cap: int = 100_000):
+    """Plain run with sampled (features, counterfactual target) rows.
+    Returns (feat [rows, 18], target [rows], meta [rows, 2] = (iteration, block))."""
+    L = load_library()
+    _declare_learned(L)
+    f = DeviceArray(cap * POLICY_FEATURES, np.float32)
+    t = DeviceArray(cap, np.float32)
+    m = DeviceArray(cap * 2, np.int32)
+    rows = ctypes.c_int64(0)
+    _check(L.bisim_collect_training(lts._h, int(sample_every), int(max_cands), ctypes.c_void_p(f.ptr),
+                                    ctypes.c_void_p(t.ptr), ctypes.c_void_p(m.ptr), cap,
+                                    ctypes.byref(rows)))
+    r = rows.value
+    return (f.numpy()[:r * POLICY_FEATURES].reshape(r, POLICY_FEATURES), t.numpy()[:r],
+            m.numpy()[:2 * r].reshape(r, 2))
 
 
 def coarsest_partition(src, lab, dst, n: int, num_actions: int, init=None,

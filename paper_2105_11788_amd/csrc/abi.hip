@@ -21,7 +21,8 @@ static void free_handle(bisim_lts* h) {
   hipStream_t s = h->stream;
   void* ptrs[] = {h->pre_block, h->nr_marks, h->in_ptr, h->in_src, h->in_ord, h->woff,
                   h->block,     h->mw,       h->tb,     h->lt,     h->ub,     h->nlw,
-                  h->tlist,     h->slist,    h->ctl};
+                  h->tlist,     h->slist,    h->ctl,    h->sfeat,  h->acc,    h->born,
+                  h->score,     h->chg};
   for (void* p : ptrs)
     if (p) (void)hipFreeAsync(p, s);
   (void)hipStreamSynchronize(s);

@@ -46,6 +46,8 @@ struct Ctl {
   Line cntS[2];   // v[0]: split-state list length
   Line ltany[2];  // v[0]: some block leader was touched
   Line work[2];   // traced runs only: v[0] members of C, v[1] in-transitions of C
+  Line key[2];    // learned policy: v[0..1] = 64-bit (score, ~label) key, max-reduced
+  Line cntC[2];   // learned policy: changed (old, new) block pairs this iteration
   Line state;     // v[0] iterations done, v[1] done flag, v[2] error, v[3] current splitter
   Line bar;       // v[0] arrivals, v[1] generation, v[2] abort
 };
@@ -134,6 +136,16 @@ struct bisim_lts {
   int64_t* trace_work = nullptr;
   int64_t trace_cap = 0;
 
+  // block features and the learned splitter policy
+  uint32_t* sfeat = nullptr;  // [n][16] out/in transitions of each state by label mod 8
+  uint32_t* acc = nullptr;    // [n][17] per block label: size, out[8], in[8]
+  uint32_t* born = nullptr;   // [n] iteration the block was created / last split
+  float* score = nullptr;     // [n]
+  int32_t* chg = nullptr;     // [2n] (old, new) label pairs of this iteration's splits
+  int policy = 0;
+  const uint16_t* policy_w = nullptr;  // bf16 network parameters (18 inputs)
+  int rescore_every = 64;
+
   double t_pre_ms = 0.0;
   double t_alg_ms = 0.0;
   int64_t last_iters = 0;
@@ -151,4 +163,11 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
 // refine.hip
 bisim_status refine_run(bisim_lts* h, int32_t* block_id);
 bisim_status refine_alloc(bisim_lts* h);
+}  // namespace bisim
+
+struct bisim_mlp;
+namespace bisim {
+// mlp.hip
+const uint16_t* mlp_weights_bf16(const bisim_mlp* w);
+int mlp_features(const bisim_mlp* w);
 }  // namespace bisim

@@ -1,0 +1,465 @@
+// Device-side phases of one refinement iteration (see refine.hip for the
+// algorithm), shared by the refinement engines and the training-data
+// collector.  Everything here has internal linkage: each translation unit
+// that includes it gets its own copy of the kernels.
+#pragma once
+
+#include "internal.h"
+#include "mlp_dev.h"
+
+namespace bisim {
+namespace {
+
+struct Args {
+  int32_t n;
+  int uniform;
+  const uint32_t* __restrict__ in_ptr;
+  const int32_t* __restrict__ in_src;
+  const int32_t* __restrict__ in_ord;
+  const uint32_t* __restrict__ woff;
+  int32_t* block;
+  uint64_t* mw;
+  uint64_t* tb;
+  uint64_t* lt;
+  uint64_t* ub;
+  uint64_t* nlw;
+  int32_t* tlist;
+  int32_t* slist;
+  Ctl* ctl;
+  uint32_t iter_cap;
+  int32_t* trace_C;
+  int64_t* trace_nsplit;
+  int64_t* trace_work;
+  uint32_t trace_cap;
+  // block features and the learned policy
+  const uint32_t* sfeat;  // [n][16]
+  uint32_t* acc;          // [n][17]
+  uint32_t* born;         // [n]
+  float* score;           // [n]
+  int32_t* chg;           // [2n]
+  const uint16_t* wbf;    // bf16 network parameters
+  uint32_t rescore;       // full re-scoring period
+};
+
+struct Part {
+  uint32_t gtid, gthreads, gwave, gwaves;
+};
+
+__device__ __forceinline__ Part part() {
+  const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t gthreads = gridDim.x * blockDim.x;
+  return {gtid, gthreads, gtid / kWave, gthreads / kWave};
+}
+
+__device__ __forceinline__ uint64_t* key_ptr(Ctl* c, uint32_t par) {
+  return reinterpret_cast<uint64_t*>(&c->key[par].v[0]);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = (uint64_t)__shfl_xor((unsigned long long)v, d, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Block features (log1p-scaled): size, outgoing and incoming transitions of
+// the members by label mod 8, iterations since the block was created or last
+// split (kcur = number of iterations completed).
+__device__ __forceinline__ float block_feature(const Args& a, uint32_t b, uint32_t f,
+                                               uint32_t kcur) {
+  if (f < 17) return log1pf((float)a.acc[(size_t)b * 17 + f]);
+  if (f == 17) return log1pf((float)(kcur - a.born[b]));
+  return 0.f;
+}
+
+// one wave scores block b and folds its key into *key
+__device__ __forceinline__ void score_block(const Args& a, const MlpLds& M, uint32_t b,
+                                            uint32_t kcur, uint64_t* key) {
+  const float x = block_feature(a, b, lane(), kcur);
+  float z1, z2;
+  const float y = mlp_forward_lanes(M, kPolicyF, x, &z1, &z2);
+  if (lane() == 0) {
+    a.score[b] = y;
+    atomicMax((unsigned long long*)key, (unsigned long long)score_key(y, b));
+  }
+}
+
+// Start of iteration k: returns C, or kNone when the loop ends (no unstable
+// block, which is the final counted pass, or the iteration cap).
+template <bool L>
+__device__ uint32_t head(const Args& a, uint32_t k, const Part& p) {
+  uint32_t C;
+  if (L) {
+    const uint64_t key = *key_ptr(a.ctl, k & 1);
+    C = key ? key_label(key) : kNone;
+  } else {
+    C = a.ctl->cand[k & 1].v[0];
+  }
+  const bool over = (k + 1 > a.iter_cap);
+  if (p.gtid == 0) {
+    Ctl* c = a.ctl;
+    if (C == kNone || over) {
+      c->state.v[0] = k + 1;
+      c->state.v[1] = 1;
+      if (over && C != kNone) c->state.v[2] = 1;
+      if (a.trace_C && k < a.trace_cap) a.trace_C[k] = -1;
+      if (a.trace_nsplit && k < a.trace_cap) a.trace_nsplit[k] = 0;
+      if (a.trace_work && k < a.trace_cap)
+        for (int q = 0; q < 4; ++q) a.trace_work[4 * (uint64_t)k + q] = 0;
+    } else {
+      const uint32_t nx = (k & 1) ^ 1;
+      c->state.v[3] = C;
+      c->cntT[nx].v[0] = 0;
+      c->cntS[nx].v[0] = 0;
+      c->ltany[nx].v[0] = 0;
+      c->work[nx].v[0] = 0;
+      c->work[nx].v[1] = 0;
+      c->cntC[nx].v[0] = 0;
+      if (a.trace_C && k < a.trace_cap) a.trace_C[k] = (int32_t)C;
+    }
+  }
+  return (C == kNone || over) ? kNone : C;
+}
+
+// A: clear C, reduce the other unstable labels into next iteration's candidate
+template <bool L>
+__device__ void phase_a_select(const Args& a, uint32_t par, uint32_t C, const Part& p) {
+  const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
+  if (!L) {
+    uint32_t best = kNone;
+    for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
+      uint64_t bits = a.ub[w];
+      if (w == (C >> 6)) {
+        bits &= ~(1ull << (C & 63));
+        a.ub[w] = bits;
+      }
+      if (bits) best = min(best, (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1));
+    }
+    best = wave_min_u32(best);
+    if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
+  } else {
+    uint64_t best = 0;
+    for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
+      uint64_t bits = a.ub[w];
+      if (w == (C >> 6)) {
+        bits &= ~(1ull << (C & 63));
+        a.ub[w] = bits;
+      }
+      while (bits) {
+        const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
+        bits &= bits - 1;
+        const uint64_t kk = score_key(a.score[b], b);
+        best = kk > best ? kk : best;
+      }
+    }
+    best = wave_max_u64(best);
+    if (lane() == 0 && best) atomicMax((unsigned long long*)key_ptr(a.ctl, par ^ 1), (unsigned long long)best);
+  }
+}
+
+__device__ __forceinline__ void mark_slot(const Args& a, uint32_t par, int32_t s, int32_t o,
+                                          bool valid) {
+  bool first = false;
+  if (valid) {
+    const uint64_t bit = 1ull << (o & 63);
+    const uint64_t wi = a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6);
+    const uint64_t tbit = 1ull << (s & 63);
+    if (a.uniform) {
+      const uint64_t old = atomicOr((unsigned long long*)&a.mw[wi], (unsigned long long)bit);
+      first = (old == 0);
+      if (first) atomicOr((unsigned long long*)&a.tb[s >> 6], (unsigned long long)tbit);
+    } else {
+      atomicOr((unsigned long long*)&a.mw[wi], (unsigned long long)bit);
+      first = !(atomicOr((unsigned long long*)&a.tb[s >> 6], (unsigned long long)tbit) & tbit);
+    }
+    if (first && a.block[s] == s) {
+      atomicOr((unsigned long long*)&a.lt[s >> 6], (unsigned long long)tbit);
+      a.ctl->ltany[par].v[0] = 1;
+    }
+  }
+  wave_push(a.tlist, &a.ctl->cntT[par].v[0], s, first);
+}
+
+// A: mark.  Waves scan block[] (coalesced); the in-transitions of the hits
+// are spread over the wave's 64 lanes by a prefix sum of in-degrees.
+__device__ void phase_a_mark(const Args& a, uint32_t par, uint32_t C, const Part& p) {
+  const uint32_t n = (uint32_t)a.n;
+  for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
+    const uint32_t t = base + lane();
+    const bool hit = t < n && (uint32_t)a.block[t] == C;
+    const uint64_t hits = __ballot(hit);
+    if (hits == 0) continue;
+    uint32_t beg = 0, deg = 0;
+    if (hit) {
+      beg = a.in_ptr[t];
+      deg = a.in_ptr[t + 1] - beg;
+    }
+    const uint32_t incl = wave_incl_scan_u32(deg);
+    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+    if (a.trace_work && lane() == 0) {
+      atomicAdd(&a.ctl->work[par].v[0], (uint32_t)__popcll(hits));
+      atomicAdd(&a.ctl->work[par].v[1], total);
+    }
+    for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
+      const uint32_t e = e0 + lane();
+      const bool valid = e < total;
+      const uint32_t ee = valid ? e : total - 1;
+      uint32_t j = 0;  // owner lane: the first with incl > ee
+#pragma unroll
+      for (uint32_t step = 32; step >= 1; step >>= 1) {
+        const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
+        if (probe <= ee) j += step;
+      }
+      const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
+      const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
+      const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
+      const uint32_t edge = jb + (ee - (ji - jd));
+      int32_t s = 0, o = 0;
+      if (valid) {
+        s = a.in_src[edge];
+        o = a.in_ord[edge];
+      }
+      mark_slot(a, par, s, o, valid);
+    }
+  }
+}
+
+__device__ __forceinline__ void bid(const Args& a, int32_t b, int32_t s, uint64_t epoch) {
+  const uint64_t val = epoch | (uint64_t)(kNone - (uint32_t)s);
+  const uint64_t cur = __hip_atomic_load(&a.nlw[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (cur < val) atomicMax((unsigned long long*)&a.nlw[b], (unsigned long long)val);
+}
+
+// B: compare with the leader and elect
+__device__ void phase_b(const Args& a, uint32_t par, uint32_t k, const Part& p) {
+  const uint64_t epoch = (uint64_t)(k + 1) << 32;
+  const uint32_t nT = a.ctl->cntT[par].v[0];
+  uint32_t* cntS = &a.ctl->cntS[par].v[0];
+  for (uint32_t i0 = p.gwave * kWave; i0 < nT; i0 += p.gwaves * kWave) {
+    const uint32_t i = i0 + lane();
+    bool sp = false;
+    int32_t s = 0, b = 0;
+    if (i < nT) {
+      s = a.tlist[i];
+      b = a.block[s];
+      if (s != b) {
+        if (a.uniform) {
+          sp = a.mw[s] != a.mw[b];
+        } else {
+          const uint32_t w0 = a.woff[s], w1 = a.woff[s + 1], wb = a.woff[b];
+          for (uint32_t q = 0; q < w1 - w0; ++q)
+            if (a.mw[w0 + q] != a.mw[wb + q]) {
+              sp = true;
+              break;
+            }
+        }
+      }
+    }
+    if (sp) bid(a, b, s, epoch);
+    wave_push(a.slist, cntS, s, sp);
+  }
+  if (a.ctl->ltany[par].v[0]) {
+    const uint32_t n = (uint32_t)a.n;
+    for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
+      const uint32_t s = base + lane();
+      bool sp = false;
+      int32_t b = 0;
+      if (s < n) {
+        b = a.block[s];
+        sp = test_bit(a.lt, (uint32_t)b) && !test_bit(a.tb, s);
+      }
+      if (sp) bid(a, b, (int32_t)s, epoch);
+      wave_push(a.slist, cntS, (int32_t)s, sp);
+    }
+  }
+}
+
+// C: relabel and update the unstable set (T: keep block features; L: learned
+// policy bookkeeping)
+template <bool L, bool T>
+__device__ void phase_c(const Args& a, uint32_t par, uint32_t k, uint32_t C, const Part& p) {
+  const uint32_t nS = a.ctl->cntS[par].v[0];
+  const uint32_t nT = a.ctl->cntT[par].v[0];
+  uint32_t best = kNone;
+  for (uint32_t i0 = p.gwave * kWave; i0 < nS; i0 += p.gwaves * kWave) {
+    const uint32_t i = i0 + lane();
+    bool lead = false;
+    int32_t old = 0, nl = 0;
+    if (i < nS) {
+      const int32_t s = a.slist[i];
+      old = a.block[s];
+      nl = (int32_t)(kNone - (uint32_t)a.nlw[old]);
+      a.block[s] = nl;
+      lead = (s == nl);
+      if (T) {
+        atomicAdd(&a.acc[(size_t)nl * 17], 1u);
+        atomicSub(&a.acc[(size_t)old * 17], 1u);
+        for (int q = 0; q < 16; ++q) {
+          const uint32_t v = a.sfeat[(size_t)s * 16 + q];
+          if (v) {
+            atomicAdd(&a.acc[(size_t)nl * 17 + 1 + q], v);
+            atomicSub(&a.acc[(size_t)old * 17 + 1 + q], v);
+          }
+        }
+      }
+      if (lead) {
+        atomicOr((unsigned long long*)&a.ub[old >> 6], 1ull << (old & 63));
+        atomicOr((unsigned long long*)&a.ub[nl >> 6], 1ull << (nl & 63));
+        best = min(best, (uint32_t)old);
+        if (T) {
+          a.born[old] = k + 1;
+          a.born[nl] = k + 1;
+        }
+      }
+    }
+    if (L) {  // record (old, new) pairs for re-scoring
+      const uint64_t bal = __ballot(lead);
+      if (bal) {
+        const int leader = __ffsll((unsigned long long)bal) - 1;
+        uint32_t base = 0;
+        if ((int)lane() == leader) base = atomicAdd(&a.ctl->cntC[par].v[0], (uint32_t)__popcll(bal));
+        base = (uint32_t)__shfl((int)base, leader, kWave);
+        if (lead) {
+          const uint32_t idx = base + __popcll(bal & ((1ull << lane()) - 1ull));
+          a.chg[2 * idx] = old;
+          a.chg[2 * idx + 1] = nl;
+        }
+      }
+    }
+  }
+  for (uint32_t i = p.gtid; i < nT; i += p.gthreads) {
+    const int32_t s = a.tlist[i];
+    if (a.uniform) {
+      a.mw[s] = 0;
+    } else {
+      for (uint32_t q = a.woff[s]; q < a.woff[s + 1]; ++q) a.mw[q] = 0;
+    }
+    a.tb[s >> 6] = 0;
+    a.lt[s >> 6] = 0;
+  }
+  if (!L) {
+    best = wave_min_u32(best);
+    if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
+  }
+  if (p.gtid == 0) {
+    if (nS > 0) atomicOr((unsigned long long*)&a.ub[C >> 6], 1ull << (C & 63));
+    if (!L) {
+      if (nS > 0) atomicMin(&a.ctl->cand[par ^ 1].v[0], C);
+      a.ctl->cand[par].v[0] = kNone;
+    } else {
+      const bool full = a.rescore && ((k + 1) % a.rescore) == 0;
+      if (full)
+        *key_ptr(a.ctl, par ^ 1) = 0;  // every unstable block is re-scored in D
+      else if (nS > 0)
+        atomicMax((unsigned long long*)key_ptr(a.ctl, par ^ 1),
+                  (unsigned long long)score_key(a.score[C], C));
+      *key_ptr(a.ctl, par) = 0;
+    }
+    if (a.trace_nsplit && k < a.trace_cap) a.trace_nsplit[k] = nS;
+    if (a.trace_work && k < a.trace_cap) {
+      int64_t* w = a.trace_work + 4 * (uint64_t)k;
+      w[0] = a.ctl->work[par].v[0];
+      w[1] = a.ctl->work[par].v[1];
+      w[2] = nT;
+      w[3] = a.ctl->ltany[par].v[0];
+    }
+  }
+}
+
+// D (learned policy): re-score changed blocks, or every unstable block
+__device__ void phase_d(const Args& a, const MlpLds& M, uint32_t par, uint32_t k, const Part& p) {
+  const uint32_t kcur = k + 1;
+  uint64_t* key = key_ptr(a.ctl, par ^ 1);
+  const bool full = a.rescore && (kcur % a.rescore) == 0;
+  if (!full) {
+    const uint32_t nC = a.ctl->cntC[par].v[0];
+    for (uint32_t q = p.gwave; q < 2 * nC; q += p.gwaves)
+      score_block(a, M, (uint32_t)a.chg[q], kcur, key);
+  } else {
+    const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
+    for (uint32_t w = p.gwave; w < nwd; w += p.gwaves) {
+      uint64_t bits = a.ub[w];
+      while (bits) {
+        const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
+        bits &= bits - 1;
+        score_block(a, M, b, kcur, key);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-run initialisation
+// ---------------------------------------------------------------------------
+__global__ void k_init_run(Args a, const int32_t* __restrict__ pre, uint32_t first,
+                           uint64_t nwords, uint32_t learned) {
+  const Part p = part();
+  const uint32_t n = (uint32_t)a.n;
+  for (uint32_t s = p.gtid; s < n; s += p.gthreads) {
+    a.block[s] = pre[s];
+    a.nlw[s] = 0;
+  }
+  for (uint64_t w = p.gtid; w < nwords; w += p.gthreads) a.mw[w] = 0;
+  const uint32_t nwd = (n + 63u) >> 6;
+  for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
+    uint64_t bits = 0;
+    const uint32_t s0 = w << 6;
+    for (uint32_t j = 0; j < 64 && s0 + j < n; ++j)
+      if ((uint32_t)pre[s0 + j] == s0 + j) bits |= 1ull << j;
+    a.ub[w] = bits;
+    a.tb[w] = 0;
+    a.lt[w] = 0;
+  }
+  if (blockIdx.x == 0) {
+    uint32_t* c = reinterpret_cast<uint32_t*>(a.ctl);
+    for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) c[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.ctl->cand[0].v[0] = (n == 0 || learned) ? kNone : first;
+      a.ctl->cand[1].v[0] = kNone;
+    }
+  }
+}
+
+__global__ void k_zero_features(Args a) {
+  const Part p = part();
+  const uint64_t n = (uint32_t)a.n;
+  for (uint64_t i = p.gtid; i < 17 * n; i += p.gthreads) a.acc[i] = 0;
+  for (uint64_t i = p.gtid; i < n; i += p.gthreads) a.born[i] = 0;
+}
+__global__ void k_accumulate_features(Args a, const int32_t* __restrict__ pre) {
+  const Part p = part();
+  for (uint32_t s = p.gtid; s < (uint32_t)a.n; s += p.gthreads) {
+    const size_t b = (size_t)pre[s];
+    atomicAdd(&a.acc[b * 17], 1u);
+    for (int q = 0; q < 16; ++q) {
+      const uint32_t v = a.sfeat[(size_t)s * 16 + q];
+      if (v) atomicAdd(&a.acc[b * 17 + 1 + q], v);
+    }
+  }
+}
+// initial scores of the preprocessed blocks and the first candidate
+__global__ void k_init_scores(Args a, const int32_t* __restrict__ pre) {
+  extern __shared__ float sw[];
+  MlpLds M = mlp_lds_layout(sw, kPolicyF);
+  mlp_stage(M, a.wbf, kPolicyF);
+  __syncthreads();
+  const Part p = part();
+  for (uint32_t b = p.gwave; b < (uint32_t)a.n; b += p.gwaves)
+    if ((uint32_t)pre[b] == b) score_block(a, M, b, 0, key_ptr(a.ctl, 0));
+}
+
+__global__ void k_count_leaders(const int32_t* __restrict__ block, int32_t n,
+                                unsigned long long* out) {
+  const Part p = part();
+  uint32_t c = 0;
+  for (uint32_t s = p.gtid; s < (uint32_t)n; s += p.gthreads) c += (block[s] == (int32_t)s);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += (uint32_t)__shfl_xor((int)c, d, kWave);
+  if (lane() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+}  // namespace
+}  // namespace bisim

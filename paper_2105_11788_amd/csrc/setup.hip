@@ -192,6 +192,18 @@ __global__ void k_in_scatter(const int32_t* __restrict__ src, const int32_t* __r
   }
 }
 
+// outgoing / incoming transitions of every state by label mod 8 (block
+// features of the learned splitter policy are sums of these)
+__global__ void k_static_features(const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
+                                  const int32_t* __restrict__ dst, int64_t m,
+                                  uint32_t* __restrict__ sfeat) {
+  GSTRIDE(i, m) {
+    const uint32_t q = (uint32_t)lab[i] & 7u;
+    atomicAdd(&sfeat[(size_t)src[i] * 16 + q], 1u);
+    atomicAdd(&sfeat[(size_t)dst[i] * 16 + 8 + q], 1u);
+  }
+}
+
 template <class T>
 bisim_status dalloc(T** p, size_t count, hipStream_t s) {
   *p = nullptr;
@@ -354,6 +366,14 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
   if (m > 0)
     hipLaunchKernelGGL(k_in_scatter, dim3(grid_for(m, cu)), dim3(kT), 0, st, src, dst, ord, m,
                        cursor, h->in_src, h->in_ord);
+  BISIM_TRY_HIP(hipGetLastError());
+
+  // 7. per-state transition counts by label bucket (block features)
+  BISIM_TRY(dalloc(&h->sfeat, 16 * (size_t)n, st));
+  BISIM_TRY_HIP(hipMemsetAsync(h->sfeat, 0, sizeof(uint32_t) * 16 * (size_t)n, st));
+  if (m > 0)
+    hipLaunchKernelGGL(k_static_features, dim3(grid_for(m, cu)), dim3(kT), 0, st, src, lab, dst,
+                       m, h->sfeat);
   BISIM_TRY_HIP(hipGetLastError());
   return BISIM_OK;
 }

@@ -264,6 +264,15 @@ def random_lts(n: int, m: int, K: int, seed: int, init_blocks: int = 0) -> LTS:
     return LTS(n, K, src, lab, dst, init, name=f"random(n={n},m={m},K={K},seed={seed})")
 
 
+def uniform_zipf(n: int = 1000, m: int = 5000, K: int = 64, seed: int = 1) -> LTS:
+    """Uniform src/dst, Zipf(1.1) labels over K actions, pi_0 = {S}."""
+    rng = _rng(seed)
+    src = rng.integers(0, n, size=m, dtype=np.int64)
+    dst = rng.integers(0, n, size=m, dtype=np.int64)
+    lab = zipf_labels(rng, m, K)
+    return LTS(n, K, src, lab, dst, None, name=f"uniform_zipf(n={n},m={m},K={K},seed={seed})")
+
+
 def uniform_lts(n: int, deg_mean: float, K: int, seed: int) -> LTS:
     """Poisson(deg_mean) out-degree per state, uniform targets and labels."""
     rng = _rng(seed)
