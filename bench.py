@@ -1,20 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark: strong-bisimulation refinement on one MI355X.
 
-A step is one full fixpoint of the plain refinement loop (coarsest_partition:
-every iteration of select -> mark -> compare/elect -> relabel until no block
-is unstable) on an LTS already loaded in HBM.  The metric is
-transitions x iterations per second, m * #It / (seconds per step).
+A step is one full fixpoint of the refinement loop (every iteration of
+select -> mark -> compare/elect -> relabel until no block is unstable) on an
+LTS already loaded in HBM.  The metric is transitions x iterations per
+second, m * #It / (seconds per step); for a batch, sum_k m_k * #It_k over
+the wall time of the batch.
 
-Default workload: a planted-quotient LTS with ~1.03M states and ~8.2M
-transitions (50,000 quotient nodes, Poisson(8) out-degree, Zipf(1.1) labels
-over 16 actions, U{1..40} copies per node, seed 1).
+Forms (--form):
+  plain    (default) the plain method, smallest-label splitter, on the
+           planted-quotient LTS with ~1.03M states / ~8.2M transitions
+           (50,000 quotient nodes, Poisson(8) out-degree, Zipf(1.1) labels
+           over 16 actions, U{1..40} copies per node, seed 1);
+  batched  4096 independent LTSs in one launch (sizes log-uniform in
+           [100, n_hi], Poisson(6), K ~ U{1..32}, half planted), against
+           running each instance alone with the plain engine (timed on a
+           sample of instances and scaled);
+  learned  the learned splitter policy (network trained on the GPU first)
+           against the plain policy on the same LTS.
 
-Prints one JSON line.  Extra fields: `roofline` for the persistent
-refinement kernel (algorithmic bytes per launch from the per-iteration work
-counters / its HIP-event-timed duration, against 8 TB/s), and `cpu_baseline`
-(the CPU oracle's lock-step simulation timed on a bounded prefix of the same
-workload, single-threaded).
+Prints one JSON line.  Extra fields: `roofline` for the dominant kernel
+(algorithmic bytes per launch from the per-iteration work counters / its
+HIP-event-timed duration, against 8 TB/s, with the measured copy bandwidth
+beside it), and `cpu_baseline` (the CPU oracle timed on a bounded prefix of
+the same workload, single-threaded).
 """
 from __future__ import annotations
 
@@ -53,6 +62,10 @@ WORKLOADS = {
 }
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes(n: int, work: np.ndarray, nsplit: np.ndarray) -> float:
     """Bytes one fixpoint must move with this layout (int32 ids, 64-bit mark
     words, 1-bit unstable/touched/leader-touched flags), summed over
@@ -87,11 +100,11 @@ def cpu_baseline(L, target_s: float = 12.0):
         return time.perf_counter() - t, r
 
     t1, _ = timed(1)
-    t5, r5 = timed(6)
+    t5, _ = timed(6)
     per_it = max((t5 - t1) / 5, 1e-6)
     X = int(max(5, min(100000, target_s / per_it)))
     tX, rX = timed(1 + X)
-    X_done = rX["iters"] - 1 if not rX["truncated"] else X
+    X_done = X if rX["truncated"] else rX["iters"] - 1
     el = max(tX - t1, 1e-9)
     return {
         "value": L.m * X_done / el,
@@ -104,79 +117,14 @@ def cpu_baseline(L, target_s: float = 12.0):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="planted-quotient-1M", choices=sorted(WORKLOADS))
-    ap.add_argument("--engine", type=int, default=1, help="1 persistent, 2 per-phase kernels")
-    ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only: the refinement of one "
-                                   "LTS is a single-device fixpoint; run with --gpus 1"}))
-        sys.exit(2)
-
-    from paper_2105_11788_amd import bisim, gen
-
-    wl = WORKLOADS[args.workload]
-    t = time.perf_counter()
-    L = wl["make"](gen)
-    t_gen = time.perf_counter() - t
-    print(f"[bench] workload {args.workload}: n={L.n} m={L.m} K={L.K} (generated in {t_gen:.1f}s)",
-          file=sys.stderr, flush=True)
-
-    bisim.load_library()
-    if bisim.device_count() < 1:
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(3)
+def upload(bisim, L):
     to = lambda a: bisim.DeviceArray.from_numpy(a, np.int32)
-    src, lab, dst = to(L.src), to(L.lab), to(L.dst)
-    init = None if L.init is None else to(L.init)
-    h = bisim.LTS(src, lab, dst, L.n, L.K, init)
-    h.set_option(bisim.OPT_ENGINE, args.engine)
-    if args.grid:
-        h.set_option(bisim.OPT_GRID, args.grid)
-    out = bisim.DeviceArray(L.n, np.int32)
+    return to(L.src), to(L.lab), to(L.dst), (None if L.init is None else to(L.init))
 
-    for w in range(args.warmup):
-        _, st = h.run(out)
-        print(f"[bench] warmup {w}: #It={st.iterations} blocks={st.blocks} "
-              f"t_alg={st.t_alg_ms:.1f} ms", file=sys.stderr, flush=True)
 
-    bisim.synchronize()
-    t0 = time.perf_counter()
-    alg_ms = []
-    for k in range(args.steps):
-        _, st = h.run(out)
-        alg_ms.append(st.t_alg_ms)
-    bisim.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    iters = st.iterations
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, #It={iters}",
-          file=sys.stderr, flush=True)
-
-    # one traced run outside the timed region for the byte count
-    tr = h.set_trace(iters + 1, work=True)
-    _, st_tr = h.run(out)
-    assert st_tr.iterations == iters
-    h.set_trace(0)
-    work = tr[2].numpy().reshape(-1, 4)[:iters]
-    nsplit = tr[1].numpy()[:iters]
-    bytes_launch = algorithmic_bytes(L.n, work, nsplit)
-    kern_ms = float(np.mean(alg_ms))
-    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
-    h.close()
-
-    value = L.m * iters / (ms_per_step * 1e-3)
-    res = {
-        "metric": "transitions*iterations/sec (plain refinement to fixpoint)",
+def base_record(args, metric, value, ms_per_step, config):
+    return {
+        "metric": metric,
         "value": value,
         "unit": "transition*iterations/s",
         "n_gpus": 1,
@@ -188,20 +136,68 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {
-            "workload": args.workload,
-            "description": wl["desc"],
-            "n": L.n, "m": L.m, "K": L.K,
-            "iterations": iters,
-            "blocks": st.blocks,
-            "pre_blocks": st.pre_blocks,
-            "mark_length": st.mark_length,
-            "form": "plain",
-            "engine": {1: "persistent", 2: "per-phase"}.get(args.engine, str(args.engine)),
-        },
-        "seconds_to_fixpoint": ms_per_step / 1000.0,
+        "config": config,
+    }
+
+
+def run_single(bisim, L, args, engine, mlp=None, trace=True):
+    """Time `steps` fixpoints of one LTS; returns a dict of measurements."""
+    src, lab, dst, init = upload(bisim, L)
+    h = bisim.LTS(src, lab, dst, L.n, L.K, init)
+    h.set_option(bisim.OPT_ENGINE, engine)
+    if args.grid:
+        h.set_option(bisim.OPT_GRID, args.grid)
+    if mlp is not None:
+        bisim.set_splitter_policy(h, bisim.POLICY_LEARNED, mlp, args.rescore)
+    out = bisim.DeviceArray(L.n, np.int32)
+    for w in range(args.warmup):
+        _, st = h.run(out)
+        log(f"warmup {w}: #It={st.iterations} blocks={st.blocks} t_alg={st.t_alg_ms:.1f} ms")
+    bisim.synchronize()
+    t0 = time.perf_counter()
+    alg_ms = []
+    for _ in range(args.steps):
+        _, st = h.run(out)
+        alg_ms.append(st.t_alg_ms)
+    bisim.synchronize()
+    t1 = time.perf_counter()
+    res = {"ms_per_step": (t1 - t0) * 1000.0 / args.steps, "stats": st,
+           "kern_ms": float(np.mean(alg_ms)), "block": out.numpy()}
+    if trace:
+        iters = st.iterations
+        tr = h.set_trace(iters + 1, work=True)
+        _, st_tr = h.run(out)
+        assert st_tr.iterations == iters
+        h.set_trace(0)
+        res["work"] = tr[2].numpy().reshape(-1, 4)[:iters]
+        res["nsplit"] = tr[1].numpy()[:iters]
+    h.close()
+    return res
+
+
+def form_plain(bisim, gen, args):
+    wl = WORKLOADS[args.workload]
+    t = time.perf_counter()
+    L = wl["make"](gen)
+    log(f"workload {args.workload}: n={L.n} m={L.m} K={L.K} ({time.perf_counter() - t:.1f}s)")
+    r = run_single(bisim, L, args, args.engine)
+    st = r["stats"]
+    iters = st.iterations
+    bytes_launch = algorithmic_bytes(L.n, r["work"], r["nsplit"])
+    achieved = bytes_launch / (r["kern_ms"] * 1e-3) / 1e9
+    copy_gbs = bisim.copy_bandwidth(1 << 30)
+    log(f"{r['ms_per_step']:.2f} ms/step, #It={iters}, kernel {r['kern_ms']:.2f} ms, "
+        f"{achieved:.1f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s")
+    cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
+           "iterations": iters, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
+           "mark_length": st.mark_length, "form": "plain",
+           "engine": {1: "persistent", 2: "per-phase"}.get(args.engine, str(args.engine))}
+    res = base_record(args, "transitions*iterations/sec (plain refinement to fixpoint)",
+                      L.m * iters / (r["ms_per_step"] * 1e-3), r["ms_per_step"], cfg)
+    res.update({
+        "seconds_to_fixpoint": r["ms_per_step"] / 1000.0,
         "t_pre_ms": st.t_pre_ms,
-        "us_per_iteration": kern_ms * 1000.0 / iters,
+        "us_per_iteration": r["kern_ms"] * 1000.0 / iters,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_persistent" if args.engine == 1 else "k_phase_*",
@@ -211,12 +207,136 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
             "bytes_per_launch": bytes_launch,
-            "kernel_ms": kern_ms,
+            "kernel_ms": r["kern_ms"],
+            "measured_copy_GBs": copy_gbs,
         },
-    }
+    })
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
+        log("cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline(L, args.cpu_seconds)
+    return res
+
+
+def form_batched(bisim, gen, args):
+    t = time.perf_counter()
+    insts = gen.batch(count=args.count, n_lo=100, n_hi=args.n_hi, seed=1)
+    N = sum(x.n for x in insts)
+    M = sum(x.m for x in insts)
+    log(f"batch: {len(insts)} instances, sum n={N} sum m={M} ({time.perf_counter() - t:.1f}s)")
+    b = bisim.Batch(insts)
+    out = bisim.DeviceArray(b.N, np.int32)
+    for w in range(args.warmup):
+        _, its, st = b.run(out)
+        log(f"warmup {w}: max #It={st['max_iterations']} t_alg={st['t_alg_ms']:.1f} ms "
+            f"(wg {st['workgroup_size']}, grid {st['grid']}, lds/global {st['lds_instances']}/"
+            f"{st['global_instances']})")
+    bisim.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, its, st = b.run(out)
+    bisim.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    work = float(sum(x.m * int(i) for x, i in zip(insts, its)))
+    b.close()
+    # the same instances one at a time through the plain single-instance engine
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(insts), size=min(args.plain_sample, len(insts)), replace=False)
+    t_s, it_s = 0.0, 0
+    for k in sample:
+        L = insts[int(k)]
+        src, lab, dst, init = upload(bisim, L)
+        with bisim.LTS(src, lab, dst, L.n, L.K, init) as h:
+            h.set_option(bisim.OPT_ENGINE, args.engine)
+            o = bisim.DeviceArray(max(L.n, 1), np.int32)
+            h.run(o)
+            bisim.synchronize()
+            t1 = time.perf_counter()
+            _, s1 = h.run(o)
+            bisim.synchronize()
+            t_s += time.perf_counter() - t1
+            it_s += s1.iterations
+            assert s1.iterations == its[int(k)]
+    scale = float(its.sum()) / max(it_s, 1)
+    plain_est_ms = t_s * 1000.0 * scale
+    log(f"batched {ms:.1f} ms; plain one-by-one estimate {plain_est_ms:.0f} ms "
+        f"({len(sample)} sampled instances, scaled by iterations)")
+    cfg = {"workload": f"batch-{args.count}-up-to-{args.n_hi}",
+           "description": f"{args.count} LTSs, log-uniform 100..{args.n_hi} states, Poisson(6), "
+                          "K~U{1..32}, half planted quotients, seed 1",
+           "instances": args.count, "sum_n": N, "sum_m": M,
+           "max_iterations": int(its.max()), "sum_iterations": int(its.sum()),
+           "form": "batched", "workgroup_size": st["workgroup_size"], "grid": st["grid"],
+           "lds_instances": st["lds_instances"], "global_instances": st["global_instances"]}
+    res = base_record(args, "transitions*iterations/sec (batched refinement to fixpoint)",
+                      work / (ms * 1e-3), ms, cfg)
+    res.update({"seconds_to_fixpoint": ms / 1000.0,
+                "plain_one_by_one_estimate_s": plain_est_ms / 1000.0,
+                "speedup_vs_plain": plain_est_ms / ms,
+                "iteration_count": {"batched_critical_path": int(its.max()),
+                                    "plain_sequential_total": int(its.sum())}})
+    return res
+
+
+def form_learned(bisim, gen, args):
+    from paper_2105_11788_amd import learn
+    t = time.perf_counter()
+    mlp, losses, rows = learn.train_policy(train_seeds=range(1001, 1001 + args.train_lts),
+                                           steps=args.train_steps)
+    t_train = time.perf_counter() - t
+    log(f"trained on {rows} rows in {t_train:.1f}s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    wl = WORKLOADS[args.workload]
+    L = wl["make"](gen)
+    log(f"workload {args.workload}: n={L.n} m={L.m} K={L.K}")
+    rp = run_single(bisim, L, args, args.engine, trace=False)
+    rl = run_single(bisim, L, args, args.engine, mlp=mlp, trace=False)
+    assert (rp["block"] == rl["block"]).all(), "learned policy changed the partition"
+    ip, il = rp["stats"].iterations, rl["stats"].iterations
+    log(f"plain #It={ip} {rp['ms_per_step']:.1f} ms; learned #It={il} {rl['ms_per_step']:.1f} ms")
+    cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
+           "form": "learned", "iterations": il, "plain_iterations": ip,
+           "rescore_every": args.rescore, "train_rows": rows, "train_seconds": t_train}
+    res = base_record(args, "transitions*iterations/sec (learned-splitter refinement)",
+                      L.m * il / (rl["ms_per_step"] * 1e-3), rl["ms_per_step"], cfg)
+    res.update({"seconds_to_fixpoint": rl["ms_per_step"] / 1000.0,
+                "plain_seconds_to_fixpoint": rp["ms_per_step"] / 1000.0,
+                "iteration_ratio_learned_over_plain": il / ip,
+                "wall_ratio_learned_over_plain": rl["ms_per_step"] / rp["ms_per_step"],
+                "partition_equal": True})
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"])
+    ap.add_argument("--workload", default="planted-quotient-1M", choices=sorted(WORKLOADS))
+    ap.add_argument("--engine", type=int, default=1, help="1 persistent, 2 per-phase kernels")
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--count", type=int, default=4096)
+    ap.add_argument("--n-hi", type=int, default=10_000)
+    ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--rescore", type=int, default=64)
+    ap.add_argument("--train-lts", type=int, default=12)
+    ap.add_argument("--train-steps", type=int, default=300)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the refinement of one "
+                                   "LTS is a single-device fixpoint; run with --gpus 1"}))
+        sys.exit(2)
+
+    from paper_2105_11788_amd import bisim, gen
+    bisim.load_library()
+    if bisim.device_count() < 1:
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(3)
+    res = {"plain": form_plain, "batched": form_batched, "learned": form_learned}[args.form](
+        bisim, gen, args)
     print(json.dumps(res), flush=True)
 
 

@@ -320,6 +320,19 @@ bisim_status bisim_collect_training(bisim_lts* h, int64_t sample_every, int32_t 
                                     float* feat, float* target, int32_t* meta, int64_t cap,
                                     int64_t* rows);
 
+/* ------------------------------------------------------------------------ */
+/* Measurement                                                               */
+/* ------------------------------------------------------------------------ */
+/*
+ * bisim_device_copy — copy `bytes` (a multiple of 16, 16-byte aligned device
+ * pointers) with a plain streaming kernel and report its device time in ms
+ * (ms_out, host, nullable).  Used to measure the bandwidth the device
+ * sustains and to calibrate memory-traffic counters; not part of the method.
+ * Errors: BISIM_E_INVALID, BISIM_E_DEVICE.
+ */
+bisim_status bisim_device_copy(void* dst, const void* src, int64_t bytes, void* hip_stream,
+                               double* ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -507,6 +507,27 @@ def collect_training(lts: "LTS", sample_every: int = 1, max_cands: int = 64, cap
             m.numpy()[:2 * r].reshape(r, 2))
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, repeats: int = 5) -> float:
+    """GB/s of a plain device copy of nbytes (read + write counted), best of
+    `repeats` (bisim_device_copy)."""
+    L = load_library()
+    if not getattr(L, "_copy_declared", False):
+        L.bisim_device_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+        L.bisim_device_copy.restype = ctypes.c_int32
+        L._copy_declared = True
+    nbytes -= nbytes % 16
+    a = DeviceArray(nbytes // 4, np.int32).fill(1)
+    b = DeviceArray(nbytes // 4, np.int32)
+    best = float("inf")
+    for _ in range(repeats):
+        ms = ctypes.c_double(0)
+        _check(L.bisim_device_copy(ctypes.c_void_p(b.ptr), ctypes.c_void_p(a.ptr), nbytes, None,
+                                   ctypes.byref(ms)))
+        best = min(best, ms.value)
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def coarsest_partition(src, lab, dst, n: int, num_actions: int, init=None,
                        engine: int = ENGINE_AUTO):
     """One-shot: load, refine, free.  Returns (block ids as numpy, Stats)."""

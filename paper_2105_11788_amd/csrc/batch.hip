@@ -456,6 +456,15 @@ BArgs make_args(bisim_batch* b, int32_t* out) {
   return a;
 }
 
+// allow dynamic LDS up to the device's per-workgroup maximum
+void allow_lds(bisim_batch* b) {
+  (void)hipFuncSetAttribute((const void*)k_batch<uint64_t>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, b->lds_max);
+  (void)hipFuncSetAttribute((const void*)k_batch<uint32_t>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, b->lds_max);
+  (void)hipGetLastError();
+}
+
 bisim_status launch_once(bisim_batch* b, int32_t* out, int wg, int grid, int lds) {
   BArgs a = make_args(b, out);
   a.lds_bytes = (uint32_t)lds;
@@ -632,6 +641,7 @@ bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* 
       break;
     }
     b->lds_max -= (int)sizeof(Shared) + 64;
+    allow_lds(b);
     b->stream = hip_stream ? (hipStream_t)hip_stream : b->own_stream;
     hipStream_t s = b->stream;
     if (hipEventRecord(b->ev0, s) != hipSuccess) { st = BISIM_E_DEVICE; break; }

@@ -49,7 +49,8 @@ struct Ctl {
   Line key[2];    // learned policy: v[0..1] = 64-bit (score, ~label) key, max-reduced
   Line cntC[2];   // learned policy: changed (old, new) block pairs this iteration
   Line state;     // v[0] iterations done, v[1] done flag, v[2] error, v[3] current splitter
-  Line bar;       // v[0] arrivals, v[1] generation, v[2] abort
+  Line bar;       // v[0] group arrivals, v[1] generation, v[2] abort
+  Line barg[8];   // v[0]: arrivals within workgroup group g (blockIdx % 8)
 };
 
 // ---------------------------------------------------------------------------

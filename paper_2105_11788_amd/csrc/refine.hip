@@ -87,20 +87,42 @@ __global__ void __launch_bounds__(kT) k_phase_d(Args a, uint32_t k) {
 // ---------------------------------------------------------------------------
 // engine 1: persistent cooperative kernel
 // ---------------------------------------------------------------------------
+// Grid barrier.  Arrival is two-level: workgroups are grouped by
+// blockIdx % 8 (the hardware deals consecutive workgroups round-robin to the
+// 8 XCDs), the last arriver of each group arrives at the top counter, and the
+// last of those advances the generation.  Every arrival is preceded by an
+// agent-scope release (this workgroup's writes reach memory visible to all
+// XCDs); waiting polls the generation with relaxed loads and issues a single
+// acquire fence once it has moved, so polling does not keep invalidating the
+// caches the other workgroups of the XCD are using.  The wait is bounded:
+// after the timeout every workgroup leaves through the abort flag.
 __device__ bool grid_barrier(Ctl* ctl, uint32_t& gen) {
   __shared__ uint32_t ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t g = gen;
-    __threadfence();
-    const uint32_t arrived = atomicAdd(&ctl->bar.v[0], 1u);
-    if (arrived == gridDim.x - 1) {
-      atomicExch(&ctl->bar.v[0], 0u);
-      __threadfence();
-      atomicExch(&ctl->bar.v[1], g + 1);
-    } else {
+    const uint32_t groups = gridDim.x < 8 ? gridDim.x : 8;
+    const uint32_t grp = blockIdx.x % groups;
+    const uint32_t members = (gridDim.x - grp + groups - 1) / groups;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    uint32_t* gcount = &ctl->barg[grp].v[0];
+    const uint32_t a1 = __hip_atomic_fetch_add(gcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool last = false;
+    if (a1 == members - 1) {
+      // the group counter is reset before (release) the arrival that can
+      // let the generation advance
+      __hip_atomic_store(gcount, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t a2 =
+          __hip_atomic_fetch_add(&ctl->bar.v[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (a2 == groups - 1) {
+        __hip_atomic_store(&ctl->bar.v[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->bar.v[1], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
       const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&ctl->bar.v[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(&ctl->bar.v[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (__hip_atomic_load(&ctl->bar.v[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
           atomicExch(&ctl->bar.v[2], 1u);
@@ -109,7 +131,7 @@ __device__ bool grid_barrier(Ctl* ctl, uint32_t& gen) {
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     gen = g + 1;
     ok = __hip_atomic_load(&ctl->bar.v[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
   }
@@ -496,6 +518,9 @@ bisim_status bisim_collect_training(bisim_lts* h, int64_t sample_every, int32_t 
     return BISIM_E_UNSUPPORTED;
   }
   hipStream_t st = h->stream;
+  (void)hipFuncSetAttribute((const void*)k_collect, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  (void)hipGetLastError();
   BISIM_TRY(refine_alloc_features(h));
   int64_t cap_it = 3 * (int64_t)h->n - h->pre_blocks + 1;
   if (cap_it < 1) cap_it = 1;

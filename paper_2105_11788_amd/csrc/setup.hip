@@ -126,8 +126,11 @@ __global__ void k_round_split(int32_t n, const int32_t* __restrict__ block,
   GSTRIDE(s, (int64_t)n) {
     int32_t b = block[s];
     if (has[s] != has[b]) {
-      atomicMax((unsigned long long*)&nlw[b],
-                (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
+      // the bids of one round only grow, so a bid not above the current
+      // value cannot win and skips the atomic
+      const uint64_t val = epoch | (uint64_t)(kNone - (uint32_t)s);
+      if (__hip_atomic_load(&nlw[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < val)
+        atomicMax((unsigned long long*)&nlw[b], (unsigned long long)val);
       flag[s] = 1;
     }
   }
