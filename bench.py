@@ -66,26 +66,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(n: int, work: np.ndarray, nsplit: np.ndarray) -> float:
-    """Bytes one fixpoint must move with this layout (int32 ids, 64-bit mark
-    words, 1-bit unstable/touched/leader-touched flags), summed over
-    iterations.  Per iteration:
-      select   n/8 (unstable bitmap)
-      mark     4n (block[] scan) + 8 per member of C (in_ptr pair)
-               + 24 per in-transition (source, rank, mark-word RMW)
-               + 8 per touched state (list append, leader test)
-      compare  24 per touched state (list, block, own + leader mark words)
-               + [a leader was touched] (4n block scan + n/4 touched/leader bits)
-               + 12 per split state (bid, list append)
-      relabel  20 per split state (list, block r/w, new-leader word)
-               + 28 per touched state (list, mark word, touched/leader words)
-    The final pass reads the candidate only."""
+def phase_bytes(n: int, work: np.ndarray, nsplit: np.ndarray):
+    """Bytes each phase of each iteration must move with this layout (int32
+    ids, 64-bit mark words, 1-bit unstable/touched/leader-touched flags):
+      select+mark    n/8 (unstable bitmap) + 4n (block[] scan)
+                     + 8 per member of C (in_ptr pair)
+                     + 24 per in-transition of C (source, rank, mark-word RMW)
+                     + 8 per touched state (list append, leader test)
+      compare+elect  24 per touched state (list, block, own + leader mark words)
+                     + [a leader was touched] (4n block scan + n/4 flag bits)
+                     + 12 per split state (bid, list append)
+      relabel        20 per split state (list, block r/w, new-leader word)
+                     + 28 per touched state (list, mark word, touched/leader words)
+    Returns an array [iterations, 3]; the final pass (no splitter) is zero."""
     members, edges, touched, ltany = (work[:, i].astype(np.float64) for i in range(4))
     s = nsplit.astype(np.float64)
-    per = (n / 8 + 4 * n + 8 * members + 24 * edges + 8 * touched + 24 * touched
-           + ltany * (4 * n + n / 4) + 12 * s + 20 * s + 28 * touched)
-    per[-1] = 0.0  # final pass: no splitter
-    return float(per.sum())
+    out = np.stack([n / 8 + 4 * n + 8 * members + 24 * edges + 8 * touched,
+                    24 * touched + ltany * (4 * n + n / 4) + 12 * s,
+                    20 * s + 28 * touched], axis=1)
+    out[-1] = 0.0
+    return out
 
 
 def cpu_baseline(L, target_s: float = 12.0):
@@ -150,9 +150,12 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
     if mlp is not None:
         bisim.set_splitter_policy(h, bisim.POLICY_LEARNED, mlp, args.rescore)
     out = bisim.DeviceArray(L.n, np.int32)
+    st = None
     for w in range(args.warmup):
         _, st = h.run(out)
         log(f"warmup {w}: #It={st.iterations} blocks={st.blocks} t_alg={st.t_alg_ms:.1f} ms")
+    if engine != 1 and st is not None:  # sample ~200 iterations' phase kernels per step
+        h.set_option(bisim.OPT_PROFILE_EVERY, max(1, st.iterations // 200))
     bisim.synchronize()
     t0 = time.perf_counter()
     alg_ms = []
@@ -163,6 +166,9 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
     t1 = time.perf_counter()
     res = {"ms_per_step": (t1 - t0) * 1000.0 / args.steps, "stats": st,
            "kern_ms": float(np.mean(alg_ms)), "block": out.numpy()}
+    if engine != 1:
+        res["phase_ms"], res["phase_samples"] = h.phase_times()
+        h.set_option(bisim.OPT_PROFILE_EVERY, 0)
     if trace:
         iters = st.iterations
         tr = h.set_trace(iters + 1, work=True)
@@ -183,15 +189,30 @@ def form_plain(bisim, gen, args):
     r = run_single(bisim, L, args, args.engine)
     st = r["stats"]
     iters = st.iterations
-    bytes_launch = algorithmic_bytes(L.n, r["work"], r["nsplit"])
-    achieved = bytes_launch / (r["kern_ms"] * 1e-3) / 1e9
+    pb = phase_bytes(L.n, r["work"], r["nsplit"])
     copy_gbs = bisim.copy_bandwidth(1 << 30)
-    log(f"{r['ms_per_step']:.2f} ms/step, #It={iters}, kernel {r['kern_ms']:.2f} ms, "
-        f"{achieved:.1f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s")
+    names = ["k_phase_a (select+mark)", "k_phase_b (compare+elect)", "k_phase_c (relabel)"]
+    if args.engine == 1:
+        kernel, bytes_launch, kern_ms = "k_persistent", float(pb.sum()), r["kern_ms"]
+        per_phase = None
+    else:
+        ms = r["phase_ms"][:3]
+        q = int(np.argmax(ms))  # every phase runs once per iteration
+        kernel = names[q]
+        bytes_launch = float(pb[:-1, q].mean())
+        kern_ms = float(ms[q])
+        per_phase = {names[i]: {"avg_us": float(ms[i] * 1e3),
+                                "bytes_per_launch": float(pb[:-1, i].mean()),
+                                "GBs": float(pb[:-1, i].mean() / (ms[i] * 1e-3) / 1e9)
+                                if ms[i] > 0 else None,
+                                "samples": int(r["phase_samples"][i])} for i in range(3)}
+    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+    log(f"{r['ms_per_step']:.2f} ms/step, #It={iters}, {kernel}: {kern_ms * 1e3:.2f} us/launch, "
+        f"{achieved:.1f} GB/s algorithmic; copy {copy_gbs:.0f} GB/s")
     cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
            "iterations": iters, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
            "mark_length": st.mark_length, "form": "plain",
-           "engine": {1: "persistent", 2: "per-phase"}.get(args.engine, str(args.engine))}
+           "engine": "persistent" if args.engine == 1 else "per-phase kernels"}
     res = base_record(args, "transitions*iterations/sec (plain refinement to fixpoint)",
                       L.m * iters / (r["ms_per_step"] * 1e-3), r["ms_per_step"], cfg)
     res.update({
@@ -200,15 +221,16 @@ def form_plain(bisim, gen, args):
         "us_per_iteration": r["kern_ms"] * 1000.0 / iters,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_persistent" if args.engine == 1 else "k_phase_*",
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
             "bytes_per_launch": bytes_launch,
-            "kernel_ms": r["kern_ms"],
+            "kernel_ms": kern_ms,
             "measured_copy_GBs": copy_gbs,
+            "per_phase": per_phase,
         },
     })
     if not args.no_cpu_baseline:
@@ -312,7 +334,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"])
     ap.add_argument("--workload", default="planted-quotient-1M", choices=sorted(WORKLOADS))
-    ap.add_argument("--engine", type=int, default=1, help="1 persistent, 2 per-phase kernels")
+    ap.add_argument("--engine", type=int, default=0,
+                    help="0 automatic (per-phase kernels), 1 persistent, 2 per-phase kernels")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -131,7 +131,19 @@ const char* bisim_last_error(void);
 #define BISIM_OPT_FIRST_SPLITTER 2
 #define BISIM_OPT_ITER_LIMIT 3
 #define BISIM_OPT_GRID 4
+#define BISIM_OPT_PROFILE_EVERY 5 /* 0 (default) or P: with the per-phase engine, time the
+                                     phase kernels of every P-th iteration (at most 256
+                                     iterations per run) with kernel start/stop events */
 bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
+
+/*
+ * bisim_get_phase_times — after a run with BISIM_OPT_PROFILE_EVERY > 0:
+ * average kernel execution time in ms (avg_ms, host, 4 entries: select+mark,
+ * compare+elect, relabel, re-score) over the sampled iterations that had a
+ * splitter, and the number of samples per phase (samples, host, 4 entries).
+ * Errors: BISIM_E_INVALID.
+ */
+bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* samples);
 
 /*
  * bisim_set_trace — record, for each iteration k < cap of subsequent

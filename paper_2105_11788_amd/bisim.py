@@ -35,6 +35,7 @@ OPT_ENGINE = 1
 OPT_FIRST_SPLITTER = 2
 OPT_ITER_LIMIT = 3
 OPT_GRID = 4
+OPT_PROFILE_EVERY = 5
 
 ENGINE_AUTO = 0
 ENGINE_PERSISTENT = 1
@@ -45,7 +46,7 @@ EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
            "lts_batch_load", "coarsest_partition_batch", "lts_batch_free",
            "bisim_batch_set_option", "mlp_num_params", "mlp_create", "mlp_free",
            "mlp_get_params", "mlp_forward", "mlp_train_step", "bisim_set_splitter_policy",
-           "bisim_collect_training"]
+           "bisim_collect_training", "bisim_get_phase_times", "bisim_device_copy"]
 
 
 class BisimError(RuntimeError):
@@ -254,6 +255,20 @@ class LTS:
         _check(self._L.coarsest_partition(self._h, po, ctypes.byref(st)))
         return out, Stats(st.iterations, st.blocks, st.pre_blocks, st.mark_length,
                           st.t_pre_ms, st.t_alg_ms)
+
+    def phase_times(self):
+        """(avg kernel ms per phase [select+mark, compare+elect, relabel, re-score],
+        samples per phase) of the last run with OPT_PROFILE_EVERY set."""
+        L = self._L
+        if not getattr(L, "_phase_declared", False):
+            L.bisim_get_phase_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+            L.bisim_get_phase_times.restype = ctypes.c_int32
+            L._phase_declared = True
+        ms = np.zeros(4, np.float64)
+        cnt = np.zeros(4, np.int64)
+        _check(L.bisim_get_phase_times(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                       cnt.ctypes.data_as(ctypes.c_void_p)))
+        return ms, cnt
 
     def preprocessed(self):
         """(pi_pre block ids, nr_marks) as numpy arrays."""

@@ -29,6 +29,8 @@ static void free_handle(bisim_lts* h) {
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  for (int i = 0; i < 8 * h->pev_slots; ++i) (void)hipEventDestroy(h->pev[i]);
+  delete[] h->pev;
   delete h;
 }
 static bisim_status load_impl(const int32_t* src, const int32_t* label, const int32_t* dst,
@@ -166,6 +168,10 @@ bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value) {
       if (value < 0 || value > (1 << 20)) break;
       h->grid = (int)value;
       return BISIM_OK;
+    case BISIM_OPT_PROFILE_EVERY:
+      if (value < 0) break;
+      h->profile_every = value;
+      return BISIM_OK;
     default:
       break;
   }
@@ -183,6 +189,18 @@ bisim_status bisim_set_trace(bisim_lts* h, int32_t* trace_C, int64_t* trace_nspl
   h->trace_nsplit = cap ? trace_nsplit : nullptr;
   h->trace_work = cap ? trace_work : nullptr;
   h->trace_cap = cap;
+  return BISIM_OK;
+}
+
+bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* samples) {
+  if (!h || !avg_ms) {
+    set_error("bisim_get_phase_times: NULL argument");
+    return BISIM_E_INVALID;
+  }
+  for (int q = 0; q < 4; ++q) {
+    avg_ms[q] = h->phase_cnt[q] ? h->phase_ms[q] / (double)h->phase_cnt[q] : 0.0;
+    if (samples) samples[q] = h->phase_cnt[q];
+  }
   return BISIM_OK;
 }
 

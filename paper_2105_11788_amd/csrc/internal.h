@@ -147,6 +147,13 @@ struct bisim_lts {
   const uint16_t* policy_w = nullptr;  // bf16 network parameters (18 inputs)
   int rescore_every = 64;
 
+  // sampled phase timing (per-phase engine)
+  int64_t profile_every = 0;
+  hipEvent_t* pev = nullptr;  // 8 events per sampled iteration
+  int pev_slots = 0;
+  double phase_ms[4] = {0, 0, 0, 0};
+  int64_t phase_cnt[4] = {0, 0, 0, 0};
+
   double t_pre_ms = 0.0;
   double t_alg_ms = 0.0;
   int64_t last_iters = 0;

@@ -40,7 +40,11 @@
 // L2s see each other's writes); (2) one kernel per phase, enqueued in
 // batches with a device-side done flag, where kernel boundaries are the
 // barriers.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
+#include <new>
+#include <vector>
 
 #include "internal.h"
 #include "mlp_dev.h"
@@ -301,8 +305,9 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
 
   const int cu = h->num_cu > 0 ? h->num_cu : 1;
   const size_t lds = learned ? mlp_lds_floats(kPolicyF) * sizeof(float) : 0;
+  std::vector<uint32_t> sampled;
   int engine = h->engine;
-  if (engine == 0) engine = 1;
+  if (engine == 0) engine = 2;  // per-phase kernels measured fastest on MI355X
   if (engine == 1) {
     int per_cu = 0;
     if (learned)
@@ -320,18 +325,38 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
     BISIM_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPT), args, lds, st));
   } else {
     int grid = h->grid > 0 ? h->grid : cu * 4;
+    const bool prof = h->profile_every > 0;
+    if (prof && !h->pev) {
+      h->pev = new (std::nothrow) hipEvent_t[8 * 256];
+      if (!h->pev) return BISIM_E_NOMEM;
+      for (int i = 0; i < 8 * 256; ++i) BISIM_TRY_HIP(hipEventCreate(&h->pev[i]));
+      h->pev_slots = 256;
+    }
+    sampled.clear();
+    // one phase kernel, with kernel start/stop events when this iteration is sampled
+    auto go = [&](auto kern, hipEvent_t* e, size_t shm, uint32_t k) {
+      if (e)
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kT), (uint32_t)shm, st, e[0], e[1], 0, a, k);
+      else
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kT), shm, st, a, k);
+    };
     uint32_t k = 0, chunk = 8;
     for (;;) {
       for (uint32_t j = 0; j < chunk; ++j, ++k) {
+        hipEvent_t* e = nullptr;
+        if (prof && k % (uint64_t)h->profile_every == 0 && sampled.size() < (size_t)h->pev_slots) {
+          e = h->pev + 8 * sampled.size();
+          sampled.push_back(k);
+        }
         if (learned) {
-          hipLaunchKernelGGL((k_phase_a<true, true>), dim3(grid), dim3(kT), 0, st, a, k);
-          hipLaunchKernelGGL((k_phase_b<true, true>), dim3(grid), dim3(kT), 0, st, a, k);
-          hipLaunchKernelGGL((k_phase_c<true, true>), dim3(grid), dim3(kT), 0, st, a, k);
-          hipLaunchKernelGGL(k_phase_d, dim3(grid), dim3(kT), lds, st, a, k);
+          go(k_phase_a<true, true>, e, 0, k);
+          go(k_phase_b<true, true>, e ? e + 2 : nullptr, 0, k);
+          go(k_phase_c<true, true>, e ? e + 4 : nullptr, 0, k);
+          go(k_phase_d, e ? e + 6 : nullptr, lds, k);
         } else {
-          hipLaunchKernelGGL((k_phase_a<false, false>), dim3(grid), dim3(kT), 0, st, a, k);
-          hipLaunchKernelGGL((k_phase_b<false, false>), dim3(grid), dim3(kT), 0, st, a, k);
-          hipLaunchKernelGGL((k_phase_c<false, false>), dim3(grid), dim3(kT), 0, st, a, k);
+          go(k_phase_a<false, false>, e, 0, k);
+          go(k_phase_b<false, false>, e ? e + 2 : nullptr, 0, k);
+          go(k_phase_c<false, false>, e ? e + 4 : nullptr, 0, k);
         }
       }
       BISIM_TRY_HIP(hipGetLastError());
@@ -360,6 +385,21 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
     return BISIM_E_DEVICE;
   }
   h->last_iters = c.state.v[0];
+  for (int q = 0; q < 4; ++q) {
+    h->phase_ms[q] = 0;
+    h->phase_cnt[q] = 0;
+  }
+  for (size_t i = 0; i < sampled.size(); ++i) {
+    if ((int64_t)sampled[i] + 1 >= h->last_iters) continue;  // no splitter: early-exit kernels
+    for (int q = 0; q < (learned ? 4 : 3); ++q) {
+      float pm = 0.f;
+      if (hipEventElapsedTime(&pm, h->pev[8 * i + 2 * q], h->pev[8 * i + 2 * q + 1]) ==
+          hipSuccess) {
+        h->phase_ms[q] += pm;
+        h->phase_cnt[q] += 1;
+      }
+    }
+  }
   if (c.state.v[2]) {
     set_error("iteration cap %lld exceeded", (long long)cap);
     return BISIM_E_ITERCAP;

@@ -51,8 +51,13 @@ def test_mixed_batch_tiers(B, wg, lds):
         out, its, st = b.run()
         blocks = b.split(out.numpy())
     check(B, insts, blocks, its)
-    if lds == 1024:
-        assert st["lds_instances"] <= 2  # only empty / one-state instances fit 1 KiB
+    if lds:
+        # LDS bytes an instance needs: 3 bitmaps, 64-bit bids, mark words
+        # (32-bit when every K <= 32), block ids
+        mask = 8 if max(x.K for x in insts) > 32 else 4
+        need = lambda n: 24 * ((n + 63) // 64) + 8 * n + ((mask * n + 7) // 8) * 8 + 4 * n
+        assert st["lds_instances"] == sum(need(x.n) <= lds for x in insts)
+        assert st["global_instances"] == len(insts) - st["lds_instances"] > 0
     assert st["max_iterations"] == its.max() and st["sum_iterations"] == its.sum()
 
 
