@@ -88,6 +88,52 @@ def phase_bytes(n: int, work: np.ndarray, nsplit: np.ndarray):
     return out
 
 
+def method_bytes(n: int, m: int, mark_length: int, work: np.ndarray, nsplit: np.ndarray):
+    """Bytes one iteration of the method as specified moves (Algorithm 3 with
+    int32 ids and byte flags, each pass over all transitions or states), per
+    phase kernel of this implementation:
+      select+mark    select + reset: n/8 unstable bits + L mark zeroing + n
+                     split flags; mark: 4m targets + 4m block[target] gather
+                     + 5 per transition into C
+      compare+elect  4n block + 8n slot offsets + 4n leader offsets + 2L marks
+                     + n split flags
+      relabel        2n split flags + 23 per split state (election and relabel)
+    L is the mark length (section 4.1).  The kernels skip most of this work;
+    the ratio of these bytes to kernel time is therefore the rate at which the
+    method's passes are completed, and can exceed the memory bandwidth."""
+    edges = work[:, 1].astype(np.float64)
+    s = nsplit.astype(np.float64)
+    n, m, L = float(n), float(m), float(mark_length)
+    out = np.stack([np.full_like(s, n / 8 + L + n) + 8 * m + 5 * edges,
+                    np.full_like(s, 17 * n + 2 * L),
+                    2 * n + 23 * s], axis=1)
+    out[-1] = 0.0
+    return out
+
+
+def stored_traffic(kernel: str, workload: str):
+    """Memory traffic per launch measured with rocprofv3 counters (FETCH_SIZE
+    + WRITE_SIZE, calibrated on a plain copy) and kept under profiles/; None
+    when absent or when the kernel sources have changed since."""
+    from paper_2105_11788_amd import profsum
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("#", " ", "|")):
+                key, val = line.split(":", 1)
+                kv[key.strip()] = val.strip()
+    src = os.path.join(ROOT, "paper_2105_11788_amd", "csrc")
+    if kv.get("source_sha1") != profsum.source_digest(src):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(L, target_s: float = 12.0):
     """The lock-step oracle (Algorithm 3 simulation) on a bounded prefix of
     the same workload: time(1 + X iterations) - time(1 iteration)."""
@@ -154,8 +200,9 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
     for w in range(args.warmup):
         _, st = h.run(out)
         log(f"warmup {w}: #It={st.iterations} blocks={st.blocks} t_alg={st.t_alg_ms:.1f} ms")
-    if engine != 1 and st is not None:  # sample ~200 iterations' phase kernels per step
-        h.set_option(bisim.OPT_PROFILE_EVERY, max(1, st.iterations // 200))
+    if engine != 1:  # sample ~200 iterations' phase kernels per step
+        h.set_option(bisim.OPT_PROFILE_EVERY,
+                     max(1, st.iterations // 200) if st is not None else 256)
     bisim.synchronize()
     t0 = time.perf_counter()
     alg_ms = []
@@ -190,25 +237,33 @@ def form_plain(bisim, gen, args):
     st = r["stats"]
     iters = st.iterations
     pb = phase_bytes(L.n, r["work"], r["nsplit"])
+    mb = method_bytes(L.n, L.m, st.mark_length, r["work"], r["nsplit"])
     copy_gbs = bisim.copy_bandwidth(1 << 30)
     names = ["k_phase_a (select+mark)", "k_phase_b (compare+elect)", "k_phase_c (relabel)"]
     if args.engine == 1:
-        kernel, bytes_launch, kern_ms = "k_persistent", float(pb.sum()), r["kern_ms"]
+        kernel, kern_ms = "k_persistent", r["kern_ms"]
+        bytes_launch, touched_launch = float(mb.sum()), float(pb.sum())
         per_phase = None
     else:
         ms = r["phase_ms"][:3]
         q = int(np.argmax(ms))  # every phase runs once per iteration
         kernel = names[q]
-        bytes_launch = float(pb[:-1, q].mean())
+        bytes_launch = float(mb[:-1, q].mean())
+        touched_launch = float(pb[:-1, q].mean())
         kern_ms = float(ms[q])
         per_phase = {names[i]: {"avg_us": float(ms[i] * 1e3),
-                                "bytes_per_launch": float(pb[:-1, i].mean()),
-                                "GBs": float(pb[:-1, i].mean() / (ms[i] * 1e-3) / 1e9)
+                                "method_bytes_per_launch": float(mb[:-1, i].mean()),
+                                "method_GBs": float(mb[:-1, i].mean() / (ms[i] * 1e-3) / 1e9)
+                                if ms[i] > 0 else None,
+                                "touched_bytes_per_launch": float(pb[:-1, i].mean()),
+                                "touched_GBs": float(pb[:-1, i].mean() / (ms[i] * 1e-3) / 1e9)
                                 if ms[i] > 0 else None,
                                 "samples": int(r["phase_samples"][i])} for i in range(3)}
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+    touched_gbs = touched_launch / (kern_ms * 1e-3) / 1e9
     log(f"{r['ms_per_step']:.2f} ms/step, #It={iters}, {kernel}: {kern_ms * 1e3:.2f} us/launch, "
-        f"{achieved:.1f} GB/s algorithmic; copy {copy_gbs:.0f} GB/s")
+        f"method bytes {achieved:.1f} GB/s, touched bytes {touched_gbs:.1f} GB/s; "
+        f"copy {copy_gbs:.0f} GB/s")
     cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
            "iterations": iters, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
            "mark_length": st.mark_length, "form": "plain",
@@ -226,8 +281,12 @@ def form_plain(bisim, gen, args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": stored_traffic(kernel.split(" ")[0], args.workload),
             "bytes_per_launch": bytes_launch,
+            "bytes_definition": "method bytes: each pass of Algorithm 3 over all "
+                                "transitions/states with int32 ids and byte flags",
+            "touched_bytes_per_launch": touched_launch,
+            "touched_GBs": touched_gbs,
             "kernel_ms": kern_ms,
             "measured_copy_GBs": copy_gbs,
             "per_phase": per_phase,

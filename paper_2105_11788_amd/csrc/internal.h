@@ -121,6 +121,7 @@ struct bisim_lts {
   uint64_t* tb = nullptr;    // [ceil(n/64)] touched states
   uint64_t* lt = nullptr;    // [ceil(n/64)] touched leaders
   uint64_t* ub = nullptr;    // [ceil(n/64)] unstable block labels
+  uint64_t* us = nullptr;    // [ceil(n/4096)] summary: bit w set iff ub[w] != 0
   uint64_t* nlw = nullptr;   // [n] (epoch << 32) | ~state, max-reduced
   int32_t* tlist = nullptr;  // [n]
   int32_t* slist = nullptr;  // [n]

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kT) k_phase_a(Args a, uint32_t k) {
   const Part p = part();
   const uint32_t C = head<L>(a, k, p);
   if (C == kNone) return;
-  phase_a_select<L>(a, k & 1, C, p);
+  phase_a_select<L>(a, k & 1, C, k, p);
   phase_a_mark(a, k & 1, C, p);
 }
 template <bool L, bool T>
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(kPT) k_persistent(Args a) {
   for (uint32_t k = 0;; ++k) {
     const uint32_t C = head<L>(a, k, p);
     if (C == kNone) break;
-    phase_a_select<L>(a, k & 1, C, p);
+    phase_a_select<L>(a, k & 1, C, k, p);
     phase_a_mark(a, k & 1, C, p);
     if (!grid_barrier(a.ctl, gen)) break;
     phase_b(a, k & 1, k, p);
@@ -195,6 +195,7 @@ bisim_status refine_alloc(bisim_lts* h) {
   BISIM_TRY(dalloc(&h->tb, nwd, s));
   BISIM_TRY(dalloc(&h->lt, nwd, s));
   BISIM_TRY(dalloc(&h->ub, nwd, s));
+  BISIM_TRY(dalloc(&h->us, (nwd + 63) / 64, s));
   BISIM_TRY(dalloc(&h->nlw, n, s));
   BISIM_TRY(dalloc(&h->tlist, n, s));
   BISIM_TRY(dalloc(&h->slist, n, s));
@@ -228,6 +229,7 @@ Args make_args(bisim_lts* h, uint32_t cap, bool learned, bool track) {
   a.tb = h->tb;
   a.lt = h->lt;
   a.ub = h->ub;
+  a.us = h->us;
   a.nlw = h->nlw;
   a.tlist = h->tlist;
   a.slist = h->slist;
@@ -257,6 +259,7 @@ bisim_status refine_init(bisim_lts* h, const Args& a, uint32_t first, bool learn
   g = g > grid_cap(cu) ? grid_cap(cu) : (g < 1 ? 1 : g);
   hipLaunchKernelGGL(k_init_run, dim3((unsigned)g), dim3(kT), 0, st, a, h->pre_block, first,
                      h->nwords, learned ? 1u : 0u);
+  hipLaunchKernelGGL(k_init_summary, dim3((unsigned)g), dim3(kT), 0, st, a);
   BISIM_TRY_HIP(hipGetLastError());
   if (track || learned) {
     hipLaunchKernelGGL(k_zero_features, dim3((unsigned)g), dim3(kT), 0, st, a);
@@ -306,6 +309,7 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   const int cu = h->num_cu > 0 ? h->num_cu : 1;
   const size_t lds = learned ? mlp_lds_floats(kPolicyF) * sizeof(float) : 0;
   std::vector<uint32_t> sampled;
+  std::vector<hipEvent_t> sample_start;
   int engine = h->engine;
   if (engine == 0) engine = 2;  // per-phase kernels measured fastest on MI355X
   if (engine == 1) {
@@ -324,7 +328,7 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
     const void* fn = learned ? (const void*)k_persistent<true> : (const void*)k_persistent<false>;
     BISIM_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPT), args, lds, st));
   } else {
-    int grid = h->grid > 0 ? h->grid : cu * 4;
+    int grid = h->grid > 0 ? h->grid : cu * 8;  // 2048 workgroups on MI355X: best of a 128..2048 sweep
     const bool prof = h->profile_every > 0;
     if (prof && !h->pev) {
       h->pev = new (std::nothrow) hipEvent_t[8 * 256];
@@ -333,30 +337,45 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
       h->pev_slots = 256;
     }
     sampled.clear();
-    // one phase kernel, with kernel start/stop events when this iteration is sampled
-    auto go = [&](auto kern, hipEvent_t* e, size_t shm, uint32_t k) {
-      if (e)
-        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kT), (uint32_t)shm, st, e[0], e[1], 0, a, k);
+    sample_start.clear();
+    // Sampled iterations bind an event to the end of each phase kernel (and of
+    // the previous iteration's last kernel).  Kernels of one stream run back to
+    // back, so a phase's duration is the distance between consecutive ends; no
+    // start marker is put between the kernels.
+    auto go = [&](auto kern, hipEvent_t stop, size_t shm, uint32_t k) {
+      if (stop)
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kT), (uint32_t)shm, st, nullptr, stop, 0, a, k);
       else
         hipLaunchKernelGGL(kern, dim3(grid), dim3(kT), shm, st, a, k);
     };
+    const int nph = learned ? 4 : 3;
+    const uint64_t pe = prof ? (uint64_t)h->profile_every : 0;
+    hipEvent_t carry = nullptr;  // end of the previous iteration, if the current one is sampled
     uint32_t k = 0, chunk = 8;
     for (;;) {
       for (uint32_t j = 0; j < chunk; ++j, ++k) {
-        hipEvent_t* e = nullptr;
-        if (prof && k % (uint64_t)h->profile_every == 0 && sampled.size() < (size_t)h->pev_slots) {
-          e = h->pev + 8 * sampled.size();
+        hipEvent_t ends[4] = {nullptr, nullptr, nullptr, nullptr};
+        const size_t slot = sampled.size();
+        const bool samp = prof && carry && slot < (size_t)h->pev_slots;
+        if (samp) {
+          for (int q = 0; q < nph; ++q) ends[q] = h->pev[8 * slot + 1 + q];
           sampled.push_back(k);
+          sample_start.push_back(carry);
+        }
+        carry = nullptr;
+        if (prof && (k + 1) % pe == 0 && sampled.size() < (size_t)h->pev_slots) {
+          if (!ends[nph - 1]) ends[nph - 1] = h->pev[8 * sampled.size()];
+          carry = ends[nph - 1];
         }
         if (learned) {
-          go(k_phase_a<true, true>, e, 0, k);
-          go(k_phase_b<true, true>, e ? e + 2 : nullptr, 0, k);
-          go(k_phase_c<true, true>, e ? e + 4 : nullptr, 0, k);
-          go(k_phase_d, e ? e + 6 : nullptr, lds, k);
+          go(k_phase_a<true, true>, ends[0], 0, k);
+          go(k_phase_b<true, true>, ends[1], 0, k);
+          go(k_phase_c<true, true>, ends[2], 0, k);
+          go(k_phase_d, ends[3], lds, k);
         } else {
-          go(k_phase_a<false, false>, e, 0, k);
-          go(k_phase_b<false, false>, e ? e + 2 : nullptr, 0, k);
-          go(k_phase_c<false, false>, e ? e + 4 : nullptr, 0, k);
+          go(k_phase_a<false, false>, ends[0], 0, k);
+          go(k_phase_b<false, false>, ends[1], 0, k);
+          go(k_phase_c<false, false>, ends[2], 0, k);
         }
       }
       BISIM_TRY_HIP(hipGetLastError());
@@ -391,13 +410,15 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   }
   for (size_t i = 0; i < sampled.size(); ++i) {
     if ((int64_t)sampled[i] + 1 >= h->last_iters) continue;  // no splitter: early-exit kernels
+    hipEvent_t prev = sample_start[i];
     for (int q = 0; q < (learned ? 4 : 3); ++q) {
+      hipEvent_t cur = h->pev[8 * i + 1 + q];
       float pm = 0.f;
-      if (hipEventElapsedTime(&pm, h->pev[8 * i + 2 * q], h->pev[8 * i + 2 * q + 1]) ==
-          hipSuccess) {
+      if (hipEventElapsedTime(&pm, prev, cur) == hipSuccess) {
         h->phase_ms[q] += pm;
         h->phase_cnt[q] += 1;
       }
+      prev = cur;
     }
   }
   if (c.state.v[2]) {

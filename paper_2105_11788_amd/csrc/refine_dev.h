@@ -22,6 +22,7 @@ struct Args {
   uint64_t* tb;
   uint64_t* lt;
   uint64_t* ub;
+  uint64_t* us;  // summary: bit w set iff ub[w] != 0
   uint64_t* nlw;
   int32_t* tlist;
   int32_t* slist;
@@ -123,22 +124,55 @@ __device__ uint32_t head(const Args& a, uint32_t k, const Part& p) {
   return (C == kNone || over) ? kNone : C;
 }
 
-// A: clear C, reduce the other unstable labels into next iteration's candidate
+// set / clear an unstable label, keeping the summary level (one bit per
+// non-zero word of ub) exact
+__device__ __forceinline__ void unstable_set(const Args& a, uint32_t b) {
+  const uint32_t w = b >> 6;
+  const uint64_t old = atomicOr((unsigned long long*)&a.ub[w], 1ull << (b & 63));
+  if (old == 0) atomicOr((unsigned long long*)&a.us[w >> 6], 1ull << (w & 63));
+}
+
+// A: clear C and find the next iteration's candidate.  Plain policy: C is
+// the smallest unstable label, so the smallest remaining one is the next set
+// bit after C; one wave finds it through the summary level.  Labels made
+// unstable later in this iteration are min-reduced into the candidate in C.
 template <bool L>
-__device__ void phase_a_select(const Args& a, uint32_t par, uint32_t C, const Part& p) {
+__device__ void phase_a_select(const Args& a, uint32_t par, uint32_t C, uint32_t k,
+                               const Part& p) {
   const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
   if (!L) {
-    uint32_t best = kNone;
-    for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
-      uint64_t bits = a.ub[w];
-      if (w == (C >> 6)) {
-        bits &= ~(1ull << (C & 63));
-        a.ub[w] = bits;
-      }
-      if (bits) best = min(best, (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1));
+    if (p.gwave != 0) return;
+    const uint32_t w0 = C >> 6;
+    const uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
+    if (lane() == 0) {
+      a.ub[w0] = bits;
+      if (bits == 0) atomicAnd((unsigned long long*)&a.us[w0 >> 6], ~(1ull << (w0 & 63)));
     }
-    best = wave_min_u32(best);
-    if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
+    // Labels below C are stable, except in the first iteration, where the
+    // splitter may have been forced: search from word 0 there.  Word w0 is
+    // taken from `bits` (this wave's own update may not be visible yet).
+    const uint32_t from = (k == 0) ? 0u : w0;
+    const uint32_t nsw = (nwd + 63u) >> 6;
+    uint32_t next = kNone;
+    for (uint32_t q = from >> 6; q < nsw; q += kWave) {
+      const uint32_t qq = q + lane();
+      uint64_t sv = qq < nsw ? a.us[qq] : 0ull;
+      if (qq == (from >> 6)) sv &= ~0ull << (from & 63);
+      if (qq == (w0 >> 6)) {
+        const uint64_t b0 = 1ull << (w0 & 63);
+        sv = bits ? (sv | b0) : (sv & ~b0);
+      }
+      const uint64_t bal = __ballot(sv != 0);
+      if (bal) {
+        const int l = __ffsll((unsigned long long)bal) - 1;
+        const uint64_t v = (uint64_t)__shfl((unsigned long long)sv, l, kWave);
+        const uint32_t word = ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)v) - 1);
+        const uint64_t wb = (word == w0) ? bits : a.ub[word];
+        if (wb) next = (word << 6) + (uint32_t)(__ffsll((unsigned long long)wb) - 1);
+        break;
+      }
+    }
+    if (lane() == 0 && next != kNone) a.ctl->cand[par ^ 1].v[0] = next;
   } else {
     uint64_t best = 0;
     for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
@@ -146,6 +180,7 @@ __device__ void phase_a_select(const Args& a, uint32_t par, uint32_t C, const Pa
       if (w == (C >> 6)) {
         bits &= ~(1ull << (C & 63));
         a.ub[w] = bits;
+        if (bits == 0) atomicAnd((unsigned long long*)&a.us[w >> 6], ~(1ull << (w & 63)));
       }
       while (bits) {
         const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
@@ -305,8 +340,8 @@ __device__ void phase_c(const Args& a, uint32_t par, uint32_t k, uint32_t C, con
         }
       }
       if (lead) {
-        atomicOr((unsigned long long*)&a.ub[old >> 6], 1ull << (old & 63));
-        atomicOr((unsigned long long*)&a.ub[nl >> 6], 1ull << (nl & 63));
+        unstable_set(a, (uint32_t)old);
+        unstable_set(a, (uint32_t)nl);
         best = min(best, (uint32_t)old);
         if (T) {
           a.born[old] = k + 1;
@@ -344,7 +379,7 @@ __device__ void phase_c(const Args& a, uint32_t par, uint32_t k, uint32_t C, con
     if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
   }
   if (p.gtid == 0) {
-    if (nS > 0) atomicOr((unsigned long long*)&a.ub[C >> 6], 1ull << (C & 63));
+    if (nS > 0) unstable_set(a, C);
     if (!L) {
       if (nS > 0) atomicMin(&a.ctl->cand[par ^ 1].v[0], C);
       a.ctl->cand[par].v[0] = kNone;
@@ -420,6 +455,19 @@ __global__ void k_init_run(Args a, const int32_t* __restrict__ pre, uint32_t fir
       a.ctl->cand[0].v[0] = (n == 0 || learned) ? kNone : first;
       a.ctl->cand[1].v[0] = kNone;
     }
+  }
+}
+
+// summary level of the unstable bitmap (after k_init_run has written ub)
+__global__ void k_init_summary(Args a) {
+  const Part p = part();
+  const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
+  const uint32_t nsw = (nwd + 63u) >> 6;
+  for (uint32_t q = p.gtid; q < nsw; q += p.gthreads) {
+    uint64_t bits = 0;
+    for (uint32_t j = 0; j < 64 && (q << 6) + j < nwd; ++j)
+      if (a.ub[(q << 6) + j]) bits |= 1ull << j;
+    a.us[q] = bits;
   }
 }
 
