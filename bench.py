@@ -304,8 +304,12 @@ def form_batched(bisim, gen, args):
     N = sum(x.n for x in insts)
     M = sum(x.m for x in insts)
     log(f"batch: {len(insts)} instances, sum n={N} sum m={M} ({time.perf_counter() - t:.1f}s)")
+    t = time.perf_counter()
     b = bisim.Batch(insts)
+    if args.batch_wg:  # fixed configuration instead of the autotuner
+        b.set_option(bisim.BOPT_WG_SIZE, args.batch_wg)
     out = bisim.DeviceArray(b.N, np.int32)
+    log(f"batch loaded and preprocessed ({time.perf_counter() - t:.1f}s)")
     for w in range(args.warmup):
         _, its, st = b.run(out)
         log(f"warmup {w}: max #It={st['max_iterations']} t_alg={st['t_alg_ms']:.1f} ms "
@@ -337,6 +341,7 @@ def form_batched(bisim, gen, args):
             t_s += time.perf_counter() - t1
             it_s += s1.iterations
             assert s1.iterations == its[int(k)]
+        log(f"plain instance {int(k)}: n={L.n} #It={s1.iterations}")
     scale = float(its.sum()) / max(it_s, 1)
     plain_est_ms = t_s * 1000.0 * scale
     log(f"batched {ms:.1f} ms; plain one-by-one estimate {plain_est_ms:.0f} ms "
@@ -401,6 +406,8 @@ def main():
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--n-hi", type=int, default=10_000)
     ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--batch-wg", type=int, default=0,
+                    help="batched form: fixed workgroup size instead of the autotuner")
     ap.add_argument("--rescore", type=int, default=64)
     ap.add_argument("--train-lts", type=int, default=12)
     ap.add_argument("--train-steps", type=int, default=300)

@@ -133,7 +133,9 @@ const char* bisim_last_error(void);
 #define BISIM_OPT_GRID 4
 #define BISIM_OPT_PROFILE_EVERY 5 /* 0 (default) or P: with the per-phase engine, time the
                                      phase kernels of every P-th iteration (at most 256
-                                     iterations per run) with kernel start/stop events */
+                                     iterations per run) with events bound to the end of
+                                     each kernel; a phase's time is the distance between
+                                     the ends of consecutive kernels of the stream */
 bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
 
 /*
@@ -253,18 +255,22 @@ bisim_status bisim_batch_set_option(bisim_batch* b, int32_t option, int64_t valu
  * concurrent write of section 3.2 may be won by any block; Theorem 1 and the
  * labelled argument of section 4.2 do not depend on it), so the splitter
  * order can be chosen to cut the iteration count without changing the
- * result.  The learned policy picks C = the unstable block with the highest
- * score (ties: the smallest label), where the score is a small network
+ * result.  The learned policy scores each unstable block with a small network
  *     y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3,   hidden width 64,
- * evaluated on per-block features x (18 values, each log1p-scaled):
+ * (trained to predict log(1 + number of blocks the splitter would split)),
+ * quantises the score into 16 priority levels, floor(3y) clamped to 0..15,
+ * and picks C = the smallest label of the highest non-empty level.  Features
+ * x (19 values; the first 18 log1p-scaled):
  *     x[0]      block size
  *     x[1..8]   outgoing transitions of the members, by label mod 8
  *     x[9..16]  incoming transitions of the members, by label mod 8
- *     x[17]     iterations since the block was created or last split.
+ *     x[17]     iterations since the block was created or last split
+ *     x[18]     1 if the block has been the splitter since it was created or
+ *               last split, else 0.
  * Parameters are fp32 masters with bf16 copies used by the forward pass
- * (inputs also rounded to bf16, fp32 accumulation).  Scores are refreshed for
- * every block created or split in an iteration, and for all unstable blocks
- * every R iterations.
+ * (inputs also rounded to bf16, fp32 accumulation).  Levels are refreshed for
+ * both blocks of every split and for the splitter in each iteration, and for
+ * all unstable blocks every R iterations.
  */
 typedef struct bisim_mlp bisim_mlp;
 
@@ -309,7 +315,7 @@ bisim_status mlp_train_step(bisim_mlp* w, const float* x, const float* target, i
 
 /*
  * bisim_set_splitter_policy — 0: the smallest unstable label (default);
- * 1: the learned score (`w` must have 18 inputs and outlive the handle's
+ * 1: the learned score (`w` must have 19 inputs and outlive the handle's
  * runs).  rescore_every: full re-scoring period R (>= 1).
  * Errors: BISIM_E_INVALID.
  */
@@ -319,10 +325,10 @@ bisim_status bisim_set_splitter_policy(bisim_lts* h, int32_t policy, const bisim
 /*
  * bisim_collect_training — run the plain policy to the fixpoint and, before
  * every `sample_every`-th iteration, evaluate up to `max_cands` unstable
- * blocks (evenly spaced in label order): their 18 features (as above) and
+ * blocks (evenly spaced in label order): their 19 features (as above) and
  * the counterfactual target log(1 + number of blocks that would split if
  * that block were the splitter now).
- *   feat device fp32 [cap][18]; target device fp32 [cap];
+ *   feat device fp32 [cap][19]; target device fp32 [cap];
  *   meta device int32 [cap][2], nullable: (iteration, block label) per row;
  *   rows host: rows written (<= cap).
  * Supports states with at most 64 distinct outgoing actions and

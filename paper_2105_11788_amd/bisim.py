@@ -400,7 +400,7 @@ class Batch:
 
 POLICY_PLAIN = 0
 POLICY_LEARNED = 1
-POLICY_FEATURES = 18
+POLICY_FEATURES = 19
 
 
 def _declare_learned(L):
@@ -507,7 +507,7 @@ def set_splitter_policy(lts: "LTS", policy: int, mlp: Optional[MLP] = None,
 
 def collect_training(lts: "LTS", sample_every: int = 1, max_cands: int = 64, cap: int = 100_000):
     """Plain run with sampled (features, counterfactual target) rows.
-    Returns (feat [rows, 18], target [rows], meta [rows, 2] = (iteration, block))."""
+    Returns (feat [rows, 19], target [rows], meta [rows, 2] = (iteration, block))."""
     L = load_library()
     _declare_learned(L)
     f = DeviceArray(cap * POLICY_FEATURES, np.float32)

@@ -22,7 +22,8 @@ static void free_handle(bisim_lts* h) {
   void* ptrs[] = {h->pre_block, h->nr_marks, h->in_ptr, h->in_src, h->in_ord, h->woff,
                   h->block,     h->mw,       h->tb,     h->lt,     h->ub,     h->nlw,
                   h->tlist,     h->slist,    h->ctl,    h->sfeat,  h->acc,    h->born,
-                  h->score,     h->chg,      h->us};
+                  h->used,      h->chg,      h->us,     h->lvl,    h->lvb,    h->lvs,
+                  h->lvt,       h->lvq};
   for (void* p : ptrs)
     if (p) (void)hipFreeAsync(p, s);
   (void)hipStreamSynchronize(s);

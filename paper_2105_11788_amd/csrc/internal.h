@@ -46,9 +46,9 @@ struct Ctl {
   Line cntS[2];   // v[0]: split-state list length
   Line ltany[2];  // v[0]: some block leader was touched
   Line work[2];   // traced runs only: v[0] members of C, v[1] in-transitions of C
-  Line key[2];    // learned policy: v[0..1] = 64-bit (score, ~label) key, max-reduced
   Line cntC[2];   // learned policy: changed (old, new) block pairs this iteration
-  Line state;     // v[0] iterations done, v[1] done flag, v[2] error, v[3] current splitter
+  Line state;     // v[0] iterations done, v[1] done flag, v[2] iteration cap hit,
+                  // v[3] current splitter, v[4] learned priority structure inconsistent
   Line bar;       // v[0] group arrivals, v[1] generation, v[2] abort
   Line barg[8];   // v[0]: arrivals within workgroup group g (blockIdx % 8)
 };
@@ -142,8 +142,13 @@ struct bisim_lts {
   uint32_t* sfeat = nullptr;  // [n][16] out/in transitions of each state by label mod 8
   uint32_t* acc = nullptr;    // [n][17] per block label: size, out[8], in[8]
   uint32_t* born = nullptr;   // [n] iteration the block was created / last split
-  float* score = nullptr;     // [n]
+  uint32_t* used = nullptr;   // [n] iteration the block was last the splitter
   int32_t* chg = nullptr;     // [2n] (old, new) label pairs of this iteration's splits
+  uint8_t* lvl = nullptr;     // [n] priority level of each unstable label (learned policy)
+  uint64_t* lvb = nullptr;    // [16][ceil(n/64)] unstable labels by level
+  uint64_t* lvs = nullptr;    // [16][ceil(n/4096)] non-empty words of lvb
+  uint64_t* lvt = nullptr;    // [16][ceil(n/262144)] non-empty words of lvs
+  uint8_t* lvq = nullptr;     // [2n+1] scratch of the re-scoring step
   int policy = 0;
   const uint16_t* policy_w = nullptr;  // bf16 network parameters (18 inputs)
   int rescore_every = 64;

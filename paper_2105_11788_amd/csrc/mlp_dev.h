@@ -11,7 +11,7 @@ namespace bisim {
 
 constexpr int kMlpH = 64;     // hidden width (= wave size: lane j is unit j)
 constexpr int kMlpMaxF = 32;  // largest supported input width
-constexpr int kPolicyF = 18;  // block features used by the learned splitter
+constexpr int kPolicyF = 19;  // block features used by the learned splitter
 
 // flat parameter layout: W1 [H][F], b1 [H], W2 [H][H], b2 [H], w3 [H], b3 [1]
 struct MlpOffsets {
@@ -116,15 +116,13 @@ __device__ __forceinline__ float mlp_row_forward(const MlpLds& L, int F, const f
   return mlp_forward_lanes(L, F, xl, z1o, z2o);
 }
 
-// Orderable key of a score: larger score -> larger key; ties broken towards the
-// smaller block label.  Key 0 means "no candidate".
-__device__ __forceinline__ uint64_t score_key(float score, uint32_t label) {
-  uint32_t u = __float_as_uint(score);
-  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-  return ((uint64_t)u << 32) | (uint64_t)(0xFFFFFFFFu - label);
-}
-__device__ __forceinline__ uint32_t key_label(uint64_t key) {
-  return 0xFFFFFFFFu - (uint32_t)key;
+// Priority level of a predicted log(1 + blocks split): 16 levels of width 1/3.
+// The learned policy takes the smallest label of the highest non-empty level.
+constexpr int kLevels = 16;
+__device__ __forceinline__ uint32_t score_level(float y) {
+  const float q = floorf(y * 3.0f);
+  if (!(q > 0.f)) return 0u;  // also NaN
+  return q >= (float)(kLevels - 1) ? (uint32_t)(kLevels - 1) : (uint32_t)q;
 }
 
 }  // namespace bisim

@@ -5,14 +5,15 @@
 //
 //   A  select + mark    C is the unstable block chosen by the policy (plain:
 //                       the smallest label, the priority-CRCW reading of the
-//                       concurrent write; learned: the highest score).  Clear
-//                       C's unstable bit; reduce the remaining unstable labels
-//                       into the next iteration's candidate; for every state t
-//                       with block[t] == C visit t's in-transitions (source s,
-//                       action rank o) and set mark slot o of s.  The first
-//                       touch of a state appends it to the touched list T; a
-//                       touched leader sets its bit in the leader-touched
-//                       bitmap.
+//                       concurrent write; learned: the smallest label of the
+//                       highest priority level).  Clear C's unstable bit; for
+//                       the plain policy, find the next smallest unstable
+//                       label for the next iteration's candidate; for every
+//                       state t with block[t] == C visit t's in-transitions
+//                       (source s, action rank o) and set mark slot o of s.
+//                       The first touch of a state appends it to the touched
+//                       list T; a touched leader sets its bit in the
+//                       leader-touched bitmap.
 //   B  compare + elect  A state splits iff its marks differ from its
 //                       leader's.  Only two kinds of state can differ:
 //                       touched states (compared word by word), and untouched
@@ -26,9 +27,10 @@
 //                       C is re-marked unstable if anything split.  New
 //                       unstable labels are reduced into the candidate.
 //                       Marks and touched bits of T are cleared.
-//   D  (learned policy) re-score the blocks created or split in C (and all
-//                       unstable blocks every R iterations) with the network,
-//                       and fold their keys into the candidate.
+//   S  (learned policy, one workgroup) re-score the blocks created or split
+//                       in C and C itself with the network, move them between
+//                       priority levels, and pick the next splitter.  Every R
+//                       iterations all unstable blocks are re-scored first.
 //
 // Marks: each state's slots (one per distinct outgoing action, section 4.1)
 // are bits of 64-bit words; with <= 64 actions per state the word index is
@@ -64,7 +66,7 @@ template <bool L, bool T>
 __global__ void __launch_bounds__(kT) k_phase_a(Args a, uint32_t k) {
   if (a.ctl->state.v[1]) return;
   const Part p = part();
-  const uint32_t C = head<L>(a, k, p);
+  const uint32_t C = head(a, k, p);
   if (C == kNone) return;
   phase_a_select<L>(a, k & 1, C, k, p);
   phase_a_mark(a, k & 1, C, p);
@@ -79,13 +81,26 @@ __global__ void __launch_bounds__(kT) k_phase_c(Args a, uint32_t k) {
   if (a.ctl->state.v[1]) return;
   phase_c<L, T>(a, k & 1, k, a.ctl->state.v[3], part());
 }
-__global__ void __launch_bounds__(kT) k_phase_d(Args a, uint32_t k) {
+constexpr int kST = 1024;  // re-scoring + selection workgroup (learned policy)
+__global__ void __launch_bounds__(kST) k_phase_s(Args a, uint32_t k) {
   if (a.ctl->state.v[1]) return;
   extern __shared__ float sw[];
   MlpLds M = mlp_lds_layout(sw, kPolicyF);
   mlp_stage(M, a.wbf, kPolicyF);
   __syncthreads();
-  phase_d(a, M, k & 1, k, part());
+  phase_s(a, M, k & 1, k);
+}
+__global__ void __launch_bounds__(kT) k_phase_f1(Args a, uint32_t k) {
+  if (a.ctl->state.v[1]) return;
+  extern __shared__ float sw[];
+  MlpLds M = mlp_lds_layout(sw, kPolicyF);
+  mlp_stage(M, a.wbf, kPolicyF);
+  __syncthreads();
+  phase_f1(a, M, k + 1, part());
+}
+__global__ void __launch_bounds__(kT) k_phase_f2(Args a, uint32_t k) {
+  if (a.ctl->state.v[1]) return;
+  phase_f2(a, part());
 }
 
 // ---------------------------------------------------------------------------
@@ -155,7 +170,7 @@ __global__ void __launch_bounds__(kPT) k_persistent(Args a) {
   const Part p = part();
   uint32_t gen = 0;
   for (uint32_t k = 0;; ++k) {
-    const uint32_t C = head<L>(a, k, p);
+    const uint32_t C = head(a, k, p);
     if (C == kNone) break;
     phase_a_select<L>(a, k & 1, C, k, p);
     phase_a_mark(a, k & 1, C, p);
@@ -165,7 +180,13 @@ __global__ void __launch_bounds__(kPT) k_persistent(Args a) {
     phase_c<L, L>(a, k & 1, k, C, p);
     if (!grid_barrier(a.ctl, gen)) break;
     if (L) {
-      phase_d(a, M, k & 1, k, p);
+      if (a.rescore && (k + 1) % a.rescore == 0) {
+        phase_f1(a, M, k + 1, p);
+        if (!grid_barrier(a.ctl, gen)) break;
+        phase_f2(a, p);
+        if (!grid_barrier(a.ctl, gen)) break;
+      }
+      if (blockIdx.x == 0) phase_s(a, M, k & 1, k);
       if (!grid_barrier(a.ctl, gen)) break;
     }
   }
@@ -209,10 +230,16 @@ bisim_status refine_alloc_features(bisim_lts* h) {
   if (h->acc) return BISIM_OK;
   const size_t n = (size_t)h->n;
   hipStream_t s = h->stream;
+  const size_t nwd = (n + 63) / 64, nsw = (nwd + 63) / 64, ntw = (nsw + 63) / 64;
   BISIM_TRY(dalloc(&h->acc, 17 * n, s));
   BISIM_TRY(dalloc(&h->born, n, s));
-  BISIM_TRY(dalloc(&h->score, n, s));
+  BISIM_TRY(dalloc(&h->used, n, s));
   BISIM_TRY(dalloc(&h->chg, 2 * n, s));
+  BISIM_TRY(dalloc(&h->lvl, n, s));
+  BISIM_TRY(dalloc(&h->lvb, kLevels * nwd, s));
+  BISIM_TRY(dalloc(&h->lvs, kLevels * nsw, s));
+  BISIM_TRY(dalloc(&h->lvt, kLevels * ntw, s));
+  BISIM_TRY(dalloc(&h->lvq, 2 * n + 1, s));
   return BISIM_OK;
 }
 
@@ -243,8 +270,15 @@ Args make_args(bisim_lts* h, uint32_t cap, bool learned, bool track) {
     a.sfeat = h->sfeat;
     a.acc = h->acc;
     a.born = h->born;
-    a.score = h->score;
+    a.used = h->used;
     a.chg = h->chg;
+  }
+  if (learned) {
+    a.lvl = h->lvl;
+    a.lvb = h->lvb;
+    a.lvs = h->lvs;
+    a.lvt = h->lvt;
+    a.lvq = h->lvq;
   }
   a.wbf = learned ? h->policy_w : nullptr;
   a.rescore = (uint32_t)(h->rescore_every > 0 ? h->rescore_every : 64);
@@ -268,8 +302,10 @@ bisim_status refine_init(bisim_lts* h, const Args& a, uint32_t first, bool learn
     BISIM_TRY_HIP(hipGetLastError());
   }
   if (learned) {
-    hipLaunchKernelGGL(k_init_scores, dim3((unsigned)g), dim3(kT),
-                       mlp_lds_floats(kPolicyF) * sizeof(float), st, a, h->pre_block);
+    hipLaunchKernelGGL(k_levels_all, dim3((unsigned)g), dim3(kT),
+                       mlp_lds_floats(kPolicyF) * sizeof(float), st, a, 0u);
+    hipLaunchKernelGGL(k_levels_insert, dim3((unsigned)g), dim3(kT), 0, st, a);
+    hipLaunchKernelGGL(k_learned_first, dim3(1), dim3(kWave), 0, st, a);
     BISIM_TRY_HIP(hipGetLastError());
   }
   return BISIM_OK;
@@ -371,7 +407,15 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
           go(k_phase_a<true, true>, ends[0], 0, k);
           go(k_phase_b<true, true>, ends[1], 0, k);
           go(k_phase_c<true, true>, ends[2], 0, k);
-          go(k_phase_d, ends[3], lds, k);
+          if (a.rescore && (k + 1) % a.rescore == 0) {
+            go(k_phase_f1, nullptr, lds, k);
+            go(k_phase_f2, nullptr, 0, k);
+          }
+          if (ends[3])
+            hipExtLaunchKernelGGL(k_phase_s, dim3(1), dim3(kST), (uint32_t)lds, st, nullptr,
+                                  ends[3], 0, a, k);
+          else
+            hipLaunchKernelGGL(k_phase_s, dim3(1), dim3(kST), lds, st, a, k);
         } else {
           go(k_phase_a<false, false>, ends[0], 0, k);
           go(k_phase_b<false, false>, ends[1], 0, k);
@@ -397,6 +441,10 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   const Ctl& c = *h->ctl_host;
   if (c.bar.v[2]) {
     set_error("grid barrier timed out");
+    return BISIM_E_DEVICE;
+  }
+  if (c.state.v[4]) {
+    set_error("learned splitter policy: priority structure inconsistent");
     return BISIM_E_DEVICE;
   }
   if (!c.state.v[1]) {
@@ -551,7 +599,7 @@ bisim_status bisim_set_splitter_policy(bisim_lts* h, int32_t policy, const bisim
                                        int32_t rescore_every) {
   if (!h || (policy != 0 && policy != 1) || rescore_every < 1 ||
       (policy == 1 && (!w || mlp_features(w) != kPolicyF))) {
-    set_error("bisim_set_splitter_policy: policy 0 or 1, rescore_every >= 1, and an 18-input "
+    set_error("bisim_set_splitter_policy: policy 0 or 1, rescore_every >= 1, and a 19-input "
               "network for policy 1");
     return BISIM_E_INVALID;
   }

@@ -35,11 +35,18 @@ struct Args {
   // block features and the learned policy
   const uint32_t* sfeat;  // [n][16]
   uint32_t* acc;          // [n][17]
-  uint32_t* born;         // [n]
-  float* score;           // [n]
-  int32_t* chg;           // [2n]
+  uint32_t* born;         // [n] iterations completed when the block was created / last split
+  uint32_t* used;         // [n] iterations completed when the block was last the splitter
+  int32_t* chg;           // [2n] (old, new) label pairs of this iteration's splits
   const uint16_t* wbf;    // bf16 network parameters
   uint32_t rescore;       // full re-scoring period
+  // learned policy: unstable labels by priority level, three bitmap levels
+  // each (labels; words; summary words), kept exact
+  uint8_t* lvl;   // [n] level of each label in the structure
+  uint64_t* lvb;  // [kLevels][nwd]
+  uint64_t* lvs;  // [kLevels][nsw]
+  uint64_t* lvt;  // [kLevels][ntw]
+  uint8_t* lvq;   // [2n+1] scratch: new level per re-scored entry
 };
 
 struct Part {
@@ -52,10 +59,6 @@ __device__ __forceinline__ Part part() {
   return {gtid, gthreads, gtid / kWave, gthreads / kWave};
 }
 
-__device__ __forceinline__ uint64_t* key_ptr(Ctl* c, uint32_t par) {
-  return reinterpret_cast<uint64_t*>(&c->key[par].v[0]);
-}
-
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
@@ -65,39 +68,104 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
-// Block features (log1p-scaled): size, outgoing and incoming transitions of
-// the members by label mod 8, iterations since the block was created or last
-// split (kcur = number of iterations completed).
+// Block features: size, outgoing and incoming transitions of the members by
+// label mod 8, iterations since the block was created or last split (all
+// log1p-scaled), and whether the block has been the splitter since it was
+// created or last split (0/1).  kcur = number of iterations completed.
 __device__ __forceinline__ float block_feature(const Args& a, uint32_t b, uint32_t f,
                                                uint32_t kcur) {
   if (f < 17) return log1pf((float)a.acc[(size_t)b * 17 + f]);
   if (f == 17) return log1pf((float)(kcur - a.born[b]));
+  if (f == 18) return a.used[b] > a.born[b] ? 1.f : 0.f;
   return 0.f;
 }
 
-// one wave scores block b and folds its key into *key
-__device__ __forceinline__ void score_block(const Args& a, const MlpLds& M, uint32_t b,
-                                            uint32_t kcur, uint64_t* key) {
+// one wave: priority level of block b (wave-uniform)
+__device__ __forceinline__ uint32_t block_level(const Args& a, const MlpLds& M, uint32_t b,
+                                                uint32_t kcur) {
   const float x = block_feature(a, b, lane(), kcur);
   float z1, z2;
-  const float y = mlp_forward_lanes(M, kPolicyF, x, &z1, &z2);
-  if (lane() == 0) {
-    a.score[b] = y;
-    atomicMax((unsigned long long*)key, (unsigned long long)score_key(y, b));
+  return score_level(mlp_forward_lanes(M, kPolicyF, x, &z1, &z2));
+}
+
+// ---- the level structure of the learned policy ----------------------------
+struct LvDims {
+  uint32_t nwd, nsw, ntw;
+};
+__device__ __forceinline__ LvDims lv_dims(const Args& a) {
+  const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
+  const uint32_t nsw = (nwd + 63u) >> 6;
+  return {nwd, nsw, (nsw + 63u) >> 6};
+}
+__device__ __forceinline__ uint64_t aload(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Insert label b at level L.  Safe against concurrent insertions.
+__device__ __forceinline__ void lv_insert(const Args& a, uint32_t b, uint32_t L) {
+  const LvDims d = lv_dims(a);
+  const uint32_t w = b >> 6, sw = w >> 6;
+  const uint64_t o1 = atomicOr((unsigned long long*)&a.lvb[(size_t)L * d.nwd + w], 1ull << (b & 63));
+  if (o1 != 0) return;
+  const uint64_t o2 = atomicOr((unsigned long long*)&a.lvs[(size_t)L * d.nsw + sw], 1ull << (w & 63));
+  if (o2 != 0) return;
+  atomicOr((unsigned long long*)&a.lvt[(size_t)L * d.ntw + (sw >> 6)], 1ull << (sw & 63));
+}
+// Remove label b from level L (no-op if absent).  Safe against concurrent
+// removals; must not run concurrently with insertions.
+__device__ __forceinline__ void lv_remove(const Args& a, uint32_t b, uint32_t L) {
+  const LvDims d = lv_dims(a);
+  const uint32_t w = b >> 6, sw = w >> 6;
+  const uint64_t bit = 1ull << (b & 63), sbit = 1ull << (w & 63);
+  const uint64_t o1 = atomicAnd((unsigned long long*)&a.lvb[(size_t)L * d.nwd + w], ~bit);
+  if (!(o1 & bit) || (o1 & ~bit)) return;
+  const uint64_t o2 = atomicAnd((unsigned long long*)&a.lvs[(size_t)L * d.nsw + sw], ~sbit);
+  if (!(o2 & sbit) || (o2 & ~sbit)) return;
+  atomicAnd((unsigned long long*)&a.lvt[(size_t)L * d.ntw + (sw >> 6)], ~(1ull << (sw & 63)));
+}
+// one wave, from the summary word chunk q whose ballot is bal: the smallest
+// label of level L
+__device__ __forceinline__ uint32_t lv_descend(const Args& a, const LvDims& d, uint32_t L,
+                                               uint32_t q, uint64_t bal, uint64_t v) {
+  const int l = __ffsll((unsigned long long)bal) - 1;
+  const uint64_t tv = (uint64_t)__shfl((unsigned long long)v, l, kWave);
+  const uint32_t sw = ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)tv) - 1);
+  const uint64_t sv = aload(&a.lvs[(size_t)L * d.nsw + sw]);
+  if (sv == 0) return kNone - 1;  // inconsistent structure
+  const uint32_t w = (sw << 6) + (uint32_t)(__ffsll((unsigned long long)sv) - 1);
+  const uint64_t wv = aload(&a.lvb[(size_t)L * d.nwd + w]);
+  if (wv == 0) return kNone - 1;
+  const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)wv) - 1);
+  return b < (uint32_t)a.n ? b : kNone - 1;
+}
+// one wave: the smallest label of the highest non-empty level, kNone if the
+// structure is empty, kNone - 1 if it is inconsistent
+__device__ uint32_t lv_search(const Args& a) {
+  const LvDims d = lv_dims(a);
+  if (d.ntw <= (uint32_t)kWave) {
+    uint64_t v[kLevels];
+#pragma unroll
+    for (int L = 0; L < kLevels; ++L)
+      v[L] = lane() < d.ntw ? aload(&a.lvt[(size_t)L * d.ntw + lane()]) : 0ull;
+#pragma unroll
+    for (int L = kLevels - 1; L >= 0; --L) {
+      const uint64_t bal = __ballot(v[L] != 0);
+      if (bal) return lv_descend(a, d, (uint32_t)L, 0, bal, v[L]);
+    }
+    return kNone;
   }
+  for (int L = kLevels - 1; L >= 0; --L)
+    for (uint32_t q = 0; q < d.ntw; q += kWave) {
+      const uint64_t v = q + lane() < d.ntw ? aload(&a.lvt[(size_t)L * d.ntw + q + lane()]) : 0ull;
+      const uint64_t bal = __ballot(v != 0);
+      if (bal) return lv_descend(a, d, (uint32_t)L, q, bal, v);
+    }
+  return kNone;
 }
 
 // Start of iteration k: returns C, or kNone when the loop ends (no unstable
 // block, which is the final counted pass, or the iteration cap).
-template <bool L>
 __device__ uint32_t head(const Args& a, uint32_t k, const Part& p) {
-  uint32_t C;
-  if (L) {
-    const uint64_t key = *key_ptr(a.ctl, k & 1);
-    C = key ? key_label(key) : kNone;
-  } else {
-    C = a.ctl->cand[k & 1].v[0];
-  }
+  const uint32_t C = a.ctl->cand[k & 1].v[0];
   const bool over = (k + 1 > a.iter_cap);
   if (p.gtid == 0) {
     Ctl* c = a.ctl;
@@ -118,6 +186,7 @@ __device__ uint32_t head(const Args& a, uint32_t k, const Part& p) {
       c->work[nx].v[0] = 0;
       c->work[nx].v[1] = 0;
       c->cntC[nx].v[0] = 0;
+      if (a.used) a.used[C] = k + 1;
       if (a.trace_C && k < a.trace_cap) a.trace_C[k] = (int32_t)C;
     }
   }
@@ -132,66 +201,49 @@ __device__ __forceinline__ void unstable_set(const Args& a, uint32_t b) {
   if (old == 0) atomicOr((unsigned long long*)&a.us[w >> 6], 1ull << (w & 63));
 }
 
-// A: clear C and find the next iteration's candidate.  Plain policy: C is
-// the smallest unstable label, so the smallest remaining one is the next set
-// bit after C; one wave finds it through the summary level.  Labels made
-// unstable later in this iteration are min-reduced into the candidate in C.
+// A: clear C and, for the plain policy, find the next iteration's candidate.
+// Plain policy: C is the smallest unstable label, so the smallest remaining
+// one is the next set bit after C; one wave finds it through the summary
+// level.  Labels made unstable later in this iteration are min-reduced into
+// the candidate in C.  Learned policy: the candidate is chosen after the
+// re-scoring at the end of the iteration.
 template <bool L>
 __device__ void phase_a_select(const Args& a, uint32_t par, uint32_t C, uint32_t k,
                                const Part& p) {
+  if (p.gwave != 0) return;
   const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
-  if (!L) {
-    if (p.gwave != 0) return;
-    const uint32_t w0 = C >> 6;
-    const uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
-    if (lane() == 0) {
-      a.ub[w0] = bits;
-      if (bits == 0) atomicAnd((unsigned long long*)&a.us[w0 >> 6], ~(1ull << (w0 & 63)));
-    }
-    // Labels below C are stable, except in the first iteration, where the
-    // splitter may have been forced: search from word 0 there.  Word w0 is
-    // taken from `bits` (this wave's own update may not be visible yet).
-    const uint32_t from = (k == 0) ? 0u : w0;
-    const uint32_t nsw = (nwd + 63u) >> 6;
-    uint32_t next = kNone;
-    for (uint32_t q = from >> 6; q < nsw; q += kWave) {
-      const uint32_t qq = q + lane();
-      uint64_t sv = qq < nsw ? a.us[qq] : 0ull;
-      if (qq == (from >> 6)) sv &= ~0ull << (from & 63);
-      if (qq == (w0 >> 6)) {
-        const uint64_t b0 = 1ull << (w0 & 63);
-        sv = bits ? (sv | b0) : (sv & ~b0);
-      }
-      const uint64_t bal = __ballot(sv != 0);
-      if (bal) {
-        const int l = __ffsll((unsigned long long)bal) - 1;
-        const uint64_t v = (uint64_t)__shfl((unsigned long long)sv, l, kWave);
-        const uint32_t word = ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)v) - 1);
-        const uint64_t wb = (word == w0) ? bits : a.ub[word];
-        if (wb) next = (word << 6) + (uint32_t)(__ffsll((unsigned long long)wb) - 1);
-        break;
-      }
-    }
-    if (lane() == 0 && next != kNone) a.ctl->cand[par ^ 1].v[0] = next;
-  } else {
-    uint64_t best = 0;
-    for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
-      uint64_t bits = a.ub[w];
-      if (w == (C >> 6)) {
-        bits &= ~(1ull << (C & 63));
-        a.ub[w] = bits;
-        if (bits == 0) atomicAnd((unsigned long long*)&a.us[w >> 6], ~(1ull << (w & 63)));
-      }
-      while (bits) {
-        const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
-        bits &= bits - 1;
-        const uint64_t kk = score_key(a.score[b], b);
-        best = kk > best ? kk : best;
-      }
-    }
-    best = wave_max_u64(best);
-    if (lane() == 0 && best) atomicMax((unsigned long long*)key_ptr(a.ctl, par ^ 1), (unsigned long long)best);
+  const uint32_t w0 = C >> 6;
+  const uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
+  if (lane() == 0) {
+    a.ub[w0] = bits;
+    if (bits == 0) atomicAnd((unsigned long long*)&a.us[w0 >> 6], ~(1ull << (w0 & 63)));
   }
+  if (L) return;
+  // Labels below C are stable, except in the first iteration, where the
+  // splitter may have been forced: search from word 0 there.  Word w0 is
+  // taken from `bits` (this wave's own update may not be visible yet).
+  const uint32_t from = (k == 0) ? 0u : w0;
+  const uint32_t nsw = (nwd + 63u) >> 6;
+  uint32_t next = kNone;
+  for (uint32_t q = from >> 6; q < nsw; q += kWave) {
+    const uint32_t qq = q + lane();
+    uint64_t sv = qq < nsw ? a.us[qq] : 0ull;
+    if (qq == (from >> 6)) sv &= ~0ull << (from & 63);
+    if (qq == (w0 >> 6)) {
+      const uint64_t b0 = 1ull << (w0 & 63);
+      sv = bits ? (sv | b0) : (sv & ~b0);
+    }
+    const uint64_t bal = __ballot(sv != 0);
+    if (bal) {
+      const int l = __ffsll((unsigned long long)bal) - 1;
+      const uint64_t v = (uint64_t)__shfl((unsigned long long)sv, l, kWave);
+      const uint32_t word = ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)v) - 1);
+      const uint64_t wb = (word == w0) ? bits : a.ub[word];
+      if (wb) next = (word << 6) + (uint32_t)(__ffsll((unsigned long long)wb) - 1);
+      break;
+    }
+  }
+  if (lane() == 0 && next != kNone) a.ctl->cand[par ^ 1].v[0] = next;
 }
 
 __device__ __forceinline__ void mark_slot(const Args& a, uint32_t par, int32_t s, int32_t o,
@@ -383,14 +435,6 @@ __device__ void phase_c(const Args& a, uint32_t par, uint32_t k, uint32_t C, con
     if (!L) {
       if (nS > 0) atomicMin(&a.ctl->cand[par ^ 1].v[0], C);
       a.ctl->cand[par].v[0] = kNone;
-    } else {
-      const bool full = a.rescore && ((k + 1) % a.rescore) == 0;
-      if (full)
-        *key_ptr(a.ctl, par ^ 1) = 0;  // every unstable block is re-scored in D
-      else if (nS > 0)
-        atomicMax((unsigned long long*)key_ptr(a.ctl, par ^ 1),
-                  (unsigned long long)score_key(a.score[C], C));
-      *key_ptr(a.ctl, par) = 0;
     }
     if (a.trace_nsplit && k < a.trace_cap) a.trace_nsplit[k] = nS;
     if (a.trace_work && k < a.trace_cap) {
@@ -403,24 +447,69 @@ __device__ void phase_c(const Args& a, uint32_t par, uint32_t k, uint32_t C, con
   }
 }
 
-// D (learned policy): re-score changed blocks, or every unstable block
-__device__ void phase_d(const Args& a, const MlpLds& M, uint32_t par, uint32_t k, const Part& p) {
-  const uint32_t kcur = k + 1;
-  uint64_t* key = key_ptr(a.ctl, par ^ 1);
-  const bool full = a.rescore && (kcur % a.rescore) == 0;
-  if (!full) {
-    const uint32_t nC = a.ctl->cntC[par].v[0];
-    for (uint32_t q = p.gwave; q < 2 * nC; q += p.gwaves)
-      score_block(a, M, (uint32_t)a.chg[q], kcur, key);
-  } else {
-    const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
-    for (uint32_t w = p.gwave; w < nwd; w += p.gwaves) {
-      uint64_t bits = a.ub[w];
-      while (bits) {
-        const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
-        bits &= bits - 1;
-        score_block(a, M, b, kcur, key);
-      }
+// S (learned policy, one workgroup): re-score the labels that changed in this
+// iteration (both labels of every split block, and C, whose "used" feature
+// changed), move them between levels (all removals before all insertions, so
+// the summaries stay exact), then pick the next splitter: the smallest label
+// of the highest non-empty level.
+__device__ void phase_s(const Args& a, const MlpLds& M, uint32_t par, uint32_t k) {
+  const uint32_t nC = a.ctl->cntC[par].v[0];
+  const uint32_t C = a.ctl->state.v[3];
+  const uint32_t ne = 2 * nC + 1;
+  const uint32_t wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  for (uint32_t q = wid; q < ne; q += nw) {
+    const uint32_t b = q < 2 * nC ? (uint32_t)a.chg[q] : C;
+    const uint32_t lv = test_bit(a.ub, b) ? block_level(a, M, b, k + 1) : 0xFFu;
+    if (lane() == 0) {
+      lv_remove(a, b, a.lvl[b]);
+      a.lvq[q] = (uint8_t)lv;
+    }
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < ne; q += blockDim.x) {
+    const uint32_t b = q < 2 * nC ? (uint32_t)a.chg[q] : C;
+    const uint32_t lv = a.lvq[q];
+    if (lv != 0xFFu) {
+      lv_insert(a, b, lv);
+      a.lvl[b] = (uint8_t)lv;
+    }
+  }
+  __syncthreads();
+  if (wid == 0) {
+    const uint32_t nx = lv_search(a);
+    if (lane() == 0) {
+      a.ctl->cand[par ^ 1].v[0] = nx == kNone - 1 ? kNone : nx;
+      if (nx == kNone - 1) a.ctl->state.v[4] = 1;
+    }
+  }
+}
+
+// Full re-scoring (every R iterations, before S): new levels of all unstable
+// labels, and an empty structure (F1); then every unstable label inserted at
+// its level (F2).
+__device__ void phase_f1(const Args& a, const MlpLds& M, uint32_t kcur, const Part& p) {
+  const LvDims d = lv_dims(a);
+  for (uint32_t i = p.gtid; i < kLevels * d.nwd; i += p.gthreads) a.lvb[i] = 0;
+  for (uint32_t i = p.gtid; i < kLevels * d.nsw; i += p.gthreads) a.lvs[i] = 0;
+  for (uint32_t i = p.gtid; i < kLevels * d.ntw; i += p.gthreads) a.lvt[i] = 0;
+  for (uint32_t w = p.gwave; w < d.nwd; w += p.gwaves) {
+    uint64_t bits = a.ub[w];
+    while (bits) {
+      const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
+      bits &= bits - 1;
+      const uint32_t lv = block_level(a, M, b, kcur);
+      if (lane() == 0) a.lvl[b] = (uint8_t)lv;
+    }
+  }
+}
+__device__ void phase_f2(const Args& a, const Part& p) {
+  const uint32_t nwd = ((uint32_t)a.n + 63u) >> 6;
+  for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
+    uint64_t bits = a.ub[w];
+    while (bits) {
+      const uint32_t b = (w << 6) + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
+      bits &= bits - 1;
+      lv_insert(a, b, a.lvl[b]);
     }
   }
 }
@@ -475,7 +564,11 @@ __global__ void k_zero_features(Args a) {
   const Part p = part();
   const uint64_t n = (uint32_t)a.n;
   for (uint64_t i = p.gtid; i < 17 * n; i += p.gthreads) a.acc[i] = 0;
-  for (uint64_t i = p.gtid; i < n; i += p.gthreads) a.born[i] = 0;
+  for (uint64_t i = p.gtid; i < n; i += p.gthreads) {
+    a.born[i] = 0;
+    a.used[i] = 0;
+    if (a.lvl) a.lvl[i] = 0;
+  }
 }
 __global__ void k_accumulate_features(Args a, const int32_t* __restrict__ pre) {
   const Part p = part();
@@ -488,15 +581,23 @@ __global__ void k_accumulate_features(Args a, const int32_t* __restrict__ pre) {
     }
   }
 }
-// initial scores of the preprocessed blocks and the first candidate
-__global__ void k_init_scores(Args a, const int32_t* __restrict__ pre) {
+// learned policy: levels of all unstable labels (F1, F2) and the splitter of
+// the first iteration
+__global__ void k_levels_all(Args a, uint32_t kcur) {
   extern __shared__ float sw[];
   MlpLds M = mlp_lds_layout(sw, kPolicyF);
   mlp_stage(M, a.wbf, kPolicyF);
   __syncthreads();
-  const Part p = part();
-  for (uint32_t b = p.gwave; b < (uint32_t)a.n; b += p.gwaves)
-    if ((uint32_t)pre[b] == b) score_block(a, M, b, 0, key_ptr(a.ctl, 0));
+  phase_f1(a, M, kcur, part());
+}
+__global__ void k_levels_insert(Args a) { phase_f2(a, part()); }
+__global__ void k_learned_first(Args a) {
+  if (threadIdx.x >= kWave) return;
+  const uint32_t nx = lv_search(a);
+  if (lane() == 0) {
+    a.ctl->cand[0].v[0] = nx == kNone - 1 ? kNone : nx;
+    if (nx == kNone - 1) a.ctl->state.v[4] = 1;
+  }
 }
 
 __global__ void k_count_leaders(const int32_t* __restrict__ block, int32_t n,

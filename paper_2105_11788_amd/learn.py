@@ -2,7 +2,7 @@
 
 Pipeline (all arithmetic on the GPU, through the C ABI):
   1. plain refinement runs on training LTSs with sampled candidates:
-     per sampled unstable block, its 18 features and the counterfactual
+     per sampled unstable block, its 19 features and the counterfactual
      target log(1 + blocks that would split if it were the splitter now)
      (bisim_collect_training);
   2. full-batch Adam on the mean squared error (mlp_train_step);

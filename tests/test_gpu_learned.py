@@ -41,7 +41,7 @@ def forward_error_bound(w, x, F):
     return e3
 
 
-@pytest.mark.parametrize("F", [18, 5])
+@pytest.mark.parametrize("F", [19, 5])
 def test_mlp_forward_matches_reference(B, F):
     rng = np.random.default_rng(F)
     w = ref.he_init(F, seed=F)
@@ -55,7 +55,7 @@ def test_mlp_forward_matches_reference(B, F):
 
 
 def test_mlp_gradient_and_adam_match_reference(B):
-    F = 18
+    F = 19
     rng = np.random.default_rng(3)
     w = ref.he_init(F, seed=11)
     x = (rng.random((512, F)) * 6.0).astype(np.float32)
@@ -80,7 +80,7 @@ def test_mlp_gradient_and_adam_match_reference(B):
 
 
 def test_mlp_training_reduces_loss(B):
-    F = 18
+    F = 19
     rng = np.random.default_rng(5)
     x = (rng.random((4096, F)) * 4).astype(np.float32)
     t = (np.sin(x[:, 0]) + 0.3 * x[:, 3]).astype(np.float32)
@@ -102,6 +102,7 @@ def test_learned_policy_partition_exact(B):
              gen.planted_quotient(q=300, deg_mean=6.0, K=16, seed=4)]
     for L in cases:
         ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        its = {}
         for engine in (1, 2):
             for R in (1, 7, 64):
                 src, lab, dst, init = _dev(B, L)
@@ -114,23 +115,29 @@ def test_learned_policy_partition_exact(B):
                 assert (b1 == ks).all(), (L.name, engine, R)
                 assert (blk2.numpy() == b1).all() and st2.iterations == st.iterations
                 assert nb + 1 <= st.iterations <= 3 * L.n - st.pre_blocks + 1
+                its.setdefault(R, set()).add(st.iterations)
+        # both engines follow the same splitter order
+        assert all(len(v) == 1 for v in its.values()), (L.name, its)
 
 
 def _trace_state(L, k):
-    """Partition at the start of iteration k and each label's 'born'
-    iteration, from the lock-step oracle."""
+    """Partition at the start of iteration k, and for each label the number
+    of iterations completed when its block was created or last split ('born')
+    and when it was last the splitter ('used'), from the lock-step oracle."""
     pp = oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst, L.init)
     r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init, trace_cap=k + 1,
                           keep_blocks=True)
     parts = [pp["pre_block"]] + [r["blocks"][i] for i in range(min(k, r["iters"]))]
     born = np.zeros(L.n, np.int64)
+    used = np.zeros(L.n, np.int64)
     for i in range(1, len(parts)):
         before, after = parts[i - 1], parts[i]
         changed = np.nonzero(before != after)[0]
         for s in changed:
             born[before[s]] = i
             born[after[s]] = i
-    return parts[min(k, len(parts) - 1)], born
+        used[r["C"][i - 1]] = i
+    return parts[min(k, len(parts) - 1)], born, used
 
 
 def test_collector_matches_definitions(B):
@@ -139,19 +146,21 @@ def test_collector_matches_definitions(B):
     with B.LTS(src, lab, dst, L.n, L.K, init) as h:
         f, t, meta = B.collect_training(h, sample_every=5, max_cands=6, cap=5000)
     assert f.shape[0] > 20
+    assert set(np.unique(f[:, 18]).tolist()) == {0.0, 1.0}  # both values of the flag occur
     S, A, D = L.src, L.lab, L.dst
     cache = {}
     for row in range(f.shape[0]):
         k, X = int(meta[row, 0]), int(meta[row, 1])
         if k not in cache:
             cache[k] = _trace_state(L, k)
-        block, born = cache[k]
+        block, born, used = cache[k]
         assert block[X] == X
         mem = block == X
         size = mem.sum()
         out8 = [np.sum(mem[S] & (A % 8 == q)) for q in range(8)]
         in8 = [np.sum(mem[D] & (A % 8 == q)) for q in range(8)]
-        exp = np.log1p(np.array([size, *out8, *in8, k - born[X]], np.float64)).astype(np.float32)
+        exp = np.log1p(np.array([size, *out8, *in8, k - born[X]], np.float64))
+        exp = np.append(exp, 1.0 if used[X] > born[X] else 0.0).astype(np.float32)
         assert np.allclose(f[row], exp, rtol=2e-6, atol=0), (row, k, X, f[row], exp)
         marked = defaultdict(set)
         for s, a, d in zip(S, A, D):
