@@ -52,6 +52,11 @@ struct bisim_batch {
   uint64_t* lt = nullptr;
   int32_t* tl = nullptr;
   int32_t* sl = nullptr;
+  // member-list tier scratch
+  int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr, *cnt = nullptr,
+          *fc = nullptr, *gc = nullptr, *tmp = nullptr, *rk = nullptr, *fi = nullptr,
+          *ltl = nullptr;
+  uint64_t *sf = nullptr, *us = nullptr;
   uint32_t* iters_d = nullptr;  // [count]
   uint32_t* ctl_d = nullptr;    // [0] queue head, [1] error
   // options / tuning
@@ -92,6 +97,8 @@ struct BArgs {
   uint64_t* lt;
   int32_t* tl;
   int32_t* sl;
+  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ltl;
+  uint64_t *sf, *us;
   int32_t* out;
   uint32_t* iters;
   uint32_t* ctl;
@@ -124,7 +131,32 @@ struct Shared {
   uint32_t nT[2];
   uint32_t nS[2];
   uint32_t ltany[2];
+  uint32_t nL[2];  // member-list tier: touched leaders
+  uint32_t wsum[16];  // member-list tier: per-wave sums of the block-size scan
+  uint32_t bad;       // member-list tier: inconsistent block sizes (never expected)
   uint32_t job;
+};
+
+// Member-list tier (instances too large for LDS): the partition is also kept
+// as a refinable partition, so an iteration visits C's members, the touched
+// states and the members of blocks whose leader was touched instead of all
+// n states.  perm lists the states block by block; block b (a label) owns
+// perm[bs[b] .. be[b]).  A split moves the split-off states to the end of the
+// block's range by swaps and gives that tail to the new label.
+struct GList {
+  int32_t* perm;  // [n] states ordered by block
+  int32_t* pos;   // [n] position of each state in perm
+  int32_t* bs;    // [n] per label: first position of its block
+  int32_t* be;    // [n] per label: one past the last position
+  int32_t* cnt;   // [n] per label: states split off this iteration (0 between iterations)
+  int32_t* fc;    // [n] per label: split states found in the front part
+  int32_t* gc;    // [n] per label: staying states found in the tail
+  int32_t* tmp;   // [n] per position: tail positions of staying states, by index
+  int32_t* rk;    // [n] per split-list entry: rank within its block's split part
+  int32_t* fi;    // [n] per split-list entry: index among front split states, or -1
+  int32_t* ltl;   // [n] touched leaders
+  uint64_t* sf;   // [ceil(n/64)] split flags
+  uint64_t* us;   // [ceil(n/4096)] summary of the unstable bitmap
 };
 
 __device__ __forceinline__ void wg_min(uint32_t* dst, uint32_t v) {
@@ -143,8 +175,9 @@ __device__ __forceinline__ void push(int32_t* list, uint32_t* cnt, int32_t v, bo
   if (pred) list[base + __popcll(bal & ((1ull << lane()) - 1ull))] = v;
 }
 
-// The whole refinement loop of one instance by one workgroup.
-template <class MaskT>
+// The whole refinement loop of one instance by one workgroup; U chunks of 64
+// states per wave and step in the scans over all states of the instance.
+template <class MaskT, uint32_t U>
 __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<MaskT> w,
                                               int32_t* T, int32_t* S, uint32_t s0, uint32_t n) {
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
@@ -199,9 +232,15 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
         sh.nS[par ^ 1] = 0;
         sh.ltany[par ^ 1] = 0;
       }
-      for (uint32_t base = wid * kWave; base < n; base += nwav * kWave) {
+      // U chunks of 64 states per wave and step: their block ids are loaded
+      // together, so a step waits for one memory latency, not U
+      for (uint32_t base0 = wid * kWave * U; base0 < n; base0 += nwav * kWave * U) {
+        const uint32_t hm = hit_mask<U>(w.blk, base0, n, C);
+        if (__ballot(hm != 0) == 0) continue;
+       for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t base = base0 + u * kWave;
         const uint32_t t = base + lane();
-        const bool hit = t < n && (uint32_t)w.blk[t] == C;
+        const bool hit = (hm >> u) & 1u;
         if (__ballot(hit) == 0) continue;
         uint32_t beg = 0, deg = 0;
         if (hit) {
@@ -243,6 +282,7 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
           }
           push(T, &sh.nT[par], s, first);
         }
+       }
       }
     }
     __syncthreads();
@@ -264,18 +304,31 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
         push(S, &sh.nS[par], s, sp);
       }
       if (sh.ltany[par]) {
-        for (uint32_t base = wid * kWave; base < n; base += nwav * kWave) {
-          const uint32_t s = base + lane();
-          bool sp = false;
-          int32_t b = 0;
-          if (s < n) {
-            b = w.blk[s];
-            sp = test_bit(w.lt, (uint32_t)b) && !test_bit(w.tb, s);
+        for (uint32_t base0 = wid * kWave * U; base0 < n; base0 += nwav * kWave * U) {
+          // block ids, then leader-touched bits, then touched bits of U
+          // chunks: three memory latencies per step
+          int32_t bv[U];
+          uint64_t lw[U], tw[U];
+#pragma unroll
+          for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t s = base0 + u * kWave + lane();
+            bv[u] = s < n ? w.blk[s] : 0;
           }
-          if (sp)
-            atomicMax((unsigned long long*)&w.nlb[b],
-                      (unsigned long long)(epoch | (uint64_t)(kNone - s)));
-          push(S, &sh.nS[par], (int32_t)s, sp);
+#pragma unroll
+          for (uint32_t u = 0; u < U; ++u) lw[u] = w.lt[(uint32_t)bv[u] >> 6];
+#pragma unroll
+          for (uint32_t u = 0; u < U; ++u)
+            tw[u] = base0 + u * kWave < n ? w.tb[(base0 + u * kWave) >> 6] : 0ull;
+#pragma unroll
+          for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t s = base0 + u * kWave + lane();
+            const int32_t b = bv[u];
+            const bool sp = s < n && ((lw[u] >> (b & 63)) & 1ull) && !((tw[u] >> (s & 63)) & 1ull);
+            if (sp)
+              atomicMax((unsigned long long*)&w.nlb[b],
+                        (unsigned long long)(epoch | (uint64_t)(kNone - s)));
+            push(S, &sh.nS[par], (int32_t)s, sp);
+          }
         }
       }
     }
@@ -316,6 +369,325 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
   return it + 1;
 }
 
+// Set unstable bit b and keep the summary exact (sets only; the one clear per
+// iteration happens in the selection, never concurrently with sets).
+__device__ __forceinline__ void wg_unstable_set(uint64_t* ub, uint64_t* us, uint32_t b) {
+  const uint32_t w = b >> 6;
+  const uint64_t old = atomicOr((unsigned long long*)&ub[w], 1ull << (b & 63));
+  if (old == 0) atomicOr((unsigned long long*)&us[w >> 6], 1ull << (w & 63));
+}
+
+// The refinement loop of one instance by one workgroup, member-list tier.
+// Same phases and the same splitter sequence as wg_refine; the scans over
+// all states are replaced by visits of block ranges.
+template <class MaskT>
+__device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, GList g,
+                                    int32_t* T, int32_t* S, uint32_t s0, uint32_t n) {
+  const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+  const uint32_t wid = tid / kWave, nwav = nthr / kWave;
+  const uint32_t nw = (n + 63u) >> 6, nsw = (nw + 63u) >> 6;
+  // ---- initial state: blocks of the preprocessed partition, all unstable
+  for (uint32_t s = tid; s < n; s += nthr) {
+    w.blk[s] = a.pre_block[s0 + s] - (int32_t)s0;
+    w.mw[s] = 0;
+    w.nlb[s] = 0;
+    g.cnt[s] = 0;
+    g.fc[s] = 0;
+    g.gc[s] = 0;
+  }
+  for (uint32_t q = tid; q < nw; q += nthr) {
+    uint64_t bits = 0;
+    for (uint32_t j = 0; j < 64 && (q << 6) + j < n; ++j)
+      if ((uint32_t)(a.pre_block[s0 + (q << 6) + j] - (int32_t)s0) == (q << 6) + j)
+        bits |= 1ull << j;
+    w.ub[q] = bits;
+    w.tb[q] = 0;
+    w.lt[q] = 0;
+    g.sf[q] = 0;
+  }
+  for (uint32_t q = tid; q < nsw; q += nthr) g.us[q] = 0;
+  if (tid == 0) {
+    sh.cand[0] = n ? 0u : kNone;
+    sh.cand[1] = kNone;
+    sh.nT[0] = sh.nT[1] = sh.nS[0] = sh.nS[1] = 0;
+    sh.ltany[0] = sh.ltany[1] = 0;
+    sh.nL[0] = sh.nL[1] = 0;
+    sh.bad = 0;
+  }
+  __syncthreads();
+  for (uint32_t q = tid; q < nw; q += nthr)
+    if (w.ub[q]) atomicOr((unsigned long long*)&g.us[q >> 6], 1ull << (q & 63));
+  for (uint32_t s = tid; s < n; s += nthr) atomicAdd(&g.cnt[w.blk[s]], 1);
+  __syncthreads();
+  // block ranges: exclusive prefix sums of the block sizes in label order
+  // (thread-contiguous label ranges; wave scan, then the <= 16 wave totals)
+  {
+    const uint32_t per = (n + nthr - 1) / nthr;
+    const uint32_t lo = min(n, tid * per), hi = min(n, lo + per);
+    uint32_t sum = 0;
+    for (uint32_t b = lo; b < hi; ++b) sum += (uint32_t)g.cnt[b];
+    const uint32_t incl = wave_incl_scan_u32(sum);
+    if (lane() == kWave - 1) sh.wsum[wid] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (uint32_t q = 0; q < wid; ++q) run += sh.wsum[q];
+    for (uint32_t b = lo; b < hi; ++b) {
+      g.bs[b] = (int32_t)run;
+      g.be[b] = (int32_t)run;  // fill cursor, ends at the block's end
+      run += (uint32_t)g.cnt[b];
+    }
+  }
+  __syncthreads();
+  for (uint32_t s = tid; s < n; s += nthr) {
+    const uint32_t p = (uint32_t)atomicAdd(&g.be[w.blk[s]], 1);
+    if (p >= n) {  // cannot happen with consistent counts; report, never write
+      sh.bad = 1;
+      continue;
+    }
+    g.perm[p] = (int32_t)s;
+    g.pos[s] = (int32_t)p;
+  }
+  __syncthreads();
+  if (sh.bad) {  // workgroup-uniform
+    if (tid == 0) atomicOr(&a.ctl[1], 2u);
+    return 0;
+  }
+  for (uint32_t s = tid; s < n; s += nthr) g.cnt[s] = 0;
+  __syncthreads();
+
+  const uint32_t cap = 3u * n + 1u;
+  uint32_t it = 0;
+  for (;; ++it) {
+    const uint32_t par = it & 1;
+    const uint32_t C = sh.cand[par];
+    if (C == kNone) break;
+    if (it + 1 > cap) {
+      if (tid == 0) atomicOr(&a.ctl[1], 1u);
+      break;
+    }
+    const uint64_t epoch = (uint64_t)(it + 1) << 32;
+    // ---- A: clear C, next candidate (one wave, through the summary), mark
+    if (wid == 0) {
+      const uint32_t w0 = C >> 6;
+      const uint64_t bits = w.ub[w0] & ~(1ull << (C & 63));
+      if (lane() == 0) {
+        w.ub[w0] = bits;
+        if (bits == 0) atomicAnd((unsigned long long*)&g.us[w0 >> 6], ~(1ull << (w0 & 63)));
+      }
+      // C is the smallest unstable label: the next one is the next set bit
+      uint32_t next = kNone;
+      for (uint32_t q = w0 >> 6; q < nsw; q += kWave) {
+        const uint32_t qq = q + lane();
+        uint64_t sv = qq < nsw ? g.us[qq] : 0ull;
+        if (qq == (w0 >> 6)) {
+          sv &= ~0ull << (w0 & 63);
+          const uint64_t b0 = 1ull << (w0 & 63);
+          sv = bits ? (sv | b0) : (sv & ~b0);
+        }
+        const uint64_t bal = __ballot(sv != 0);
+        if (bal) {
+          const int l = __ffsll((unsigned long long)bal) - 1;
+          const uint64_t v = (uint64_t)__shfl((unsigned long long)sv, l, kWave);
+          const uint32_t word = ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)v) - 1);
+          const uint64_t wb = (word == w0) ? bits : w.ub[word];
+          if (wb) next = (word << 6) + (uint32_t)(__ffsll((unsigned long long)wb) - 1);
+          break;
+        }
+      }
+      if (lane() == 0 && next != kNone) atomicMin(&sh.cand[par ^ 1], next);
+    }
+    if (tid == 0) {
+      sh.nT[par ^ 1] = 0;
+      sh.nS[par ^ 1] = 0;
+      sh.nL[par ^ 1] = 0;
+    }
+    {
+      const uint32_t cb = (uint32_t)g.bs[C];
+      uint32_t csz = (uint32_t)g.be[C] - cb;
+      if (cb > n || csz > n - cb) {  // never expected: report, visit nothing
+        sh.bad = 1;
+        csz = 0;
+      }
+      for (uint32_t i0 = wid * kWave; i0 < csz; i0 += nwav * kWave) {
+        const uint32_t i = i0 + lane();
+        const bool hit = i < csz;
+        uint32_t beg = 0, deg = 0;
+        if (hit) {
+          const uint32_t t = (uint32_t)g.perm[cb + i];
+          beg = a.in_ptr[s0 + t];
+          deg = a.in_ptr[s0 + t + 1] - beg;
+        }
+        const uint32_t incl = wave_incl_scan_u32(deg);
+        const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
+          const uint32_t e = e0 + lane();
+          const bool valid = e < total;
+          const uint32_t ee = valid ? e : total - 1;
+          uint32_t j = 0;
+#pragma unroll
+          for (uint32_t step = 32; step >= 1; step >>= 1) {
+            const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
+            if (probe <= ee) j += step;
+          }
+          const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
+          const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
+          const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
+          bool first = false, lead = false;
+          int32_t s = 0;
+          if (valid) {
+            const uint32_t edge = jb + (ee - (ji - jd));
+            s = a.in_src[edge] - (int32_t)s0;
+            const int32_t o = a.in_ord[edge];
+            const MaskT bit = (MaskT)1 << (o & (int)(sizeof(MaskT) * 8 - 1));
+            const int32_t bs_ = w.blk[s];
+            const MaskT old = atomic_or(&w.mw[s], bit);
+            first = (old == 0);
+            if (first) {
+              atomicOr((unsigned long long*)&w.tb[s >> 6], (unsigned long long)(1ull << (s & 63)));
+              lead = (bs_ == s);
+            }
+          }
+          push(T, &sh.nT[par], s, first);
+          push(g.ltl, &sh.nL[par], s, lead);
+        }
+      }
+    }
+    __syncthreads();
+    // ---- B: compare touched states with their leader; untouched members of
+    // blocks whose leader was touched differ from it; elect
+    {
+      const uint32_t nT = sh.nT[par];
+      for (uint32_t i0 = wid * kWave; i0 < nT; i0 += nwav * kWave) {
+        const uint32_t i = i0 + lane();
+        bool sp = false;
+        int32_t s = 0, b = 0;
+        if (i < nT) {
+          s = T[i];
+          b = w.blk[s];
+          sp = (s != b) && (w.mw[s] != w.mw[b]);
+        }
+        if (sp)
+          atomicMax((unsigned long long*)&w.nlb[b],
+                    (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
+        push(S, &sh.nS[par], s, sp);
+      }
+      const uint32_t nL = sh.nL[par];
+      for (uint32_t j = wid; j < nL; j += nwav) {
+        const int32_t b = g.ltl[j];
+        const uint32_t lo = (uint32_t)g.bs[b], hi = (uint32_t)g.be[b];
+        for (uint32_t i0 = lo; i0 < hi; i0 += kWave) {
+          const uint32_t i = i0 + lane();
+          int32_t s = 0;
+          bool sp = false;
+          if (i < hi) {
+            s = g.perm[i];
+            sp = !test_bit(w.tb, (uint32_t)s);
+          }
+          if (sp)
+            atomicMax((unsigned long long*)&w.nlb[b],
+                      (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
+          push(S, &sh.nS[par], s, sp);
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t nS = sh.nS[par], nT = sh.nT[par];
+    // ---- C1: size of each block's split part; split flags
+    for (uint32_t i = tid; i < nS; i += nthr) {
+      const int32_t s = S[i];
+      g.rk[i] = atomicAdd(&g.cnt[w.blk[s]], 1);
+      atomicOr((unsigned long long*)&g.sf[s >> 6], 1ull << (s & 63));
+    }
+    __syncthreads();
+    // ---- C2: the split part goes to the tail [ne, be) of the block's range:
+    // index the split states in front of ne and the staying states in the tail
+    for (uint32_t i = tid; i < nS; i += nthr) {
+      const int32_t s = S[i], b = w.blk[s];
+      const int32_t e = g.be[b], ne = e - g.cnt[b];
+      g.fi[i] = g.pos[s] < ne ? atomicAdd(&g.fc[b], 1) : -1;
+      const int32_t q = ne + g.rk[i];  // every tail position is examined once
+      if (ne < 0 || q < ne || q >= e || e > (int32_t)n) {  // never expected
+        sh.bad = 1;
+        g.fi[i] = -1;
+        continue;
+      }
+      const int32_t u = g.perm[q];
+      if (!test_bit(g.sf, (uint32_t)u)) {
+        const int32_t j = atomicAdd(&g.gc[b], 1);
+        if (ne + j < e) g.tmp[ne + j] = q;
+        else sh.bad = 1;
+      }
+    }
+    __syncthreads();
+    // ---- C3: swap the i-th front split state with the i-th tail staying state
+    for (uint32_t i = tid; i < nS; i += nthr) {
+      const int32_t f = g.fi[i];
+      if (f < 0) continue;
+      const int32_t s = S[i], b = w.blk[s];
+      const int32_t e = g.be[b], ne = e - g.cnt[b];
+      if (ne + f >= e) {  // never expected
+        sh.bad = 1;
+        continue;
+      }
+      const int32_t q = g.tmp[ne + f];
+      const int32_t ps = g.pos[s];
+      if (q < ne || q >= e || ps < 0 || ps >= ne) {
+        sh.bad = 1;
+        continue;
+      }
+      const int32_t u = g.perm[q];
+      g.perm[ps] = u;
+      g.pos[u] = ps;
+      g.perm[q] = s;
+      g.pos[s] = q;
+    }
+    __syncthreads();
+    // ---- C4: relabel, new ranges, unstable updates, clear marks
+    {
+      uint32_t best = kNone;
+      for (uint32_t i = tid; i < nS; i += nthr) {
+        const int32_t s = S[i];
+        const int32_t old = w.blk[s];
+        const int32_t nl = (int32_t)(kNone - (uint32_t)w.nlb[old]);
+        w.blk[s] = nl;
+        atomicAnd((unsigned long long*)&g.sf[s >> 6], ~(1ull << (s & 63)));
+        if (s == nl) {  // one thread per split block
+          const int32_t ne = g.be[old] - g.cnt[old];
+          g.bs[nl] = ne;
+          g.be[nl] = g.be[old];
+          g.be[old] = ne;
+          g.cnt[old] = 0;
+          g.fc[old] = 0;
+          g.gc[old] = 0;
+          wg_unstable_set(w.ub, g.us, (uint32_t)old);
+          wg_unstable_set(w.ub, g.us, (uint32_t)nl);
+          best = min(best, (uint32_t)old);
+        }
+      }
+      for (uint32_t i = tid; i < nT; i += nthr) {
+        const int32_t s = T[i];
+        w.mw[s] = 0;
+        w.tb[s >> 6] = 0;
+      }
+      wg_min(&sh.cand[par ^ 1], best);
+      if (tid == 0) {
+        if (nS > 0) {
+          wg_unstable_set(w.ub, g.us, C);
+          atomicMin(&sh.cand[par ^ 1], C);
+        }
+        sh.cand[par] = kNone;
+      }
+    }
+    __syncthreads();
+    if (sh.bad) {  // workgroup-uniform
+      if (tid == 0) atomicOr(&a.ctl[1], 2u);
+      break;
+    }
+  }
+  for (uint32_t s = tid; s < n; s += nthr) a.out[s0 + s] = w.blk[s];
+  return it + 1;
+}
+
 template <class MaskT>
 __global__ void k_batch(BArgs a) {
   extern __shared__ uint64_t lds[];
@@ -339,7 +711,7 @@ __global__ void k_batch(BArgs a) {
       w.nlb = lds + 3 * nw;
       w.mw = reinterpret_cast<MaskT*>(lds + 3 * nw + n);
       w.blk = reinterpret_cast<int32_t*>(lds + 3 * nw + n + (sizeof(MaskT) * n + 7) / 8);
-      its = wg_refine<MaskT>(a, sh, w, T, S, s0, n);
+      its = wg_refine<MaskT, 1>(a, sh, w, T, S, s0, n);
     } else {
       const uint32_t b0 = a.bw_off[k];
       WArr<MaskT> w;
@@ -349,7 +721,21 @@ __global__ void k_batch(BArgs a) {
       w.ub = a.ub + b0;
       w.tb = a.tb + b0;
       w.lt = a.lt + b0;
-      its = wg_refine<MaskT>(a, sh, w, T, S, s0, n);
+      GList g;
+      g.perm = a.perm + s0;
+      g.pos = a.pos + s0;
+      g.bs = a.bs + s0;
+      g.be = a.be + s0;
+      g.cnt = a.cnt + s0;
+      g.fc = a.fc + s0;
+      g.gc = a.gc + s0;
+      g.tmp = a.tmp + s0;
+      g.rk = a.rk + s0;
+      g.fi = a.fi + s0;
+      g.ltl = a.ltl + s0;
+      g.sf = a.sf + b0;
+      g.us = a.us + b0;
+      its = wg_refine_lists<MaskT>(a, sh, w, g, T, S, s0, n);
     }
     if (threadIdx.x == 0) a.iters[k] = its;
     __syncthreads();
@@ -420,8 +806,10 @@ void free_batch(bisim_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  void* ptrs[] = {b->n_off_d, b->bw_off_d, b->order_d, b->blk, b->mw, b->nlb, b->ub,
-                  b->tb,      b->lt,       b->tl,      b->sl,  b->iters_d, b->ctl_d};
+  void* ptrs[] = {b->n_off_d, b->bw_off_d, b->order_d, b->blk, b->mw,      b->nlb,  b->ub,
+                  b->tb,      b->lt,       b->tl,      b->sl,  b->iters_d, b->ctl_d, b->perm,
+                  b->pos,     b->bs,       b->be,      b->cnt, b->fc,      b->gc,    b->tmp,
+                  b->rk,      b->fi,       b->ltl,     b->sf,  b->us};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->u) lts_destroy(b->u);
@@ -449,6 +837,19 @@ BArgs make_args(bisim_batch* b, int32_t* out) {
   a.lt = b->lt;
   a.tl = b->tl;
   a.sl = b->sl;
+  a.perm = b->perm;
+  a.pos = b->pos;
+  a.bs = b->bs;
+  a.be = b->be;
+  a.cnt = b->cnt;
+  a.fc = b->fc;
+  a.gc = b->gc;
+  a.tmp = b->tmp;
+  a.rk = b->rk;
+  a.fi = b->fi;
+  a.ltl = b->ltl;
+  a.sf = b->sf;
+  a.us = b->us;
   a.out = out;
   a.iters = b->iters_d;
   a.ctl = b->ctl_d;
@@ -707,6 +1108,13 @@ bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* 
         (st = dmalloc(&b->nlb, (size_t)N)) || (st = dmalloc(&b->ub, BW)) ||
         (st = dmalloc(&b->tb, BW)) || (st = dmalloc(&b->lt, BW)) ||
         (st = dmalloc(&b->tl, (size_t)N)) || (st = dmalloc(&b->sl, (size_t)N)) ||
+        (st = dmalloc(&b->perm, (size_t)N)) || (st = dmalloc(&b->pos, (size_t)N)) ||
+        (st = dmalloc(&b->bs, (size_t)N)) || (st = dmalloc(&b->be, (size_t)N)) ||
+        (st = dmalloc(&b->cnt, (size_t)N)) || (st = dmalloc(&b->fc, (size_t)N)) ||
+        (st = dmalloc(&b->gc, (size_t)N)) || (st = dmalloc(&b->tmp, (size_t)N)) ||
+        (st = dmalloc(&b->rk, (size_t)N)) || (st = dmalloc(&b->fi, (size_t)N)) ||
+        (st = dmalloc(&b->ltl, (size_t)N)) || (st = dmalloc(&b->sf, BW)) ||
+        (st = dmalloc(&b->us, BW)) ||
         (st = dmalloc(&b->iters_d, count)) || (st = dmalloc(&b->ctl_d, 2)))
       break;
     float ms = 0;
@@ -797,6 +1205,10 @@ bisim_status coarsest_partition_batch(bisim_batch* b, int32_t* block_id, int64_t
   float ms = 0;
   BISIM_TRY_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
   b->t_alg_ms = ms;
+  if (ctl_h[1] & 2u) {
+    set_error("coarsest_partition_batch: inconsistent block ranges in the member-list tier");
+    return BISIM_E_DEVICE;
+  }
   if (ctl_h[1]) {
     set_error("coarsest_partition_batch: an instance exceeded its iteration cap");
     return BISIM_E_ITERCAP;

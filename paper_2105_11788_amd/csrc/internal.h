@@ -90,6 +90,25 @@ __device__ __forceinline__ bool test_bit(const uint64_t* bm, uint32_t i) {
   return (bm[i >> 6] >> (i & 63)) & 1ull;
 }
 
+// Scans of block[] over all states take U chunks of 64 states per wave and
+// step, loading all of them before testing any (U > 1 pays where one
+// workgroup scans a large instance in global memory).
+// bit u set: state base0 + 64u + lane exists (< n) and block[state] == C
+template <uint32_t U>
+__device__ __forceinline__ uint32_t hit_mask(const int32_t* blk, uint32_t base0, uint32_t n,
+                                             uint32_t C) {
+  int32_t v[U];
+#pragma unroll
+  for (uint32_t u = 0; u < U; ++u) {
+    const uint32_t t = base0 + u * kWave + lane();
+    v[u] = t < n ? blk[t] : -1;
+  }
+  uint32_t m = 0;
+#pragma unroll
+  for (uint32_t u = 0; u < U; ++u) m |= ((uint32_t)v[u] == C ? 1u : 0u) << u;
+  return m;
+}
+
 // ---------------------------------------------------------------------------
 // the handle
 // ---------------------------------------------------------------------------

@@ -53,6 +53,10 @@ struct Part {
   uint32_t gtid, gthreads, gwave, gwaves;
 };
 
+// chunks per wave and step of the grid-wide block[] scans (the whole grid
+// already keeps enough loads in flight)
+constexpr uint32_t kGridScanU = 1;
+
 __device__ __forceinline__ Part part() {
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t gthreads = gridDim.x * blockDim.x;
@@ -273,9 +277,12 @@ __device__ __forceinline__ void mark_slot(const Args& a, uint32_t par, int32_t s
 // are spread over the wave's 64 lanes by a prefix sum of in-degrees.
 __device__ void phase_a_mark(const Args& a, uint32_t par, uint32_t C, const Part& p) {
   const uint32_t n = (uint32_t)a.n;
-  for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
-    const uint32_t t = base + lane();
-    const bool hit = t < n && (uint32_t)a.block[t] == C;
+  for (uint32_t base0 = p.gwave * kWave * kGridScanU; base0 < n; base0 += p.gwaves * kWave * kGridScanU) {
+   const uint32_t hm = hit_mask<kGridScanU>(a.block, base0, n, C);
+   if (__ballot(hm != 0) == 0) continue;
+   for (uint32_t u = 0; u < kGridScanU; ++u) {
+    const uint32_t t = base0 + u * kWave + lane();
+    const bool hit = (hm >> u) & 1u;
     const uint64_t hits = __ballot(hit);
     if (hits == 0) continue;
     uint32_t beg = 0, deg = 0;
@@ -310,6 +317,7 @@ __device__ void phase_a_mark(const Args& a, uint32_t par, uint32_t C, const Part
       }
       mark_slot(a, par, s, o, valid);
     }
+   }
   }
 }
 
@@ -349,16 +357,29 @@ __device__ void phase_b(const Args& a, uint32_t par, uint32_t k, const Part& p) 
   }
   if (a.ctl->ltany[par].v[0]) {
     const uint32_t n = (uint32_t)a.n;
-    for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
-      const uint32_t s = base + lane();
-      bool sp = false;
-      int32_t b = 0;
-      if (s < n) {
-        b = a.block[s];
-        sp = test_bit(a.lt, (uint32_t)b) && !test_bit(a.tb, s);
+    for (uint32_t base0 = p.gwave * kWave * kGridScanU; base0 < n;
+         base0 += p.gwaves * kWave * kGridScanU) {
+      int32_t bv[kGridScanU];
+      uint64_t lw[kGridScanU], tw[kGridScanU];
+#pragma unroll
+      for (uint32_t u = 0; u < kGridScanU; ++u) {
+        const uint32_t s = base0 + u * kWave + lane();
+        bv[u] = s < n ? a.block[s] : 0;
       }
-      if (sp) bid(a, b, (int32_t)s, epoch);
-      wave_push(a.slist, cntS, (int32_t)s, sp);
+#pragma unroll
+      for (uint32_t u = 0; u < kGridScanU; ++u) lw[u] = a.lt[(uint32_t)bv[u] >> 6];
+#pragma unroll
+      for (uint32_t u = 0; u < kGridScanU; ++u)
+        tw[u] = base0 + u * kWave < n ? a.tb[(base0 + u * kWave) >> 6] : 0ull;
+#pragma unroll
+      for (uint32_t u = 0; u < kGridScanU; ++u) {
+        const uint32_t s = base0 + u * kWave + lane();
+        const int32_t b = bv[u];
+        const bool sp =
+            s < n && ((lw[u] >> (b & 63)) & 1ull) && !((tw[u] >> (s & 63)) & 1ull);
+        if (sp) bid(a, b, (int32_t)s, epoch);
+        wave_push(a.slist, cntS, (int32_t)s, sp);
+      }
     }
   }
 }
