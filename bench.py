@@ -67,46 +67,49 @@ def log(msg):
 
 
 def phase_bytes(n: int, work: np.ndarray, nsplit: np.ndarray):
-    """Bytes each phase of each iteration must move with this layout (int32
-    ids, 64-bit mark words, 1-bit unstable/touched/leader-touched flags):
-      select+mark    n/8 (unstable bitmap) + 4n (block[] scan)
+    """Bytes each kernel of each iteration touches with this layout (int32
+    ids, 64-bit mark words and bids, 1-bit flags):
+      X (relabel + select + mark)
+                     4n block[] scan + n/4 split-flag words (read k-1's,
+                     clear k-2's) + 20 per split state of k-1 (bid read,
+                     block write, new-leader list)
                      + 8 per member of C (in_ptr pair)
                      + 24 per in-transition of C (source, rank, mark-word RMW)
                      + 8 per touched state (list append, leader test)
-      compare+elect  24 per touched state (list, block, own + leader mark words)
+      Y (compare + elect)
+                     24 per touched state (list, block, own + leader mark words)
                      + [a leader was touched] (4n block scan + n/4 flag bits)
-                     + 12 per split state (bid, list append)
-      relabel        20 per split state (list, block r/w, new-leader word)
-                     + 28 per touched state (list, mark word, touched/leader words)
-    Returns an array [iterations, 3]; the final pass (no splitter) is zero."""
+                     + 20 per split state (bid, split flag, unstable bit)
+                     + 28 per touched state of k-1 (list, mark word, flag words)
+    Returns an array [iterations, 2]; the final pass (no splitter) is zero."""
     members, edges, touched, ltany = (work[:, i].astype(np.float64) for i in range(4))
     s = nsplit.astype(np.float64)
-    out = np.stack([n / 8 + 4 * n + 8 * members + 24 * edges + 8 * touched,
-                    24 * touched + ltany * (4 * n + n / 4) + 12 * s,
-                    20 * s + 28 * touched], axis=1)
+    s_prev = np.concatenate([[0.0], s[:-1]])
+    t_prev = np.concatenate([[0.0], touched[:-1]])
+    out = np.stack([4 * n + n / 4 + 20 * s_prev + 8 * members + 24 * edges + 8 * touched,
+                    24 * touched + ltany * (4 * n + n / 4) + 20 * s + 28 * t_prev], axis=1)
     out[-1] = 0.0
     return out
 
 
 def method_bytes(n: int, m: int, mark_length: int, work: np.ndarray, nsplit: np.ndarray):
     """Bytes one iteration of the method as specified moves (Algorithm 3 with
-    int32 ids and byte flags, each pass over all transitions or states), per
-    phase kernel of this implementation:
-      select+mark    select + reset: n/8 unstable bits + L mark zeroing + n
-                     split flags; mark: 4m targets + 4m block[target] gather
-                     + 5 per transition into C
-      compare+elect  4n block + 8n slot offsets + 4n leader offsets + 2L marks
-                     + n split flags
-      relabel        2n split flags + 23 per split state (election and relabel)
+    int32 ids and byte flags, each pass over all transitions or states),
+    assigned to the kernel that does that pass's work here:
+      X  select + reset: n/8 unstable bits + L mark zeroing + n split flags;
+         mark: 4m targets + 4m block[target] gather + 5 per transition into C;
+         the previous iteration's relabel: 2n split flags + 23 per split state
+      Y  compare: 4n block + 8n slot offsets + 4n leader offsets + 2L marks
+         + n split flags
     L is the mark length (section 4.1).  The kernels skip most of this work;
     the ratio of these bytes to kernel time is therefore the rate at which the
     method's passes are completed, and can exceed the memory bandwidth."""
     edges = work[:, 1].astype(np.float64)
     s = nsplit.astype(np.float64)
+    s_prev = np.concatenate([[0.0], s[:-1]])
     n, m, L = float(n), float(m), float(mark_length)
-    out = np.stack([np.full_like(s, n / 8 + L + n) + 8 * m + 5 * edges,
-                    np.full_like(s, 17 * n + 2 * L),
-                    2 * n + 23 * s], axis=1)
+    out = np.stack([np.full_like(s, n / 8 + L + n + 2 * n) + 8 * m + 5 * edges + 23 * s_prev,
+                    np.full_like(s, 17 * n + 2 * L)], axis=1)
     out[-1] = 0.0
     return out
 
@@ -239,13 +242,13 @@ def form_plain(bisim, gen, args):
     pb = phase_bytes(L.n, r["work"], r["nsplit"])
     mb = method_bytes(L.n, L.m, st.mark_length, r["work"], r["nsplit"])
     copy_gbs = bisim.copy_bandwidth(1 << 30)
-    names = ["k_phase_a (select+mark)", "k_phase_b (compare+elect)", "k_phase_c (relabel)"]
+    names = ["k_fused_x (relabel+select+mark)", "k_fused_y (compare+elect)"]
     if args.engine == 1:
         kernel, kern_ms = "k_persistent", r["kern_ms"]
         bytes_launch, touched_launch = float(mb.sum()), float(pb.sum())
         per_phase = None
     else:
-        ms = r["phase_ms"][:3]
+        ms = r["phase_ms"][:2]
         q = int(np.argmax(ms))  # every phase runs once per iteration
         kernel = names[q]
         bytes_launch = float(mb[:-1, q].mean())
@@ -258,7 +261,7 @@ def form_plain(bisim, gen, args):
                                 "touched_bytes_per_launch": float(pb[:-1, i].mean()),
                                 "touched_GBs": float(pb[:-1, i].mean() / (ms[i] * 1e-3) / 1e9)
                                 if ms[i] > 0 else None,
-                                "samples": int(r["phase_samples"][i])} for i in range(3)}
+                                "samples": int(r["phase_samples"][i])} for i in range(2)}
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
     touched_gbs = touched_launch / (kern_ms * 1e-3) / 1e9
     log(f"{r['ms_per_step']:.2f} ms/step, #It={iters}, {kernel}: {kern_ms * 1e3:.2f} us/launch, "
@@ -408,7 +411,8 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--batch-wg", type=int, default=0,
                     help="batched form: fixed workgroup size instead of the autotuner")
-    ap.add_argument("--rescore", type=int, default=64)
+    ap.add_argument("--rescore", type=int, default=4096,
+                    help="learned form: full re-scoring period R")
     ap.add_argument("--train-lts", type=int, default=12)
     ap.add_argument("--train-steps", type=int, default=300)
     args = ap.parse_args()

@@ -23,7 +23,7 @@ static void free_handle(bisim_lts* h) {
                   h->block,     h->mw,       h->tb,     h->lt,     h->ub,     h->nlw,
                   h->tlist,     h->slist,    h->ctl,    h->sfeat,  h->acc,    h->born,
                   h->used,      h->chg,      h->us,     h->lvl,    h->lvb,    h->lvs,
-                  h->lvt,       h->lvq};
+                  h->lvt,       h->lvq,      h->sb,     h->nlist};
   for (void* p : ptrs)
     if (p) (void)hipFreeAsync(p, s);
   (void)hipStreamSynchronize(s);

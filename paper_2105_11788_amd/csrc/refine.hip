@@ -81,6 +81,19 @@ __global__ void __launch_bounds__(kT) k_phase_c(Args a, uint32_t k) {
   if (a.ctl->state.v[1]) return;
   phase_c<L, T>(a, k & 1, k, a.ctl->state.v[3], part());
 }
+// plain policy: two kernels per iteration
+__global__ void __launch_bounds__(kT) k_fused_x(Args a, uint32_t k) {
+  if (a.ctl->state.v[1]) return;
+  const Part p = part();
+  const uint32_t C = head2(a, k, p);
+  if (C == kNone) return;
+  phase_x(a, k, C, p);
+}
+__global__ void __launch_bounds__(kT) k_fused_y(Args a, uint32_t k) {
+  if (a.ctl->state.v[1]) return;
+  phase_y(a, k, part());
+}
+
 constexpr int kST = 1024;  // re-scoring + selection workgroup (learned policy)
 __global__ void __launch_bounds__(kST) k_phase_s(Args a, uint32_t k) {
   if (a.ctl->state.v[1]) return;
@@ -169,6 +182,17 @@ __global__ void __launch_bounds__(kPT) k_persistent(Args a) {
   }
   const Part p = part();
   uint32_t gen = 0;
+  if (!L) {  // plain policy: two steps per iteration
+    for (uint32_t k = 0;; ++k) {
+      const uint32_t C = head2(a, k, p);
+      if (C == kNone) break;
+      phase_x(a, k, C, p);
+      if (!grid_barrier(a.ctl, gen)) break;
+      phase_y(a, k, p);
+      if (!grid_barrier(a.ctl, gen)) break;
+    }
+    return;
+  }
   for (uint32_t k = 0;; ++k) {
     const uint32_t C = head(a, k, p);
     if (C == kNone) break;
@@ -212,13 +236,15 @@ bisim_status refine_alloc(bisim_lts* h) {
   const size_t nwd = (n + 63) / 64;
   hipStream_t s = h->stream;
   BISIM_TRY(dalloc(&h->block, n, s));
-  BISIM_TRY(dalloc(&h->mw, (size_t)h->nwords, s));
-  BISIM_TRY(dalloc(&h->tb, nwd, s));
-  BISIM_TRY(dalloc(&h->lt, nwd, s));
+  BISIM_TRY(dalloc(&h->mw, 2 * (size_t)h->nwords, s));
+  BISIM_TRY(dalloc(&h->tb, 2 * nwd, s));
+  BISIM_TRY(dalloc(&h->lt, 2 * nwd, s));
+  BISIM_TRY(dalloc(&h->sb, 2 * nwd, s));
+  BISIM_TRY(dalloc(&h->nlist, n, s));
   BISIM_TRY(dalloc(&h->ub, nwd, s));
   BISIM_TRY(dalloc(&h->us, (nwd + 63) / 64, s));
   BISIM_TRY(dalloc(&h->nlw, n, s));
-  BISIM_TRY(dalloc(&h->tlist, n, s));
+  BISIM_TRY(dalloc(&h->tlist, 2 * n, s));
   BISIM_TRY(dalloc(&h->slist, n, s));
   BISIM_TRY(dalloc(&h->ctl, 1, s));
   BISIM_TRY_HIP(hipHostMalloc((void**)&h->ctl_host, sizeof(Ctl), hipHostMallocDefault));
@@ -259,6 +285,9 @@ Args make_args(bisim_lts* h, uint32_t cap, bool learned, bool track) {
   a.us = h->us;
   a.nlw = h->nlw;
   a.tlist = h->tlist;
+  a.sb = h->sb;
+  a.nlist = h->nlist;
+  a.nwords = h->nwords;
   a.slist = h->slist;
   a.ctl = h->ctl;
   a.iter_cap = cap;
@@ -384,7 +413,7 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
       else
         hipLaunchKernelGGL(kern, dim3(grid), dim3(kT), shm, st, a, k);
     };
-    const int nph = learned ? 4 : 3;
+    const int nph = learned ? 4 : 2;
     const uint64_t pe = prof ? (uint64_t)h->profile_every : 0;
     hipEvent_t carry = nullptr;  // end of the previous iteration, if the current one is sampled
     uint32_t k = 0, chunk = 8;
@@ -417,9 +446,8 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
           else
             hipLaunchKernelGGL(k_phase_s, dim3(1), dim3(kST), lds, st, a, k);
         } else {
-          go(k_phase_a<false, false>, ends[0], 0, k);
-          go(k_phase_b<false, false>, ends[1], 0, k);
-          go(k_phase_c<false, false>, ends[2], 0, k);
+          go(k_fused_x, ends[0], 0, k);
+          go(k_fused_y, ends[1], 0, k);
         }
       }
       BISIM_TRY_HIP(hipGetLastError());
@@ -459,7 +487,7 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   for (size_t i = 0; i < sampled.size(); ++i) {
     if ((int64_t)sampled[i] + 1 >= h->last_iters) continue;  // no splitter: early-exit kernels
     hipEvent_t prev = sample_start[i];
-    for (int q = 0; q < (learned ? 4 : 3); ++q) {
+    for (int q = 0; q < (learned ? 4 : 2); ++q) {
       hipEvent_t cur = h->pev[8 * i + 1 + q];
       float pm = 0.f;
       if (hipEventElapsedTime(&pm, prev, cur) == hipSuccess) {

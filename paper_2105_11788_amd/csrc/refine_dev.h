@@ -26,6 +26,9 @@ struct Args {
   uint64_t* nlw;
   int32_t* tlist;
   int32_t* slist;
+  uint64_t* sb;     // [2][nwd] split flags (two-kernel engine)
+  int32_t* nlist;   // [n] new leaders (two-kernel engine)
+  uint64_t nwords;  // mark words per parity half
   Ctl* ctl;
   uint32_t iter_cap;
   int32_t* trace_C;
@@ -468,6 +471,281 @@ __device__ void phase_c(const Args& a, uint32_t par, uint32_t k, uint32_t C, con
   }
 }
 
+// ---------------------------------------------------------------------------
+// Plain policy in two grid-wide steps per iteration.  The relabel of
+// iteration k-1 is folded into iteration k's scan of block[]: a state whose
+// split flag (k-1) is set takes the label its old block elected, read from
+// the epoch-tagged bid (epoch k); the owner of the state writes it back, and
+// every other reader in the same step applies the same rule, which gives the
+// same answer whether or not the write-back has happened (a new label never
+// carries a bid of epoch k).  The next splitter is known without the new
+// leaders: each is larger than its block's old label, which becomes unstable
+// in the same iteration.  Marks, touched lists and split flags alternate
+// between two halves by iteration parity, so the step that needs a half
+// clean clears what the iteration before last left in it.
+//   X(k): head; relabel k-1's splits (new leaders min-reduced into the next
+//         candidate and listed); clear C, search the next smallest unstable
+//         label; mark.
+//   Y(k): compare + elect; split flags; old labels (and C, if anything
+//         split) become unstable and are min-reduced into the next candidate;
+//         k-1's new leaders become unstable; k-1's marks are cleared.
+// ---------------------------------------------------------------------------
+struct FPar {  // the half of iteration parity `par`
+  uint64_t* mw;
+  uint64_t* tb;
+  uint64_t* lt;
+  uint64_t* sb;
+  int32_t* tl;
+};
+__device__ __forceinline__ FPar fpar(const Args& a, uint32_t par) {
+  const size_t nwd = ((uint32_t)a.n + 63u) >> 6;
+  return {a.mw + par * a.nwords, a.tb + par * nwd, a.lt + par * nwd, a.sb + par * nwd,
+          a.tlist + par * (size_t)a.n};
+}
+
+// label of s during iteration k: block[s], or its block's elected leader if s
+// split in iteration k-1 and the write-back has not happened yet
+__device__ __forceinline__ int32_t lazy_label(const Args& a, const uint64_t* prev_sb, uint32_t s,
+                                              uint32_t k) {
+  const int32_t b = a.block[s];
+  if (!test_bit(prev_sb, s)) return b;
+  const uint64_t v = a.nlw[b];
+  return (uint32_t)(v >> 32) == k ? (int32_t)(kNone - (uint32_t)v) : b;
+}
+
+__device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
+  const uint32_t C = a.ctl->cand[k & 1].v[0];
+  const bool over = (k + 1 > a.iter_cap);
+  if (p.gtid == 0) {
+    Ctl* c = a.ctl;
+    if (k > 0 && a.trace_nsplit && k - 1 < a.trace_cap)
+      a.trace_nsplit[k - 1] = c->fS[(k - 1) % 3].v[0];
+    if (C == kNone || over) {
+      c->state.v[0] = k + 1;
+      c->state.v[1] = 1;
+      if (over && C != kNone) c->state.v[2] = 1;
+      if (a.trace_C && k < a.trace_cap) a.trace_C[k] = -1;
+      if (a.trace_nsplit && k < a.trace_cap) a.trace_nsplit[k] = 0;
+      if (a.trace_work && k < a.trace_cap)
+        for (int q = 0; q < 4; ++q) a.trace_work[4 * (uint64_t)k + q] = 0;
+    } else {
+      const uint32_t q = (k + 1) % 3;  // last used by iteration k-2
+      c->state.v[3] = C;
+      c->fT[q].v[0] = 0;
+      c->fS[q].v[0] = 0;
+      c->fL[q].v[0] = 0;
+      c->fW[q].v[0] = 0;
+      c->fW[q].v[1] = 0;
+      c->fN[q].v[0] = 0;
+      if (a.trace_C && k < a.trace_cap) a.trace_C[k] = (int32_t)C;
+    }
+  }
+  return (C == kNone || over) ? kNone : C;
+}
+
+__device__ __forceinline__ void mark_slot2(const Args& a, const FPar& cur, const uint64_t* prev_sb,
+                                           uint32_t slot, uint32_t k, int32_t s, int32_t o,
+                                           bool valid) {
+  bool first = false;
+  if (valid) {
+    const uint64_t bit = 1ull << (o & 63);
+    const uint64_t wi = a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6);
+    const uint64_t tbit = 1ull << (s & 63);
+    if (a.uniform) {
+      const uint64_t old = atomicOr((unsigned long long*)&cur.mw[wi], (unsigned long long)bit);
+      first = (old == 0);
+      if (first) atomicOr((unsigned long long*)&cur.tb[s >> 6], (unsigned long long)tbit);
+    } else {
+      atomicOr((unsigned long long*)&cur.mw[wi], (unsigned long long)bit);
+      first = !(atomicOr((unsigned long long*)&cur.tb[s >> 6], (unsigned long long)tbit) & tbit);
+    }
+    if (first && lazy_label(a, prev_sb, (uint32_t)s, k) == s) {
+      atomicOr((unsigned long long*)&cur.lt[s >> 6], (unsigned long long)tbit);
+      a.ctl->fL[slot].v[0] = 1;
+    }
+  }
+  wave_push(cur.tl, &a.ctl->fT[slot].v[0], s, first);
+}
+
+__device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
+  const uint32_t par = k & 1, slot = k % 3;
+  const FPar cur = fpar(a, par), prv = fpar(a, par ^ 1);
+  uint32_t* cand = &a.ctl->cand[par ^ 1].v[0];
+  const uint32_t n = (uint32_t)a.n, nwd = (n + 63u) >> 6;
+  if (p.gwave == 0) {  // clear C, search the next smallest unstable label
+    const uint32_t w0 = C >> 6;
+    const uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
+    if (lane() == 0) {
+      a.ub[w0] = bits;
+      if (bits == 0) atomicAnd((unsigned long long*)&a.us[w0 >> 6], ~(1ull << (w0 & 63)));
+    }
+    const uint32_t from = (k == 0) ? 0u : w0;  // a forced first splitter need not be the smallest
+    const uint32_t nsw = (nwd + 63u) >> 6;
+    uint32_t next = kNone;
+    for (uint32_t q = from >> 6; q < nsw; q += kWave) {
+      const uint32_t qq = q + lane();
+      uint64_t sv = qq < nsw ? a.us[qq] : 0ull;
+      if (qq == (from >> 6)) sv &= ~0ull << (from & 63);
+      if (qq == (w0 >> 6)) {
+        const uint64_t b0 = 1ull << (w0 & 63);
+        sv = bits ? (sv | b0) : (sv & ~b0);
+      }
+      const uint64_t bal = __ballot(sv != 0);
+      if (bal) {
+        const int l = __ffsll((unsigned long long)bal) - 1;
+        const uint64_t v = (uint64_t)__shfl((unsigned long long)sv, l, kWave);
+        const uint32_t word = ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)v) - 1);
+        const uint64_t wb = (word == w0) ? bits : a.ub[word];
+        if (wb) next = (word << 6) + (uint32_t)(__ffsll((unsigned long long)wb) - 1);
+        break;
+      }
+    }
+    if (lane() == 0 && next != kNone) atomicMin(cand, next);
+  }
+  for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
+    const uint32_t t = base + lane();
+    int32_t lab = -1;
+    bool lead = false;
+    if (t < n) {
+      lab = a.block[t];
+      if ((prv.sb[base >> 6] >> lane()) & 1ull) {  // split in k-1: relabel now
+        const uint64_t v = a.nlw[lab];
+        if ((uint32_t)(v >> 32) == k) {
+          lab = (int32_t)(kNone - (uint32_t)v);
+          a.block[t] = lab;
+          lead = (lab == (int32_t)t);
+        }
+      }
+    }
+    if (lane() == 0) cur.sb[base >> 6] = 0;  // flags of iteration k-2; Y(k) writes k's
+    if (__ballot(lead)) {
+      wave_push(a.nlist, &a.ctl->fN[slot].v[0], (int32_t)t, lead);
+      const uint32_t mn = wave_min_u32(lead ? t : kNone);
+      if (lane() == 0) atomicMin(cand, mn);
+    }
+    const bool hit = (uint32_t)lab == C;
+    const uint64_t hits = __ballot(hit);
+    if (hits == 0) continue;
+    uint32_t beg = 0, deg = 0;
+    if (hit) {
+      beg = a.in_ptr[t];
+      deg = a.in_ptr[t + 1] - beg;
+    }
+    const uint32_t incl = wave_incl_scan_u32(deg);
+    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+    if (a.trace_work && lane() == 0) {
+      atomicAdd(&a.ctl->fW[slot].v[0], (uint32_t)__popcll(hits));
+      atomicAdd(&a.ctl->fW[slot].v[1], total);
+    }
+    for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
+      const uint32_t e = e0 + lane();
+      const bool valid = e < total;
+      const uint32_t ee = valid ? e : total - 1;
+      uint32_t j = 0;  // owner lane: the first with incl > ee
+#pragma unroll
+      for (uint32_t step = 32; step >= 1; step >>= 1) {
+        const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
+        if (probe <= ee) j += step;
+      }
+      const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
+      const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
+      const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
+      const uint32_t edge = jb + (ee - (ji - jd));
+      int32_t s = 0, o = 0;
+      if (valid) {
+        s = a.in_src[edge];
+        o = a.in_ord[edge];
+      }
+      mark_slot2(a, cur, prv.sb, slot, k, s, o, valid);
+    }
+  }
+}
+
+// a split state s of block b (wave-uniform call)
+__device__ __forceinline__ void split2(const Args& a, const FPar& cur, uint32_t slot, uint32_t par,
+                                       uint32_t C, int32_t s, int32_t b, bool sp, uint64_t epoch) {
+  if (sp) {
+    bid(a, b, s, epoch);
+    atomicOr((unsigned long long*)&cur.sb[s >> 6], 1ull << (s & 63));
+    if (!test_bit(a.ub, (uint32_t)b)) unstable_set(a, (uint32_t)b);
+  }
+  const uint64_t bal = __ballot(sp);
+  if (bal) {
+    const uint32_t mb = wave_min_u32(sp ? (uint32_t)b : kNone);
+    if (lane() == 0) {
+      atomicAdd(&a.ctl->fS[slot].v[0], (uint32_t)__popcll(bal));
+      atomicMin(&a.ctl->cand[par ^ 1].v[0], mb < C ? mb : C);
+      if (!test_bit(a.ub, C)) unstable_set(a, C);  // anything split: C again
+    }
+  }
+}
+
+__device__ void phase_y(const Args& a, uint32_t k, const Part& p) {
+  const uint32_t par = k & 1, slot = k % 3, pslot = (k + 2) % 3;
+  const FPar cur = fpar(a, par), prv = fpar(a, par ^ 1);
+  const uint64_t epoch = (uint64_t)(k + 1) << 32;
+  const uint32_t C = a.ctl->state.v[3];
+  const uint32_t nT = a.ctl->fT[slot].v[0];
+  for (uint32_t i0 = p.gwave * kWave; i0 < nT; i0 += p.gwaves * kWave) {
+    const uint32_t i = i0 + lane();
+    bool sp = false;
+    int32_t s = 0, b = 0;
+    if (i < nT) {
+      s = cur.tl[i];
+      b = a.block[s];
+      if (s != b) {
+        if (a.uniform) {
+          sp = cur.mw[s] != cur.mw[b];
+        } else {
+          const uint32_t w0 = a.woff[s], w1 = a.woff[s + 1], wb = a.woff[b];
+          for (uint32_t q = 0; q < w1 - w0; ++q)
+            if (cur.mw[w0 + q] != cur.mw[wb + q]) {
+              sp = true;
+              break;
+            }
+        }
+      }
+    }
+    split2(a, cur, slot, par, C, s, b, sp, epoch);
+  }
+  if (a.ctl->fL[slot].v[0]) {  // untouched members of blocks whose leader was touched
+    const uint32_t n = (uint32_t)a.n;
+    for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
+      const uint32_t s = base + lane();
+      bool sp = false;
+      int32_t b = 0;
+      if (s < n) {
+        b = a.block[s];
+        sp = test_bit(cur.lt, (uint32_t)b) && !((cur.tb[base >> 6] >> lane()) & 1ull);
+      }
+      split2(a, cur, slot, par, C, (int32_t)s, b, sp, epoch);
+    }
+  }
+  const uint32_t nN = a.ctl->fN[slot].v[0];  // new leaders of k-1
+  for (uint32_t i = p.gtid; i < nN; i += p.gthreads) unstable_set(a, (uint32_t)a.nlist[i]);
+  const uint32_t nTp = k > 0 ? a.ctl->fT[pslot].v[0] : 0u;  // k-1's marks
+  for (uint32_t i = p.gtid; i < nTp; i += p.gthreads) {
+    const int32_t s = prv.tl[i];
+    if (a.uniform) {
+      prv.mw[s] = 0;
+    } else {
+      for (uint32_t q = a.woff[s]; q < a.woff[s + 1]; ++q) prv.mw[q] = 0;
+    }
+    prv.tb[s >> 6] = 0;
+    prv.lt[s >> 6] = 0;
+  }
+  if (p.gtid == 0) {
+    a.ctl->cand[par].v[0] = kNone;  // read by X(k); reused by iteration k+2
+    if (a.trace_work && k < a.trace_cap) {
+      int64_t* w = a.trace_work + 4 * (uint64_t)k;
+      w[0] = a.ctl->fW[slot].v[0];
+      w[1] = a.ctl->fW[slot].v[1];
+      w[2] = nT;
+      w[3] = a.ctl->fL[slot].v[0];
+    }
+  }
+}
+
 // S (learned policy, one workgroup): re-score the labels that changed in this
 // iteration (both labels of every split block, and C, whose "used" feature
 // changed), move them between levels (all removals before all insertions, so
@@ -546,7 +824,7 @@ __global__ void k_init_run(Args a, const int32_t* __restrict__ pre, uint32_t fir
     a.block[s] = pre[s];
     a.nlw[s] = 0;
   }
-  for (uint64_t w = p.gtid; w < nwords; w += p.gthreads) a.mw[w] = 0;
+  for (uint64_t w = p.gtid; w < 2 * nwords; w += p.gthreads) a.mw[w] = 0;
   const uint32_t nwd = (n + 63u) >> 6;
   for (uint32_t w = p.gtid; w < nwd; w += p.gthreads) {
     uint64_t bits = 0;
@@ -554,8 +832,9 @@ __global__ void k_init_run(Args a, const int32_t* __restrict__ pre, uint32_t fir
     for (uint32_t j = 0; j < 64 && s0 + j < n; ++j)
       if ((uint32_t)pre[s0 + j] == s0 + j) bits |= 1ull << j;
     a.ub[w] = bits;
-    a.tb[w] = 0;
-    a.lt[w] = 0;
+    a.tb[w] = a.tb[nwd + w] = 0;
+    a.lt[w] = a.lt[nwd + w] = 0;
+    a.sb[w] = a.sb[nwd + w] = 0;
   }
   if (blockIdx.x == 0) {
     uint32_t* c = reinterpret_cast<uint32_t*>(a.ctl);

@@ -114,6 +114,36 @@ def test_batch_errors(B):
     assert e.value.status == B.E_UNSUPPORTED
 
 
+def test_batch_4096_up_to_200k_sampled(B):
+    """The full batch shape (4096 instances, log-uniform 100..200k states,
+    ~0.65G transitions) in the configuration the benchmark times: canonical
+    labels for every instance, the partition of a sample (always including the
+    largest instance) vs the oracle, #It vs the lock-step oracle on small ones."""
+    insts = gen.batch(count=4096, n_lo=100, n_hi=200_000, seed=1)
+    print(f"[batch-200k] generated {len(insts)} instances", flush=True)
+    with B.Batch(insts) as b:
+        b.set_option(B.BOPT_WG_SIZE, 1024)
+        out, its, st = b.run()
+        blocks = b.split(out.numpy())
+    print(f"[batch-200k] ran: max #It {its.max()}, global instances {st['global_instances']}",
+          flush=True)
+    assert st["global_instances"] > 0
+    for k, (L, blk) in enumerate(zip(insts, blocks)):
+        ids = np.arange(L.n)
+        assert (blk <= ids).all() and (blk[blk] == blk).all(), k  # smallest member labels
+        assert its[k] >= len(np.unique(blk)) + 1, k
+    rng = np.random.default_rng(7)
+    sizes = np.array([x.n for x in insts])
+    sample = set(rng.choice(len(insts), 20, replace=False).tolist()) | {int(np.argmax(sizes))}
+    for k in sorted(sample):
+        L = insts[k]
+        ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        assert (blocks[k] == ks).all(), (k, L.n)
+        if L.n <= 3000:
+            r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init)
+            assert its[k] == r["iters"], (k, its[k], r["iters"])
+
+
 def test_batch_4096_up_to_10k_full(B):
     """4096 instances, log-uniform 100..10k states, Poisson(6), K ~ U{1..32},
     half planted: every instance's partition vs the oracle, #It on a sample."""
