@@ -54,6 +54,7 @@ struct Ctl {
   Line fL[3];     // v[0]: some block leader was touched
   Line fW[3];     // traced runs only: v[0] members of C, v[1] in-transitions of C
   Line fN[3];     // v[0]: new leaders of the previous iteration's splits
+  Line fC[3];     // v[0]: the splitter
   Line state;     // v[0] iterations done, v[1] done flag, v[2] iteration cap hit,
                   // v[3] current splitter, v[4] learned priority structure inconsistent
   Line bar;       // v[0] group arrivals, v[1] generation, v[2] abort

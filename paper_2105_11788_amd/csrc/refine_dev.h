@@ -531,6 +531,7 @@ __device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
     } else {
       const uint32_t q = (k + 1) % 3;  // last used by iteration k-2
       c->state.v[3] = C;
+      c->fC[k % 3].v[0] = C;
       c->fT[q].v[0] = 0;
       c->fS[q].v[0] = 0;
       c->fL[q].v[0] = 0;
@@ -548,6 +549,9 @@ __device__ __forceinline__ void mark_slot2(const Args& a, const FPar& cur, const
                                            bool valid) {
   bool first = false;
   if (valid) {
+    // operands of the leader test, loaded before the mark atomic is waited on
+    const int32_t bl = a.block[s];
+    const bool flagged = test_bit(prev_sb, (uint32_t)s);
     const uint64_t bit = 1ull << (o & 63);
     const uint64_t wi = a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6);
     const uint64_t tbit = 1ull << (s & 63);
@@ -559,9 +563,16 @@ __device__ __forceinline__ void mark_slot2(const Args& a, const FPar& cur, const
       atomicOr((unsigned long long*)&cur.mw[wi], (unsigned long long)bit);
       first = !(atomicOr((unsigned long long*)&cur.tb[s >> 6], (unsigned long long)tbit) & tbit);
     }
-    if (first && lazy_label(a, prev_sb, (uint32_t)s, k) == s) {
-      atomicOr((unsigned long long*)&cur.lt[s >> 6], (unsigned long long)tbit);
-      a.ctl->fL[slot].v[0] = 1;
+    if (first) {
+      int32_t lab = bl;  // lazy_label, with its first two loads already issued
+      if (flagged) {
+        const uint64_t v = a.nlw[bl];
+        if ((uint32_t)(v >> 32) == k) lab = (int32_t)(kNone - (uint32_t)v);
+      }
+      if (lab == s) {
+        atomicOr((unsigned long long*)&cur.lt[s >> 6], (unsigned long long)tbit);
+        a.ctl->fL[slot].v[0] = 1;
+      }
     }
   }
   wave_push(cur.tl, &a.ctl->fT[slot].v[0], s, first);
@@ -573,11 +584,21 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
   uint32_t* cand = &a.ctl->cand[par ^ 1].v[0];
   const uint32_t n = (uint32_t)a.n, nwd = (n + 63u) >> 6;
   if (p.gwave == 0) {  // clear C, search the next smallest unstable label
+    // the previous splitter is unstable again if anything split (unless it
+    // is C itself); it is folded in here, where nothing else writes the set
+    uint32_t pc = kNone;
+    if (k > 0 && a.ctl->fS[(k - 1) % 3].v[0] != 0) pc = a.ctl->fC[(k - 1) % 3].v[0];
+    if (pc == C) pc = kNone;
     const uint32_t w0 = C >> 6;
-    const uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
+    uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
+    if (pc != kNone && (pc >> 6) == w0) bits |= 1ull << (pc & 63);
     if (lane() == 0) {
       a.ub[w0] = bits;
       if (bits == 0) atomicAnd((unsigned long long*)&a.us[w0 >> 6], ~(1ull << (w0 & 63)));
+      if (pc != kNone && (pc >> 6) != w0) {
+        atomicOr((unsigned long long*)&a.ub[pc >> 6], 1ull << (pc & 63));
+        atomicOr((unsigned long long*)&a.us[pc >> 12], 1ull << ((pc >> 6) & 63));
+      }
     }
     const uint32_t from = (k == 0) ? 0u : w0;  // a forced first splitter need not be the smallest
     const uint32_t nsw = (nwd + 63u) >> 6;
@@ -600,6 +621,7 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
         break;
       }
     }
+    if (pc < next) next = pc;  // its bit may not be visible to this search yet
     if (lane() == 0 && next != kNone) atomicMin(cand, next);
   }
   for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
@@ -664,18 +686,25 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
 // a split state s of block b (wave-uniform call)
 __device__ __forceinline__ void split2(const Args& a, const FPar& cur, uint32_t slot, uint32_t par,
                                        uint32_t C, int32_t s, int32_t b, bool sp, uint64_t epoch) {
+  // every atomic here is fire-and-forget: no result is waited on
   if (sp) {
-    bid(a, b, s, epoch);
+    atomicMax((unsigned long long*)&a.nlw[b],
+              (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
     atomicOr((unsigned long long*)&cur.sb[s >> 6], 1ull << (s & 63));
-    if (!test_bit(a.ub, (uint32_t)b)) unstable_set(a, (uint32_t)b);
+    const uint32_t w = (uint32_t)b >> 6;
+    if (!((a.ub[w] >> (b & 63)) & 1ull)) {  // old label unstable (sets only in this step)
+      atomicOr((unsigned long long*)&a.ub[w], 1ull << (b & 63));
+      atomicOr((unsigned long long*)&a.us[w >> 6], 1ull << (w & 63));
+    }
   }
   const uint64_t bal = __ballot(sp);
   if (bal) {
     const uint32_t mb = wave_min_u32(sp ? (uint32_t)b : kNone);
     if (lane() == 0) {
       atomicAdd(&a.ctl->fS[slot].v[0], (uint32_t)__popcll(bal));
+      // anything split: C is a candidate again (its unstable bit is set by
+      // the next step's selection)
       atomicMin(&a.ctl->cand[par ^ 1].v[0], mb < C ? mb : C);
-      if (!test_bit(a.ub, C)) unstable_set(a, C);  // anything split: C again
     }
   }
 }
@@ -722,7 +751,11 @@ __device__ void phase_y(const Args& a, uint32_t k, const Part& p) {
     }
   }
   const uint32_t nN = a.ctl->fN[slot].v[0];  // new leaders of k-1
-  for (uint32_t i = p.gtid; i < nN; i += p.gthreads) unstable_set(a, (uint32_t)a.nlist[i]);
+  for (uint32_t i = p.gtid; i < nN; i += p.gthreads) {
+    const uint32_t t = (uint32_t)a.nlist[i], w = t >> 6;
+    atomicOr((unsigned long long*)&a.ub[w], 1ull << (t & 63));
+    atomicOr((unsigned long long*)&a.us[w >> 6], 1ull << (w & 63));
+  }
   const uint32_t nTp = k > 0 ? a.ctl->fT[pslot].v[0] : 0u;  // k-1's marks
   for (uint32_t i = p.gtid; i < nTp; i += p.gthreads) {
     const int32_t s = prv.tl[i];
