@@ -74,20 +74,21 @@ def phase_bytes(n: int, work: np.ndarray, nsplit: np.ndarray):
                      clear k-2's) + 20 per split state of k-1 (bid read,
                      block write, new-leader list)
                      + 8 per member of C (in_ptr pair)
-                     + 24 per in-transition of C (source, rank, mark-word RMW)
-                     + 8 per touched state (list append, leader test)
-      Y (compare + elect)
-                     24 per touched state (list, block, own + leader mark words)
-                     + [a leader was touched] (4n block scan + n/4 flag bits)
+                     + 40 per in-transition of C (source, rank, block and
+                       split flag of the source, mark-word and touched-word RMW)
+      Y (compare + elect, clear k-1's marks)
+                     4n block[] scan + n/4 touched words (this and the other
+                     half) + n/8 leader-touched words
+                     + 16 per touched state (own and leader mark words)
                      + 20 per split state (bid, split flag, unstable bit)
-                     + 28 per touched state of k-1 (list, mark word, flag words)
+                     + 24 per touched state of k-1 (mark word, flag words)
     Returns an array [iterations, 2]; the final pass (no splitter) is zero."""
-    members, edges, touched, ltany = (work[:, i].astype(np.float64) for i in range(4))
+    members, edges, touched = (work[:, i].astype(np.float64) for i in range(3))
     s = nsplit.astype(np.float64)
     s_prev = np.concatenate([[0.0], s[:-1]])
     t_prev = np.concatenate([[0.0], touched[:-1]])
-    out = np.stack([4 * n + n / 4 + 20 * s_prev + 8 * members + 24 * edges + 8 * touched,
-                    24 * touched + ltany * (4 * n + n / 4) + 20 * s + 28 * t_prev], axis=1)
+    out = np.stack([4 * n + n / 4 + 20 * s_prev + 8 * members + 40 * edges,
+                    4 * n + n / 4 + n / 8 + 16 * touched + 20 * s + 24 * t_prev], axis=1)
     out[-1] = 0.0
     return out
 

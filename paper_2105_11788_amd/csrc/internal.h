@@ -49,10 +49,10 @@ struct Ctl {
   Line cntC[2];   // learned policy: changed (old, new) block pairs this iteration
   // plain policy, two kernels per iteration: counters of iteration k in slot
   // k % 3 (a slot is read up to the iteration after and reset two later)
-  Line fT[3];     // v[0]: touched-state list length
   Line fS[3];     // v[0]: split states
   Line fL[3];     // v[0]: some block leader was touched
-  Line fW[3];     // traced runs only: v[0] members of C, v[1] in-transitions of C
+  Line fW[3];     // traced runs only: v[0] members of C, v[1] in-transitions of C,
+                  // v[2] touched states
   Line fN[3];     // v[0]: new leaders of the previous iteration's splits
   Line fC[3];     // v[0]: the splitter
   Line state;     // v[0] iterations done, v[1] done flag, v[2] iteration cap hit,
@@ -143,8 +143,8 @@ struct bisim_lts {
   int64_t mark_length = 0;
 
   // per-run working set
-  // (mw, tb, lt, tlist and sb hold two halves, one per iteration parity, for
-  // the two-kernel plain engine; the other engines use the first half)
+  // (mw, tb, lt and sb hold two halves, one per iteration parity, for the
+  // two-step plain engine; the three-step path uses the first half)
   int32_t* block = nullptr;  // [n]
   uint64_t* mw = nullptr;    // [2][nwords] packed marks
   uint64_t* tb = nullptr;    // [2][ceil(n/64)] touched states
@@ -153,7 +153,7 @@ struct bisim_lts {
   uint64_t* ub = nullptr;    // [ceil(n/64)] unstable block labels
   uint64_t* us = nullptr;    // [ceil(n/4096)] summary: bit w set iff ub[w] != 0
   uint64_t* nlw = nullptr;   // [n] (epoch << 32) | ~state, max-reduced
-  int32_t* tlist = nullptr;  // [2][n]
+  int32_t* tlist = nullptr;  // [n]
   int32_t* slist = nullptr;  // [n]
   int32_t* nlist = nullptr;  // [n] new leaders (two-kernel engine)
   bisim::Ctl* ctl = nullptr;

@@ -244,7 +244,7 @@ bisim_status refine_alloc(bisim_lts* h) {
   BISIM_TRY(dalloc(&h->ub, nwd, s));
   BISIM_TRY(dalloc(&h->us, (nwd + 63) / 64, s));
   BISIM_TRY(dalloc(&h->nlw, n, s));
-  BISIM_TRY(dalloc(&h->tlist, 2 * n, s));
+  BISIM_TRY(dalloc(&h->tlist, n, s));
   BISIM_TRY(dalloc(&h->slist, n, s));
   BISIM_TRY(dalloc(&h->ctl, 1, s));
   BISIM_TRY_HIP(hipHostMalloc((void**)&h->ctl_host, sizeof(Ctl), hipHostMallocDefault));

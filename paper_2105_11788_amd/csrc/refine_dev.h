@@ -484,23 +484,24 @@ __device__ void phase_c(const Args& a, uint32_t par, uint32_t k, uint32_t C, con
 // between two halves by iteration parity, so the step that needs a half
 // clean clears what the iteration before last left in it.
 //   X(k): head; relabel k-1's splits (new leaders min-reduced into the next
-//         candidate and listed); clear C, search the next smallest unstable
-//         label; mark.
-//   Y(k): compare + elect; split flags; old labels (and C, if anything
-//         split) become unstable and are min-reduced into the next candidate;
-//         k-1's new leaders become unstable; k-1's marks are cleared.
+//         candidate and listed); re-mark the previous splitter if anything
+//         split; clear C, search the next smallest unstable label; mark
+//         (marks, touched and leader-touched bits; no lists).
+//   Y(k): one pass over all states: compare touched states with their
+//         leader, untouched members of leader-touched blocks split; elect;
+//         split flags; old labels become unstable and, with C if anything
+//         split, are min-reduced into the next candidate; k-1's marks are
+//         cleared in the same pass; k-1's new leaders become unstable.
 // ---------------------------------------------------------------------------
 struct FPar {  // the half of iteration parity `par`
   uint64_t* mw;
   uint64_t* tb;
   uint64_t* lt;
   uint64_t* sb;
-  int32_t* tl;
 };
 __device__ __forceinline__ FPar fpar(const Args& a, uint32_t par) {
   const size_t nwd = ((uint32_t)a.n + 63u) >> 6;
-  return {a.mw + par * a.nwords, a.tb + par * nwd, a.lt + par * nwd, a.sb + par * nwd,
-          a.tlist + par * (size_t)a.n};
+  return {a.mw + par * a.nwords, a.tb + par * nwd, a.lt + par * nwd, a.sb + par * nwd};
 }
 
 // label of s during iteration k: block[s], or its block's elected leader if s
@@ -518,8 +519,17 @@ __device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
   const bool over = (k + 1 > a.iter_cap);
   if (p.gtid == 0) {
     Ctl* c = a.ctl;
-    if (k > 0 && a.trace_nsplit && k - 1 < a.trace_cap)
-      a.trace_nsplit[k - 1] = c->fS[(k - 1) % 3].v[0];
+    if (k > 0 && k - 1 < a.trace_cap) {  // iteration k-1's counters are final now
+      const uint32_t q = (k - 1) % 3;
+      if (a.trace_nsplit) a.trace_nsplit[k - 1] = c->fS[q].v[0];
+      if (a.trace_work) {
+        int64_t* w = a.trace_work + 4 * (uint64_t)(k - 1);
+        w[0] = c->fW[q].v[0];
+        w[1] = c->fW[q].v[1];
+        w[2] = c->fW[q].v[2];
+        w[3] = c->fL[q].v[0];
+      }
+    }
     if (C == kNone || over) {
       c->state.v[0] = k + 1;
       c->state.v[1] = 1;
@@ -532,11 +542,11 @@ __device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
       const uint32_t q = (k + 1) % 3;  // last used by iteration k-2
       c->state.v[3] = C;
       c->fC[k % 3].v[0] = C;
-      c->fT[q].v[0] = 0;
       c->fS[q].v[0] = 0;
       c->fL[q].v[0] = 0;
       c->fW[q].v[0] = 0;
       c->fW[q].v[1] = 0;
+      c->fW[q].v[2] = 0;
       c->fN[q].v[0] = 0;
       if (a.trace_C && k < a.trace_cap) a.trace_C[k] = (int32_t)C;
     }
@@ -544,38 +554,29 @@ __device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
   return (C == kNone || over) ? kNone : C;
 }
 
-__device__ __forceinline__ void mark_slot2(const Args& a, const FPar& cur, const uint64_t* prev_sb,
-                                           uint32_t slot, uint32_t k, int32_t s, int32_t o,
-                                           bool valid) {
-  bool first = false;
-  if (valid) {
-    // operands of the leader test, loaded before the mark atomic is waited on
-    const int32_t bl = a.block[s];
-    const bool flagged = test_bit(prev_sb, (uint32_t)s);
-    const uint64_t bit = 1ull << (o & 63);
-    const uint64_t wi = a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6);
-    const uint64_t tbit = 1ull << (s & 63);
-    if (a.uniform) {
-      const uint64_t old = atomicOr((unsigned long long*)&cur.mw[wi], (unsigned long long)bit);
-      first = (old == 0);
-      if (first) atomicOr((unsigned long long*)&cur.tb[s >> 6], (unsigned long long)tbit);
-    } else {
-      atomicOr((unsigned long long*)&cur.mw[wi], (unsigned long long)bit);
-      first = !(atomicOr((unsigned long long*)&cur.tb[s >> 6], (unsigned long long)tbit) & tbit);
-    }
-    if (first) {
-      int32_t lab = bl;  // lazy_label, with its first two loads already issued
-      if (flagged) {
-        const uint64_t v = a.nlw[bl];
-        if ((uint32_t)(v >> 32) == k) lab = (int32_t)(kNone - (uint32_t)v);
-      }
-      if (lab == s) {
-        atomicOr((unsigned long long*)&cur.lt[s >> 6], (unsigned long long)tbit);
-        a.ctl->fL[slot].v[0] = 1;
-      }
-    }
+// chunks of 64 states per wave and step of the two-step engine's scans; all
+// their loads are issued before any is used
+constexpr uint32_t kFusedU = 2;
+
+// mark slot o of state s; every atomic is fire-and-forget (the touched set is
+// the tb bitmap, read back by the next step's scan)
+__device__ __forceinline__ void mark_slot3(const Args& a, const FPar& cur, const uint64_t* prev_sb,
+                                           uint32_t slot, uint32_t k, int32_t s, int32_t o) {
+  const int32_t bl = a.block[s];
+  const bool flagged = test_bit(prev_sb, (uint32_t)s);
+  const uint64_t wi = a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6);
+  const uint64_t tbit = 1ull << (s & 63);
+  atomicOr((unsigned long long*)&cur.mw[wi], 1ull << (o & 63));
+  atomicOr((unsigned long long*)&cur.tb[s >> 6], (unsigned long long)tbit);
+  int32_t lab = bl;  // lazy_label, with its loads issued before the atomics
+  if (flagged) {
+    const uint64_t v = a.nlw[bl];
+    if ((uint32_t)(v >> 32) == k) lab = (int32_t)(kNone - (uint32_t)v);
   }
-  wave_push(cur.tl, &a.ctl->fT[slot].v[0], s, first);
+  if (lab == s) {  // a touched leader
+    atomicOr((unsigned long long*)&cur.lt[s >> 6], (unsigned long long)tbit);
+    a.ctl->fL[slot].v[0] = 1;
+  }
 }
 
 __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
@@ -624,13 +625,22 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
     if (pc < next) next = pc;  // its bit may not be visible to this search yet
     if (lane() == 0 && next != kNone) atomicMin(cand, next);
   }
-  for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
-    const uint32_t t = base + lane();
-    int32_t lab = -1;
-    bool lead = false;
-    if (t < n) {
-      lab = a.block[t];
-      if ((prv.sb[base >> 6] >> lane()) & 1ull) {  // split in k-1: relabel now
+  for (uint32_t base0 = p.gwave * kWave * kFusedU; base0 < n;
+       base0 += p.gwaves * kWave * kFusedU) {
+    int32_t bv[kFusedU];
+    uint64_t fw[kFusedU];
+#pragma unroll
+    for (uint32_t u = 0; u < kFusedU; ++u) {
+      const uint32_t base = base0 + u * kWave, t = base + lane();
+      bv[u] = t < n ? a.block[t] : -1;
+      fw[u] = base < n ? prv.sb[base >> 6] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kFusedU; ++u) {
+      const uint32_t base = base0 + u * kWave, t = base + lane();
+      int32_t lab = bv[u];
+      bool lead = false;
+      if (t < n && ((fw[u] >> lane()) & 1ull)) {  // split in k-1: relabel now
         const uint64_t v = a.nlw[lab];
         if ((uint32_t)(v >> 32) == k) {
           lab = (int32_t)(kNone - (uint32_t)v);
@@ -638,55 +648,50 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
           lead = (lab == (int32_t)t);
         }
       }
-    }
-    if (lane() == 0) cur.sb[base >> 6] = 0;  // flags of iteration k-2; Y(k) writes k's
-    if (__ballot(lead)) {
-      wave_push(a.nlist, &a.ctl->fN[slot].v[0], (int32_t)t, lead);
-      const uint32_t mn = wave_min_u32(lead ? t : kNone);
-      if (lane() == 0) atomicMin(cand, mn);
-    }
-    const bool hit = (uint32_t)lab == C;
-    const uint64_t hits = __ballot(hit);
-    if (hits == 0) continue;
-    uint32_t beg = 0, deg = 0;
-    if (hit) {
-      beg = a.in_ptr[t];
-      deg = a.in_ptr[t + 1] - beg;
-    }
-    const uint32_t incl = wave_incl_scan_u32(deg);
-    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
-    if (a.trace_work && lane() == 0) {
-      atomicAdd(&a.ctl->fW[slot].v[0], (uint32_t)__popcll(hits));
-      atomicAdd(&a.ctl->fW[slot].v[1], total);
-    }
-    for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
-      const uint32_t e = e0 + lane();
-      const bool valid = e < total;
-      const uint32_t ee = valid ? e : total - 1;
-      uint32_t j = 0;  // owner lane: the first with incl > ee
+      if (base < n && lane() == 0) cur.sb[base >> 6] = 0;  // k-2's flags; Y(k) writes k's
+      if (__ballot(lead)) {
+        wave_push(a.nlist, &a.ctl->fN[slot].v[0], (int32_t)t, lead);
+        const uint32_t mn = wave_min_u32(lead ? t : kNone);
+        if (lane() == 0) atomicMin(cand, mn);
+      }
+      const bool hit = (uint32_t)lab == C;
+      const uint64_t hits = __ballot(hit);
+      if (hits == 0) continue;
+      uint32_t beg = 0, deg = 0;
+      if (hit) {
+        beg = a.in_ptr[t];
+        deg = a.in_ptr[t + 1] - beg;
+      }
+      const uint32_t incl = wave_incl_scan_u32(deg);
+      const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+      if (a.trace_work && lane() == 0) {
+        atomicAdd(&a.ctl->fW[slot].v[0], (uint32_t)__popcll(hits));
+        atomicAdd(&a.ctl->fW[slot].v[1], total);
+      }
+      for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
+        const uint32_t e = e0 + lane();
+        const bool valid = e < total;
+        const uint32_t ee = valid ? e : total - 1;
+        uint32_t j = 0;  // owner lane: the first with incl > ee
 #pragma unroll
-      for (uint32_t step = 32; step >= 1; step >>= 1) {
-        const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
-        if (probe <= ee) j += step;
+        for (uint32_t step = 32; step >= 1; step >>= 1) {
+          const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
+          if (probe <= ee) j += step;
+        }
+        const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
+        const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
+        const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
+        const uint32_t edge = jb + (ee - (ji - jd));
+        if (valid) mark_slot3(a, cur, prv.sb, slot, k, a.in_src[edge], a.in_ord[edge]);
       }
-      const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
-      const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
-      const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
-      const uint32_t edge = jb + (ee - (ji - jd));
-      int32_t s = 0, o = 0;
-      if (valid) {
-        s = a.in_src[edge];
-        o = a.in_ord[edge];
-      }
-      mark_slot2(a, cur, prv.sb, slot, k, s, o, valid);
     }
   }
 }
 
-// a split state s of block b (wave-uniform call)
+// a split state s of block b (wave-uniform call); every atomic here is
+// fire-and-forget
 __device__ __forceinline__ void split2(const Args& a, const FPar& cur, uint32_t slot, uint32_t par,
                                        uint32_t C, int32_t s, int32_t b, bool sp, uint64_t epoch) {
-  // every atomic here is fire-and-forget: no result is waited on
   if (sp) {
     atomicMax((unsigned long long*)&a.nlw[b],
               (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
@@ -709,45 +714,66 @@ __device__ __forceinline__ void split2(const Args& a, const FPar& cur, uint32_t 
   }
 }
 
+// Y(k): one pass over all states.  A touched state (tb) splits iff its marks
+// differ from its leader's; an untouched one iff its leader was touched (lt).
+// The same pass clears what iteration k-1 left in the other half.
 __device__ void phase_y(const Args& a, uint32_t k, const Part& p) {
-  const uint32_t par = k & 1, slot = k % 3, pslot = (k + 2) % 3;
+  const uint32_t par = k & 1, slot = k % 3;
   const FPar cur = fpar(a, par), prv = fpar(a, par ^ 1);
   const uint64_t epoch = (uint64_t)(k + 1) << 32;
   const uint32_t C = a.ctl->state.v[3];
-  const uint32_t nT = a.ctl->fT[slot].v[0];
-  for (uint32_t i0 = p.gwave * kWave; i0 < nT; i0 += p.gwaves * kWave) {
-    const uint32_t i = i0 + lane();
-    bool sp = false;
-    int32_t s = 0, b = 0;
-    if (i < nT) {
-      s = cur.tl[i];
-      b = a.block[s];
-      if (s != b) {
-        if (a.uniform) {
-          sp = cur.mw[s] != cur.mw[b];
-        } else {
-          const uint32_t w0 = a.woff[s], w1 = a.woff[s + 1], wb = a.woff[b];
-          for (uint32_t q = 0; q < w1 - w0; ++q)
-            if (cur.mw[w0 + q] != cur.mw[wb + q]) {
-              sp = true;
-              break;
+  const uint32_t n = (uint32_t)a.n;
+  for (uint32_t base0 = p.gwave * kWave * kFusedU; base0 < n;
+       base0 += p.gwaves * kWave * kFusedU) {
+    int32_t bv[kFusedU];
+    uint64_t tw[kFusedU], pw[kFusedU];
+#pragma unroll
+    for (uint32_t u = 0; u < kFusedU; ++u) {
+      const uint32_t base = base0 + u * kWave, s = base + lane();
+      bv[u] = s < n ? a.block[s] : 0;
+      tw[u] = base < n ? cur.tb[base >> 6] : 0ull;
+      pw[u] = base < n ? prv.tb[base >> 6] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kFusedU; ++u) {
+      const uint32_t base = base0 + u * kWave, s = base + lane();
+      const int32_t b = bv[u];
+      const bool touched = (tw[u] >> lane()) & 1ull;
+      bool sp = false;
+      if (s < n) {
+        if (touched) {
+          if ((int32_t)s != b) {
+            if (a.uniform) {
+              sp = cur.mw[s] != cur.mw[b];
+            } else {
+              const uint32_t w0 = a.woff[s], w1 = a.woff[s + 1], wb = a.woff[b];
+              for (uint32_t q = 0; q < w1 - w0; ++q)
+                if (cur.mw[w0 + q] != cur.mw[wb + q]) {
+                  sp = true;
+                  break;
+                }
             }
+          }
+        } else {
+          sp = test_bit(cur.lt, (uint32_t)b);
         }
       }
-    }
-    split2(a, cur, slot, par, C, s, b, sp, epoch);
-  }
-  if (a.ctl->fL[slot].v[0]) {  // untouched members of blocks whose leader was touched
-    const uint32_t n = (uint32_t)a.n;
-    for (uint32_t base = p.gwave * kWave; base < n; base += p.gwaves * kWave) {
-      const uint32_t s = base + lane();
-      bool sp = false;
-      int32_t b = 0;
-      if (s < n) {
-        b = a.block[s];
-        sp = test_bit(cur.lt, (uint32_t)b) && !((cur.tb[base >> 6] >> lane()) & 1ull);
-      }
       split2(a, cur, slot, par, C, (int32_t)s, b, sp, epoch);
+      if (a.trace_work && lane() == 0 && tw[u])
+        atomicAdd(&a.ctl->fW[slot].v[2], (uint32_t)__popcll(tw[u]));
+      if (pw[u]) {  // iteration k-1's marks in this chunk
+        if ((pw[u] >> lane()) & 1ull) {
+          if (a.uniform) {
+            prv.mw[s] = 0;
+          } else {
+            for (uint32_t q = a.woff[s]; q < a.woff[s + 1]; ++q) prv.mw[q] = 0;
+          }
+        }
+        if (lane() == 0) {
+          prv.tb[base >> 6] = 0;
+          prv.lt[base >> 6] = 0;
+        }
+      }
     }
   }
   const uint32_t nN = a.ctl->fN[slot].v[0];  // new leaders of k-1
@@ -756,27 +782,7 @@ __device__ void phase_y(const Args& a, uint32_t k, const Part& p) {
     atomicOr((unsigned long long*)&a.ub[w], 1ull << (t & 63));
     atomicOr((unsigned long long*)&a.us[w >> 6], 1ull << (w & 63));
   }
-  const uint32_t nTp = k > 0 ? a.ctl->fT[pslot].v[0] : 0u;  // k-1's marks
-  for (uint32_t i = p.gtid; i < nTp; i += p.gthreads) {
-    const int32_t s = prv.tl[i];
-    if (a.uniform) {
-      prv.mw[s] = 0;
-    } else {
-      for (uint32_t q = a.woff[s]; q < a.woff[s + 1]; ++q) prv.mw[q] = 0;
-    }
-    prv.tb[s >> 6] = 0;
-    prv.lt[s >> 6] = 0;
-  }
-  if (p.gtid == 0) {
-    a.ctl->cand[par].v[0] = kNone;  // read by X(k); reused by iteration k+2
-    if (a.trace_work && k < a.trace_cap) {
-      int64_t* w = a.trace_work + 4 * (uint64_t)k;
-      w[0] = a.ctl->fW[slot].v[0];
-      w[1] = a.ctl->fW[slot].v[1];
-      w[2] = nT;
-      w[3] = a.ctl->fL[slot].v[0];
-    }
-  }
+  if (p.gtid == 0) a.ctl->cand[par].v[0] = kNone;  // read by X(k); reused by iteration k+2
 }
 
 // S (learned policy, one workgroup): re-score the labels that changed in this
