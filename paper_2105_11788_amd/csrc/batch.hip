@@ -55,7 +55,7 @@ struct bisim_batch {
   // member-list tier scratch
   int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr, *cnt = nullptr,
           *fc = nullptr, *gc = nullptr, *tmp = nullptr, *rk = nullptr, *fi = nullptr,
-          *ltl = nullptr;
+          *ob = nullptr, *nev = nullptr, *ltl = nullptr;
   uint64_t *sf = nullptr, *us = nullptr;
   uint32_t* iters_d = nullptr;  // [count]
   uint32_t* ctl_d = nullptr;    // [0] queue head, [1] error
@@ -97,7 +97,7 @@ struct BArgs {
   uint64_t* lt;
   int32_t* tl;
   int32_t* sl;
-  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ltl;
+  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ob, *nev, *ltl;
   uint64_t *sf, *us;
   int32_t* out;
   uint32_t* iters;
@@ -125,6 +125,8 @@ __host__ __device__ inline uint64_t lds_need(uint32_t n) {
   const uint64_t nw = (n + 63u) / 64u;
   return 8ull * 3 * nw + 8ull * n + ((sizeof(MaskT) * (uint64_t)n + 7) & ~7ull) + 4ull * n;
 }
+
+constexpr uint32_t kCU = 4;  // member-list tier: split-list entries per thread and step
 
 struct Shared {
   uint32_t cand[2];
@@ -154,6 +156,8 @@ struct GList {
   int32_t* tmp;   // [n] per position: tail positions of staying states, by index
   int32_t* rk;    // [n] per split-list entry: rank within its block's split part
   int32_t* fi;    // [n] per split-list entry: index among front split states, or -1
+  int32_t* ob;    // [n] per split-list entry: old block label
+  int32_t* nev;   // [n] per split-list entry: start of its block's tail
   int32_t* ltl;   // [n] touched leaders
   uint64_t* sf;   // [ceil(n/64)] split flags
   uint64_t* us;   // [ceil(n/4096)] summary of the unstable bitmap
@@ -466,8 +470,10 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
       break;
     }
     const uint64_t epoch = (uint64_t)(it + 1) << 32;
-    // ---- A: clear C, next candidate (one wave, through the summary), mark
-    if (wid == 0) {
+    // ---- A: clear C, next candidate (one wave, through the summary), mark.
+    // The search runs on the last wave: marking a small splitter's
+    // in-transitions falls to the first waves.
+    if (wid == nwav - 1) {
       const uint32_t w0 = C >> 6;
       const uint64_t bits = w.ub[w0] & ~(1ull << (C & 63));
       if (lane() == 0) {
@@ -571,20 +577,43 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
                     (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
         push(S, &sh.nS[par], s, sp);
       }
+      // members of the blocks whose leader was touched, 64 blocks at a time:
+      // their member slots are spread over all waves by a prefix sum of the
+      // block sizes (a block can hold most of the instance)
       const uint32_t nL = sh.nL[par];
-      for (uint32_t j = wid; j < nL; j += nwav) {
-        const int32_t b = g.ltl[j];
-        const uint32_t lo = (uint32_t)g.bs[b], hi = (uint32_t)g.be[b];
-        for (uint32_t i0 = lo; i0 < hi; i0 += kWave) {
-          const uint32_t i = i0 + lane();
+      for (uint32_t j0 = 0; j0 < nL; j0 += kWave) {
+        const uint32_t j = j0 + lane();
+        int32_t b = 0;
+        uint32_t lo = 0, sz = 0;
+        if (j < nL) {
+          b = g.ltl[j];
+          lo = (uint32_t)g.bs[b];
+          sz = (uint32_t)g.be[b] - lo;
+        }
+        const uint32_t incl = wave_incl_scan_u32(sz);
+        const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        for (uint32_t e0 = wid * kWave; e0 < total; e0 += nwav * kWave) {
+          const uint32_t e = e0 + lane();
+          const bool valid = e < total;
+          const uint32_t ee = valid ? e : total - 1;
+          uint32_t o = 0;  // owner lane: the first with incl > ee
+#pragma unroll
+          for (uint32_t step = 32; step >= 1; step >>= 1) {
+            const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(o + step - 1), kWave);
+            if (probe <= ee) o += step;
+          }
+          const int32_t ob_ = __shfl(b, (int)o, kWave);
+          const uint32_t olo = (uint32_t)__shfl((int)lo, (int)o, kWave);
+          const uint32_t oin = (uint32_t)__shfl((int)incl, (int)o, kWave);
+          const uint32_t osz = (uint32_t)__shfl((int)sz, (int)o, kWave);
           int32_t s = 0;
           bool sp = false;
-          if (i < hi) {
-            s = g.perm[i];
+          if (valid) {
+            s = g.perm[olo + (ee - (oin - osz))];
             sp = !test_bit(w.tb, (uint32_t)s);
           }
           if (sp)
-            atomicMax((unsigned long long*)&w.nlb[b],
+            atomicMax((unsigned long long*)&w.nlb[ob_],
                       (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
           push(S, &sh.nS[par], s, sp);
         }
@@ -592,82 +621,141 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
     }
     __syncthreads();
     const uint32_t nS = sh.nS[par], nT = sh.nT[par];
-    // ---- C1: size of each block's split part; split flags
-    for (uint32_t i = tid; i < nS; i += nthr) {
-      const int32_t s = S[i];
-      g.rk[i] = atomicAdd(&g.cnt[w.blk[s]], 1);
-      atomicOr((unsigned long long*)&g.sf[s >> 6], 1ull << (s & 63));
+    // The split phases take kCU entries per thread and step; each stage issues
+    // the loads (or atomics) of all of them before using any, so a step waits
+    // for one memory latency per stage, not kCU.
+    // ---- C1: rank of each split state within its block's split part, split
+    // flags, relabel (later phases use the old label kept in ob); clear marks
+    for (uint32_t i0 = tid; i0 < nS; i0 += nthr * kCU) {
+      int32_t sv[kCU], bv[kCU], rv[kCU];
+      uint64_t nv[kCU];
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) {
+        const uint32_t i = i0 + u * nthr;
+        sv[u] = i < nS ? S[i] : -1;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) bv[u] = sv[u] >= 0 ? w.blk[sv[u]] : 0;
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) {
+        nv[u] = sv[u] >= 0 ? w.nlb[bv[u]] : 0ull;
+        rv[u] = sv[u] >= 0 ? atomicAdd(&g.cnt[bv[u]], 1) : 0;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) {
+        if (sv[u] < 0) continue;
+        const uint32_t i = i0 + u * nthr;
+        g.rk[i] = rv[u];
+        g.ob[i] = bv[u];
+        atomicOr((unsigned long long*)&g.sf[sv[u] >> 6], 1ull << (sv[u] & 63));
+        w.blk[sv[u]] = (int32_t)(kNone - (uint32_t)nv[u]);
+      }
+    }
+    for (uint32_t i = tid; i < nT; i += nthr) {
+      const int32_t s = T[i];
+      w.mw[s] = 0;
+      w.tb[s >> 6] = 0;
     }
     __syncthreads();
     // ---- C2: the split part goes to the tail [ne, be) of the block's range:
     // index the split states in front of ne and the staying states in the tail
-    for (uint32_t i = tid; i < nS; i += nthr) {
-      const int32_t s = S[i], b = w.blk[s];
-      const int32_t e = g.be[b], ne = e - g.cnt[b];
-      g.fi[i] = g.pos[s] < ne ? atomicAdd(&g.fc[b], 1) : -1;
-      const int32_t q = ne + g.rk[i];  // every tail position is examined once
-      if (ne < 0 || q < ne || q >= e || e > (int32_t)n) {  // never expected
-        sh.bad = 1;
-        g.fi[i] = -1;
-        continue;
+    for (uint32_t i0 = tid; i0 < nS; i0 += nthr * kCU) {
+      int32_t sv[kCU], bv[kCU], rv[kCU], ev[kCU], cv[kCU], pv[kCU], uv[kCU];
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) {
+        const uint32_t i = i0 + u * nthr;
+        const bool ok = i < nS;
+        sv[u] = ok ? S[i] : -1;
+        bv[u] = ok ? g.ob[i] : 0;
+        rv[u] = ok ? g.rk[i] : 0;
       }
-      const int32_t u = g.perm[q];
-      if (!test_bit(g.sf, (uint32_t)u)) {
-        const int32_t j = atomicAdd(&g.gc[b], 1);
-        if (ne + j < e) g.tmp[ne + j] = q;
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) {
+        ev[u] = sv[u] >= 0 ? g.be[bv[u]] : 0;
+        cv[u] = sv[u] >= 0 ? g.cnt[bv[u]] : 0;
+        pv[u] = sv[u] >= 0 ? g.pos[sv[u]] : 0;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) {
+        uv[u] = -1;
+        if (sv[u] < 0) continue;
+        const uint32_t i = i0 + u * nthr;
+        const int32_t e = ev[u], ne = e - cv[u], q = ne + rv[u];
+        g.nev[i] = ne;
+        g.fi[i] = pv[u] < ne ? atomicAdd(&g.fc[bv[u]], 1) : -1;
+        if (ne < 0 || q < ne || q >= e || e > (int32_t)n) {  // never expected
+          sh.bad = 1;
+          g.fi[i] = -1;
+          continue;
+        }
+        uv[u] = g.perm[q];  // every tail position is examined once
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kCU; ++u) {
+        if (uv[u] < 0 || test_bit(g.sf, (uint32_t)uv[u])) continue;
+        const int32_t ne = ev[u] - cv[u];
+        const int32_t j = atomicAdd(&g.gc[bv[u]], 1);
+        if (ne + j < ev[u]) g.tmp[ne + j] = ne + rv[u];
         else sh.bad = 1;
       }
     }
     __syncthreads();
-    // ---- C3: swap the i-th front split state with the i-th tail staying state
-    for (uint32_t i = tid; i < nS; i += nthr) {
-      const int32_t f = g.fi[i];
-      if (f < 0) continue;
-      const int32_t s = S[i], b = w.blk[s];
-      const int32_t e = g.be[b], ne = e - g.cnt[b];
-      if (ne + f >= e) {  // never expected
-        sh.bad = 1;
-        continue;
-      }
-      const int32_t q = g.tmp[ne + f];
-      const int32_t ps = g.pos[s];
-      if (q < ne || q >= e || ps < 0 || ps >= ne) {
-        sh.bad = 1;
-        continue;
-      }
-      const int32_t u = g.perm[q];
-      g.perm[ps] = u;
-      g.pos[u] = ps;
-      g.perm[q] = s;
-      g.pos[s] = q;
-    }
-    __syncthreads();
-    // ---- C4: relabel, new ranges, unstable updates, clear marks
+    // ---- C3: swap the i-th front split state with the i-th tail staying
+    // state; the new leader of each split block sets both ranges; unstable
+    // updates (be, bs, cnt, fc, gc of a block are read by no other thread here)
     {
       uint32_t best = kNone;
-      for (uint32_t i = tid; i < nS; i += nthr) {
-        const int32_t s = S[i];
-        const int32_t old = w.blk[s];
-        const int32_t nl = (int32_t)(kNone - (uint32_t)w.nlb[old]);
-        w.blk[s] = nl;
-        atomicAnd((unsigned long long*)&g.sf[s >> 6], ~(1ull << (s & 63)));
-        if (s == nl) {  // one thread per split block
-          const int32_t ne = g.be[old] - g.cnt[old];
-          g.bs[nl] = ne;
-          g.be[nl] = g.be[old];
-          g.be[old] = ne;
-          g.cnt[old] = 0;
-          g.fc[old] = 0;
-          g.gc[old] = 0;
-          wg_unstable_set(w.ub, g.us, (uint32_t)old);
-          wg_unstable_set(w.ub, g.us, (uint32_t)nl);
-          best = min(best, (uint32_t)old);
+      for (uint32_t i0 = tid; i0 < nS; i0 += nthr * kCU) {
+        int32_t sv[kCU], bv[kCU], nev[kCU], fv[kCU], lv[kCU], qv[kCU], psv[kCU], ev[kCU];
+#pragma unroll
+        for (uint32_t u = 0; u < kCU; ++u) {
+          const uint32_t i = i0 + u * nthr;
+          const bool ok = i < nS;
+          sv[u] = ok ? S[i] : -1;
+          bv[u] = ok ? g.ob[i] : 0;
+          nev[u] = ok ? g.nev[i] : 0;
+          fv[u] = ok ? g.fi[i] : -1;
         }
-      }
-      for (uint32_t i = tid; i < nT; i += nthr) {
-        const int32_t s = T[i];
-        w.mw[s] = 0;
-        w.tb[s >> 6] = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kCU; ++u) {
+          lv[u] = sv[u] >= 0 ? w.blk[sv[u]] : -1;
+          if (fv[u] >= 0 && nev[u] + fv[u] >= (int32_t)n) {  // never expected
+            sh.bad = 1;
+            fv[u] = -1;
+          }
+          qv[u] = fv[u] >= 0 ? g.tmp[nev[u] + fv[u]] : 0;
+          psv[u] = fv[u] >= 0 ? g.pos[sv[u]] : 0;
+          ev[u] = (sv[u] >= 0 && lv[u] == sv[u]) ? g.be[bv[u]] : 0;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kCU; ++u) {
+          if (sv[u] < 0) continue;
+          const int32_t s = sv[u], b = bv[u], ne = nev[u];
+          if (fv[u] >= 0) {
+            const int32_t q = qv[u], ps = psv[u];
+            if (q < ne || q >= (int32_t)n || ps < 0 || ps >= ne) {  // never expected
+              sh.bad = 1;
+            } else {
+              const int32_t su = g.perm[q];
+              g.perm[ps] = su;
+              g.pos[su] = ps;
+              g.perm[q] = s;
+              g.pos[s] = q;
+            }
+          }
+          if (lv[u] == s) {  // the new leader: one thread per split block
+            g.bs[s] = ne;
+            g.be[s] = ev[u];
+            g.be[b] = ne;
+            g.cnt[b] = 0;
+            g.fc[b] = 0;
+            g.gc[b] = 0;
+            wg_unstable_set(w.ub, g.us, (uint32_t)b);
+            wg_unstable_set(w.ub, g.us, (uint32_t)s);
+            best = min(best, (uint32_t)b);
+          }
+          atomicAnd((unsigned long long*)&g.sf[s >> 6], ~(1ull << (s & 63)));
+        }
       }
       wg_min(&sh.cand[par ^ 1], best);
       if (tid == 0) {
@@ -732,6 +820,8 @@ __global__ void k_batch(BArgs a) {
       g.tmp = a.tmp + s0;
       g.rk = a.rk + s0;
       g.fi = a.fi + s0;
+      g.ob = a.ob + s0;
+      g.nev = a.nev + s0;
       g.ltl = a.ltl + s0;
       g.sf = a.sf + b0;
       g.us = a.us + b0;
@@ -809,7 +899,7 @@ void free_batch(bisim_batch* b) {
   void* ptrs[] = {b->n_off_d, b->bw_off_d, b->order_d, b->blk, b->mw,      b->nlb,  b->ub,
                   b->tb,      b->lt,       b->tl,      b->sl,  b->iters_d, b->ctl_d, b->perm,
                   b->pos,     b->bs,       b->be,      b->cnt, b->fc,      b->gc,    b->tmp,
-                  b->rk,      b->fi,       b->ltl,     b->sf,  b->us};
+                  b->rk,      b->fi,       b->ltl,     b->sf,  b->us,      b->ob,    b->nev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->u) lts_destroy(b->u);
@@ -847,6 +937,8 @@ BArgs make_args(bisim_batch* b, int32_t* out) {
   a.tmp = b->tmp;
   a.rk = b->rk;
   a.fi = b->fi;
+  a.ob = b->ob;
+  a.nev = b->nev;
   a.ltl = b->ltl;
   a.sf = b->sf;
   a.us = b->us;
@@ -1114,6 +1206,7 @@ bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* 
         (st = dmalloc(&b->gc, (size_t)N)) || (st = dmalloc(&b->tmp, (size_t)N)) ||
         (st = dmalloc(&b->rk, (size_t)N)) || (st = dmalloc(&b->fi, (size_t)N)) ||
         (st = dmalloc(&b->ltl, (size_t)N)) || (st = dmalloc(&b->sf, BW)) ||
+        (st = dmalloc(&b->ob, (size_t)N)) || (st = dmalloc(&b->nev, (size_t)N)) ||
         (st = dmalloc(&b->us, BW)) ||
         (st = dmalloc(&b->iters_d, count)) || (st = dmalloc(&b->ctl_d, 2)))
       break;
