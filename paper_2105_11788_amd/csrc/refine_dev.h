@@ -584,9 +584,10 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
   const FPar cur = fpar(a, par), prv = fpar(a, par ^ 1);
   uint32_t* cand = &a.ctl->cand[par ^ 1].v[0];
   const uint32_t n = (uint32_t)a.n, nwd = (n + 63u) >> 6;
-  if (p.gwave == 0) {  // clear C, search the next smallest unstable label
-    // the previous splitter is unstable again if anything split (unless it
-    // is C itself); it is folded in here, where nothing else writes the set
+  if (p.gwave == p.gwaves - 1) {  // clear C, search the next smallest unstable label
+    // (on the last wave, which has the least scan work; the previous splitter
+    // is unstable again if anything split, unless it is C itself; it is
+    // folded in here, where nothing else writes the set)
     uint32_t pc = kNone;
     if (k > 0 && a.ctl->fS[(k - 1) % 3].v[0] != 0) pc = a.ctl->fC[(k - 1) % 3].v[0];
     if (pc == C) pc = kNone;
