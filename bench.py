@@ -197,6 +197,8 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
     h.set_option(bisim.OPT_ENGINE, engine)
     if args.grid:
         h.set_option(bisim.OPT_GRID, args.grid)
+    if getattr(args, "algorithm", 3) != 3 and mlp is None:
+        h.set_option(bisim.OPT_ALGORITHM, args.algorithm)
     if mlp is not None:
         bisim.set_splitter_policy(h, bisim.POLICY_LEARNED, mlp, args.rescore)
     out = bisim.DeviceArray(L.n, np.int32)
@@ -270,7 +272,7 @@ def form_plain(bisim, gen, args):
         f"copy {copy_gbs:.0f} GB/s")
     cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
            "iterations": iters, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
-           "mark_length": st.mark_length, "form": "plain",
+           "mark_length": st.mark_length, "form": "plain", "algorithm": args.algorithm,
            "engine": "persistent" if args.engine == 1 else "per-phase kernels"}
     res = base_record(args, "transitions*iterations/sec (plain refinement to fixpoint)",
                       L.m * iters / (r["ms_per_step"] * 1e-3), r["ms_per_step"], cfg)
@@ -405,6 +407,8 @@ def main():
     ap.add_argument("--engine", type=int, default=0,
                     help="0 automatic (per-phase kernels), 1 persistent, 2 per-phase kernels")
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--algorithm", type=int, default=3, choices=[2, 3],
+                    help="plain form: 3 = labelled algorithm, 2 = one-action RCPP algorithm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--count", type=int, default=4096)

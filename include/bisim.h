@@ -55,7 +55,8 @@ typedef int32_t bisim_status;
 #define BISIM_E_ITERCAP -5     /* iteration count exceeded 3n - |pi_pre| + 1, the bound of
                                   section 4.2's complexity theorem plus the final pass;
                                   reachable only through the test hook below */
-#define BISIM_E_UNSUPPORTED -6 /* sizes beyond the documented limits */
+#define BISIM_E_UNSUPPORTED -6 /* sizes beyond the documented limits, or an option the
+                                  input does not allow */
 
 typedef struct bisim_lts bisim_lts;
 
@@ -136,6 +137,15 @@ const char* bisim_last_error(void);
                                      iterations per run) with events bound to the end of
                                      each kernel; a phase's time is the distance between
                                      the ends of consecutive kernels of the stream */
+#define BISIM_OPT_ALGORITHM 6     /* 3 (default): the labelled algorithm (Algorithm 3, with
+                                     section 4.1's preprocessing); 2: the algorithm for the
+                                     relational coarsest partition problem (section 3.2,
+                                     Algorithm 2) — one-action LTSs (Kripke structures)
+                                     only (else BISIM_E_UNSUPPORTED): it starts from the
+                                     leader-normalised pi_0 without preprocessing, keeps
+                                     one mark per state, and does not make the splitter
+                                     unstable again after a split.  Same result, its own
+                                     iteration count; the plain policy only. */
 bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
 
 /*

@@ -36,6 +36,7 @@ OPT_FIRST_SPLITTER = 2
 OPT_ITER_LIMIT = 3
 OPT_GRID = 4
 OPT_PROFILE_EVERY = 5
+OPT_ALGORITHM = 6  # 3: labelled (Algorithm 3, default); 2: one-action RCPP (Algorithm 2)
 
 ENGINE_AUTO = 0
 ENGINE_PERSISTENT = 1

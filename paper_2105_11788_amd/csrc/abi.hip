@@ -19,7 +19,7 @@ void set_error(const char* fmt, ...) {
 static void free_handle(bisim_lts* h) {
   if (!h) return;
   hipStream_t s = h->stream;
-  void* ptrs[] = {h->pre_block, h->nr_marks, h->in_ptr, h->in_src, h->in_ord, h->woff,
+  void* ptrs[] = {h->init_block, h->pre_block, h->nr_marks, h->in_ptr, h->in_src, h->in_ord, h->woff,
                   h->block,     h->mw,       h->tb,     h->lt,     h->ub,     h->nlw,
                   h->tlist,     h->slist,    h->ctl,    h->sfeat,  h->acc,    h->born,
                   h->used,      h->chg,      h->us,     h->lvl,    h->lvb,    h->lvs,
@@ -137,7 +137,7 @@ bisim_status coarsest_partition(bisim_lts* h, int32_t* block_id, bisim_stats* st
   if (st) {
     st->iterations = h->last_iters;
     st->blocks = h->last_blocks;
-    st->pre_blocks = h->pre_blocks;
+    st->pre_blocks = h->run_pre_blocks;
     st->mark_length = h->mark_length;
     st->t_pre_ms = h->t_pre_ms;
     st->t_alg_ms = h->t_alg_ms;
@@ -172,6 +172,14 @@ bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value) {
     case BISIM_OPT_PROFILE_EVERY:
       if (value < 0) break;
       h->profile_every = value;
+      return BISIM_OK;
+    case BISIM_OPT_ALGORITHM:
+      if (value != 2 && value != 3) break;
+      if (value == 2 && (h->K != 1 || (h->n > 0 && !h->init_block))) {
+        set_error("bisim_set_option: Algorithm 2 needs a one-action LTS (num_actions = 1)");
+        return BISIM_E_UNSUPPORTED;
+      }
+      h->algorithm = (int)value;
       return BISIM_OK;
     default:
       break;

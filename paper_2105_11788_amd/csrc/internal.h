@@ -132,6 +132,7 @@ struct bisim_lts {
 
   // preprocessed, immutable after load
   int32_t* pre_block = nullptr;  // [n] pi_pre, canonical
+  int32_t* init_block = nullptr; // [n] leader-normalised pi_0 (one-action LTSs: Algorithm 2)
   int32_t* nr_marks = nullptr;   // [n] distinct outgoing actions per state
   uint32_t* in_ptr = nullptr;    // [n+1] transitions grouped by target
   int32_t* in_src = nullptr;     // [m] source of each grouped transition
@@ -161,6 +162,8 @@ struct bisim_lts {
 
   // options
   int engine = 0;
+  int algorithm = 3;  // 3: labelled (Algorithm 3); 2: one-action RCPP (Algorithm 2)
+  int64_t run_pre_blocks = 0;  // blocks the last run started from
   int64_t first_splitter = -1;
   int64_t iter_limit = 0;
   int grid = 0;

@@ -315,12 +315,13 @@ Args make_args(bisim_lts* h, uint32_t cap, bool learned, bool track) {
 }
 
 // per-run initialisation, shared with the training-data collector
-bisim_status refine_init(bisim_lts* h, const Args& a, uint32_t first, bool learned, bool track) {
+bisim_status refine_init(bisim_lts* h, const Args& a, uint32_t first, bool learned, bool track,
+                         const int32_t* start) {
   hipStream_t st = h->stream;
   const int cu = h->num_cu > 0 ? h->num_cu : 1;
   int64_t g = ((int64_t)h->n + kT - 1) / kT;
   g = g > grid_cap(cu) ? grid_cap(cu) : (g < 1 ? 1 : g);
-  hipLaunchKernelGGL(k_init_run, dim3((unsigned)g), dim3(kT), 0, st, a, h->pre_block, first,
+  hipLaunchKernelGGL(k_init_run, dim3((unsigned)g), dim3(kT), 0, st, a, start, first,
                      h->nwords, learned ? 1u : 0u);
   hipLaunchKernelGGL(k_init_summary, dim3((unsigned)g), dim3(kT), 0, st, a);
   BISIM_TRY_HIP(hipGetLastError());
@@ -340,14 +341,42 @@ bisim_status refine_init(bisim_lts* h, const Args& a, uint32_t first, bool learn
   return BISIM_OK;
 }
 
+// number of block labels (states that are their block's label) of a partition
+bisim_status count_labels(bisim_lts* h, const int32_t* block, int64_t* out) {
+  hipStream_t st = h->stream;
+  const int cu = h->num_cu > 0 ? h->num_cu : 1;
+  unsigned long long* cnt = nullptr;
+  BISIM_TRY(dalloc(&cnt, 1, st));
+  BISIM_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
+  int64_t g = ((int64_t)h->n + kT - 1) / kT;
+  g = g > grid_cap(cu) ? grid_cap(cu) : (g < 1 ? 1 : g);
+  if (h->n > 0)
+    hipLaunchKernelGGL(k_count_leaders, dim3((unsigned)g), dim3(kT), 0, st, block, h->n, cnt);
+  unsigned long long nb = 0;
+  BISIM_TRY_HIP(hipMemcpyAsync(&nb, cnt, sizeof(nb), hipMemcpyDeviceToHost, st));
+  BISIM_TRY_HIP(hipFreeAsync(cnt, st));
+  BISIM_TRY_HIP(hipStreamSynchronize(st));
+  *out = (int64_t)nb;
+  return BISIM_OK;
+}
+
 bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   hipStream_t st = h->stream;
   const int32_t n = h->n;
-  int64_t cap = 3 * (int64_t)n - h->pre_blocks + 1;
+  const bool learned = h->policy == 1 && h->policy_w;
+  const bool rcpp = h->algorithm == 2;
+  if (rcpp && learned) {
+    set_error("coarsest_partition: Algorithm 2 runs with the plain splitter policy only");
+    return BISIM_E_UNSUPPORTED;
+  }
+  // Algorithm 2 starts from pi_0 itself, Algorithm 3 from the preprocessed partition
+  const int32_t* start = rcpp ? h->init_block : h->pre_block;
+  h->run_pre_blocks = h->pre_blocks;
+  if (rcpp) BISIM_TRY(count_labels(h, start, &h->run_pre_blocks));
+  int64_t cap = 3 * (int64_t)n - h->run_pre_blocks + 1;
   if (cap < 1) cap = 1;
   if (h->iter_limit > 0 && h->iter_limit < cap) cap = h->iter_limit;
   if (cap > 0xFFFFFFF0ll) cap = 0xFFFFFFF0ll;
-  const bool learned = h->policy == 1 && h->policy_w;
 
   uint32_t first = 0;
   if (h->first_splitter >= 0 && !learned) {
@@ -356,7 +385,7 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
       return BISIM_E_INVALID;
     }
     int32_t lead = -1;
-    BISIM_TRY_HIP(hipMemcpyAsync(&lead, h->pre_block + h->first_splitter, sizeof(int32_t),
+    BISIM_TRY_HIP(hipMemcpyAsync(&lead, start + h->first_splitter, sizeof(int32_t),
                                  hipMemcpyDeviceToHost, st));
     BISIM_TRY_HIP(hipStreamSynchronize(st));
     if (lead != h->first_splitter) {
@@ -368,7 +397,8 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   }
   if (learned) BISIM_TRY(refine_alloc_features(h));
   Args a = make_args(h, (uint32_t)cap, learned, learned);
-  BISIM_TRY(refine_init(h, a, first, learned, learned));
+  a.rcpp = rcpp ? 1u : 0u;
+  BISIM_TRY(refine_init(h, a, first, learned, learned, start));
   BISIM_TRY_HIP(hipEventRecord(h->ev0, st));
 
   const int cu = h->num_cu > 0 ? h->num_cu : 1;
@@ -504,18 +534,7 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   if (block_id && n > 0)
     BISIM_TRY_HIP(hipMemcpyAsync(block_id, h->block, sizeof(int32_t) * (size_t)n,
                                  hipMemcpyDeviceToDevice, st));
-  unsigned long long* cnt = nullptr;
-  BISIM_TRY(dalloc(&cnt, 1, st));
-  BISIM_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
-  int64_t g = ((int64_t)n + kT - 1) / kT;
-  g = g > grid_cap(cu) ? grid_cap(cu) : (g < 1 ? 1 : g);
-  hipLaunchKernelGGL(k_count_leaders, dim3((unsigned)g), dim3(kT), 0, st, h->block, n, cnt);
-  unsigned long long nb = 0;
-  BISIM_TRY_HIP(hipMemcpyAsync(&nb, cnt, sizeof(nb), hipMemcpyDeviceToHost, st));
-  BISIM_TRY_HIP(hipFreeAsync(cnt, st));
-  BISIM_TRY_HIP(hipStreamSynchronize(st));
-  h->last_blocks = (int64_t)nb;
-  return BISIM_OK;
+  return count_labels(h, h->block, &h->last_blocks);
 }
 
 // one iteration of the per-phase engine with feature tracking (training-data
@@ -665,7 +684,7 @@ bisim_status bisim_collect_training(bisim_lts* h, int64_t sample_every, int32_t 
   a.trace_C = nullptr;
   a.trace_nsplit = nullptr;
   a.trace_work = nullptr;
-  BISIM_TRY(refine_init(h, a, 0, false, true));
+  BISIM_TRY(refine_init(h, a, 0, false, true, h->pre_block));
   uint32_t* written = nullptr;
   BISIM_TRY_HIP(hipMallocAsync((void**)&written, sizeof(uint32_t), st));
   int64_t r = 0;

@@ -29,6 +29,7 @@ struct Args {
   uint64_t* sb;     // [2][nwd] split flags (two-kernel engine)
   int32_t* nlist;   // [n] new leaders (two-kernel engine)
   uint64_t nwords;  // mark words per parity half
+  uint32_t rcpp;    // Algorithm 2: the splitter is not made unstable again after a split
   Ctl* ctl;
   uint32_t iter_cap;
   int32_t* trace_C;
@@ -589,7 +590,7 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
     // is unstable again if anything split, unless it is C itself; it is
     // folded in here, where nothing else writes the set)
     uint32_t pc = kNone;
-    if (k > 0 && a.ctl->fS[(k - 1) % 3].v[0] != 0) pc = a.ctl->fC[(k - 1) % 3].v[0];
+    if (k > 0 && !a.rcpp && a.ctl->fS[(k - 1) % 3].v[0] != 0) pc = a.ctl->fC[(k - 1) % 3].v[0];
     if (pc == C) pc = kNone;
     const uint32_t w0 = C >> 6;
     uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
@@ -709,8 +710,8 @@ __device__ __forceinline__ void split2(const Args& a, const FPar& cur, uint32_t 
     if (lane() == 0) {
       atomicAdd(&a.ctl->fS[slot].v[0], (uint32_t)__popcll(bal));
       // anything split: C is a candidate again (its unstable bit is set by
-      // the next step's selection)
-      atomicMin(&a.ctl->cand[par ^ 1].v[0], mb < C ? mb : C);
+      // the next step's selection) -- not in Algorithm 2
+      atomicMin(&a.ctl->cand[par ^ 1].v[0], (mb < C || a.rcpp) ? mb : C);
     }
   }
 }

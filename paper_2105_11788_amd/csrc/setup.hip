@@ -309,6 +309,11 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
   }
   hipLaunchKernelGGL(k_init_leaders_set, dim3(gn), dim3(kT), 0, st, n, init, newl, h->pre_block);
   BISIM_TRY_HIP(hipGetLastError());
+  if (K == 1) {  // kept for Algorithm 2, which starts from pi_0 itself
+    BISIM_TRY(dalloc(&h->init_block, (size_t)n, st));
+    BISIM_TRY_HIP(hipMemcpyAsync(h->init_block, h->pre_block, sizeof(int32_t) * (size_t)n,
+                                 hipMemcpyDeviceToDevice, st));
+  }
 
   // 4. Algorithm 4 rounds, fused with the action ranking
   BISIM_TRY_HIP(hipMemsetAsync(has, 0, (size_t)n, st));

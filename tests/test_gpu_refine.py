@@ -31,10 +31,12 @@ def dev(L):
     return t(L.src), t(L.lab), t(L.dst), (None if L.init is None else t(L.init))
 
 
-def run_gpu(B, L, engine=1, trace=0, first=-1, grid=0):
+def run_gpu(B, L, engine=1, trace=0, first=-1, grid=0, algorithm=3):
     src, lab, dst, init = dev(L)
     with B.LTS(src, lab, dst, L.n, L.K, init) as h:
         h.set_option(B.OPT_ENGINE, engine)
+        if algorithm != 3:
+            h.set_option(B.OPT_ALGORITHM, algorithm)
         if first >= 0:
             h.set_option(B.OPT_FIRST_SPLITTER, first)
         if grid:
@@ -267,3 +269,51 @@ def test_sync_product_full(B):
     r = run_gpu(B, P, engine=1)
     assert (r["block"] == ks).all()
     assert r["stats"].iterations <= 3 * P.n - r["stats"].pre_blocks + 1
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2 (relational coarsest partition, one action)
+# --------------------------------------------------------------------------
+def assert_parity_alg2(B, L):
+    cap = 3 * L.n + 2
+    ref = oracle.alg3_trace(L.n, 1, L.src, L.lab, L.dst, L.init, trace_cap=cap, variant=2)
+    ks, nb = oracle.ks_coarsest(L.n, 1, L.src, L.lab, L.dst, L.init)
+    for e in ENGINES:
+        g = run_gpu(B, L, engine=e, trace=cap, algorithm=2)
+        assert (g["block"] == ks).all(), (L.name, e)
+        st = g["stats"]
+        assert st.iterations == ref["iters"], (L.name, e, st.iterations, ref["iters"])
+        assert st.blocks == nb and st.pre_blocks == ref["pre_blocks"]
+        assert (g["C"] == ref["C"]).all(), (L.name, e)
+        assert (g["nsplit"] == ref["nsplit"]).all(), (L.name, e)
+    return ref["iters"]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_algorithm2_figure1(B, engine):
+    g = json.load(open(os.path.join(GOLD, "figure1.json")))
+    L = gen.figure1()
+    r = run_gpu(B, L, engine=engine, trace=16, algorithm=2)
+    assert r["block"].tolist() == g["final_partition"]
+    assert r["stats"].iterations == g["alg2_iterations"]
+    assert_parity_alg2(B, L)
+
+
+def test_algorithm2_kripke_and_random(B):
+    cases = [gen.kripke_uniform(1000, 5000, seed=s) for s in (1, 2, 3)]
+    cases += [gen.random_lts(n, 4 * n, 1, seed=300 + n, init_blocks=3) for n in (3, 17, 300)]
+    cases += [gen.random_lts(n, 2 * n, 1, seed=400 + n) for n in (1, 2)]
+    cases += [gen.LTS(5, 1, [], [], [], np.array([0, 1, 0, 1, 4]))]
+    for L in cases:
+        assert_parity_alg2(B, L)
+
+
+def test_algorithm2_needs_one_action(B):
+    L = gen.figure2()  # two actions
+    src, lab, dst, _ = dev(L)
+    with B.LTS(src, lab, dst, L.n, L.K) as h:
+        with pytest.raises(B.BisimError) as e:
+            h.set_option(B.OPT_ALGORITHM, 2)
+        assert e.value.status == B.E_UNSUPPORTED
+        with pytest.raises(B.BisimError):
+            h.set_option(B.OPT_ALGORITHM, 4)
