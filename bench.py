@@ -62,6 +62,16 @@ WORKLOADS = {
 }
 
 
+def workload(name: str):
+    """A named workload, or the family fan-out-<n> (Fan_out_n of section 5,
+    Figure 3: #It = 2n - 4)."""
+    if name.startswith("fan-out-"):
+        n = int(name[len("fan-out-"):])
+        return dict(desc=f"Fan_out_n with n={n} (section 5, Figure 3)",
+                    make=lambda g: g.fan_out(n))
+    return WORKLOADS[name]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -235,7 +245,7 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
 
 
 def form_plain(bisim, gen, args):
-    wl = WORKLOADS[args.workload]
+    wl = workload(args.workload)
     t = time.perf_counter()
     L = wl["make"](gen)
     log(f"workload {args.workload}: n={L.n} m={L.m} K={L.K} ({time.perf_counter() - t:.1f}s)")
@@ -265,10 +275,12 @@ def form_plain(bisim, gen, args):
                                 "touched_GBs": float(pb[:-1, i].mean() / (ms[i] * 1e-3) / 1e9)
                                 if ms[i] > 0 else None,
                                 "samples": int(r["phase_samples"][i])} for i in range(2)}
-    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
-    touched_gbs = touched_launch / (kern_ms * 1e-3) / 1e9
+    # (a run of a few iterations may sample none)
+    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    touched_gbs = touched_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    fmt = lambda v: "n/a" if v is None else f"{v:.1f}"
     log(f"{r['ms_per_step']:.2f} ms/step, #It={iters}, {kernel}: {kern_ms * 1e3:.2f} us/launch, "
-        f"method bytes {achieved:.1f} GB/s, touched bytes {touched_gbs:.1f} GB/s; "
+        f"method bytes {fmt(achieved)} GB/s, touched bytes {fmt(touched_gbs)} GB/s; "
         f"copy {copy_gbs:.0f} GB/s")
     cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
            "iterations": iters, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
@@ -286,7 +298,7 @@ def form_plain(bisim, gen, args):
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
             "traffic": stored_traffic(kernel.split(" ")[0], args.workload),
             "bytes_per_launch": bytes_launch,
             "bytes_definition": "method bytes: each pass of Algorithm 3 over all "
@@ -376,7 +388,7 @@ def form_learned(bisim, gen, args):
                                            steps=args.train_steps)
     t_train = time.perf_counter() - t
     log(f"trained on {rows} rows in {t_train:.1f}s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
-    wl = WORKLOADS[args.workload]
+    wl = workload(args.workload)
     L = wl["make"](gen)
     log(f"workload {args.workload}: n={L.n} m={L.m} K={L.K}")
     rp = run_single(bisim, L, args, args.engine, trace=False)
@@ -403,7 +415,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"])
-    ap.add_argument("--workload", default="planted-quotient-1M", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="planted-quotient-1M",
+                    help="one of " + ", ".join(sorted(WORKLOADS)) + ", or fan-out-<n>")
     ap.add_argument("--engine", type=int, default=0,
                     help="0 automatic (per-phase kernels), 1 persistent, 2 per-phase kernels")
     ap.add_argument("--grid", type=int, default=0)
@@ -421,6 +434,10 @@ def main():
     ap.add_argument("--train-lts", type=int, default=12)
     ap.add_argument("--train-steps", type=int, default=300)
     args = ap.parse_args()
+    try:
+        workload(args.workload)
+    except (KeyError, ValueError):
+        ap.error(f"unknown workload {args.workload}")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -139,6 +139,7 @@ struct bisim_lts {
   int32_t* in_ord = nullptr;     // [m] its action's rank among the source's actions
   uint32_t* woff = nullptr;      // [n+1] mark-word offsets (only when !uniform)
   int uniform = 1;               // every state has <= 64 actions: word index = state
+  uint32_t max_out = 0;          // largest number of outgoing transitions of a state
   uint64_t nwords = 0;
   int64_t pre_blocks = 0;
   int64_t mark_length = 0;

@@ -82,12 +82,13 @@ __global__ void __launch_bounds__(kT) k_phase_c(Args a, uint32_t k) {
   phase_c<L, T>(a, k & 1, k, a.ctl->state.v[3], part());
 }
 // plain policy: two kernels per iteration
+template <bool Agg>
 __global__ void __launch_bounds__(kT) k_fused_x(Args a, uint32_t k) {
   if (a.ctl->state.v[1]) return;
   const Part p = part();
   const uint32_t C = head2(a, k, p);
   if (C == kNone) return;
-  phase_x(a, k, C, p);
+  phase_x<Agg>(a, k, C, p);
 }
 __global__ void __launch_bounds__(kT) k_fused_y(Args a, uint32_t k) {
   if (a.ctl->state.v[1]) return;
@@ -186,7 +187,10 @@ __global__ void __launch_bounds__(kPT) k_persistent(Args a) {
     for (uint32_t k = 0;; ++k) {
       const uint32_t C = head2(a, k, p);
       if (C == kNone) break;
-      phase_x(a, k, C, p);
+      if (a.hot)
+        phase_x<true>(a, k, C, p);
+      else
+        phase_x<false>(a, k, C, p);
       if (!grid_barrier(a.ctl, gen)) break;
       phase_y(a, k, p);
       if (!grid_barrier(a.ctl, gen)) break;
@@ -273,6 +277,7 @@ Args make_args(bisim_lts* h, uint32_t cap, bool learned, bool track) {
   Args a{};
   a.n = h->n;
   a.uniform = h->uniform;
+  a.hot = h->max_out >= kHotDegree;
   a.in_ptr = h->in_ptr;
   a.in_src = h->in_src;
   a.in_ord = h->in_ord;
@@ -476,7 +481,10 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
           else
             hipLaunchKernelGGL(k_phase_s, dim3(1), dim3(kST), lds, st, a, k);
         } else {
-          go(k_fused_x, ends[0], 0, k);
+          if (a.hot)
+            go(k_fused_x<true>, ends[0], 0, k);
+          else
+            go(k_fused_x<false>, ends[0], 0, k);
           go(k_fused_y, ends[1], 0, k);
         }
       }

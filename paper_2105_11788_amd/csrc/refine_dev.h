@@ -13,6 +13,7 @@ namespace {
 struct Args {
   int32_t n;
   int uniform;
+  int hot;      // some state has >= kHotDegree outgoing transitions: combine its marks
   const uint32_t* __restrict__ in_ptr;
   const int32_t* __restrict__ in_src;
   const int32_t* __restrict__ in_ord;
@@ -559,32 +560,139 @@ __device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
 // their loads are issued before any is used
 constexpr uint32_t kFusedU = 2;
 
-// mark slot o of state s; every atomic is fire-and-forget (the touched set is
-// the tb bitmap, read back by the next step's scan)
-__device__ __forceinline__ void mark_slot3(const Args& a, const FPar& cur, const uint64_t* prev_sb,
-                                           uint32_t slot, uint32_t k, int32_t s, int32_t o) {
+// Marks of source s (slots `bits` of its word wi): the mark word, and the
+// touched-leader bit when s leads its block.  Every atomic is fire-and-forget
+// (the touched set is the tb bitmap, read back by the next step's scan).
+__device__ __forceinline__ void mark_word(const Args& a, const FPar& cur, const uint64_t* prev_sb,
+                                          uint32_t slot, uint32_t k, int32_t s, uint64_t wi,
+                                          uint64_t bits) {
   const int32_t bl = a.block[s];
   const bool flagged = test_bit(prev_sb, (uint32_t)s);
-  const uint64_t wi = a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6);
-  const uint64_t tbit = 1ull << (s & 63);
-  atomicOr((unsigned long long*)&cur.mw[wi], 1ull << (o & 63));
-  atomicOr((unsigned long long*)&cur.tb[s >> 6], (unsigned long long)tbit);
-  int32_t lab = bl;  // lazy_label, with its loads issued before the atomics
+  atomicOr((unsigned long long*)&cur.mw[wi], (unsigned long long)bits);
+  int32_t lab = bl;  // lazy_label, with its loads issued before the atomic
   if (flagged) {
     const uint64_t v = a.nlw[bl];
     if ((uint32_t)(v >> 32) == k) lab = (int32_t)(kNone - (uint32_t)v);
   }
   if (lab == s) {  // a touched leader
-    atomicOr((unsigned long long*)&cur.lt[s >> 6], (unsigned long long)tbit);
+    atomicOr((unsigned long long*)&cur.lt[s >> 6], 1ull << (s & 63));
     a.ctl->fL[slot].v[0] = 1;
   }
 }
 
+__device__ __forceinline__ void mark_state(const Args& a, const FPar& cur, const uint64_t* prev_sb,
+                                           uint32_t slot, uint32_t k, int32_t s, uint64_t wi,
+                                           uint64_t bits) {
+  mark_word(a, cur, prev_sb, slot, k, s, wi, bits);
+  atomicOr((unsigned long long*)&cur.tb[s >> 6], 1ull << (s & 63));
+}
+
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v |= (uint64_t)__shfl_xor((unsigned long long)v, d, kWave);
+  return v;
+}
+
+// Set the touched bits of the sources of the lanes with `pend` (wave-uniform
+// call).  When lanes share a bitmap word with the first such lane (sources
+// that are neighbours, like a chain's), the words of the first two groups
+// take one atomic each: consecutive words sit in few memory channels, where
+// one atomic per lane would queue.
+__device__ __forceinline__ void touch_lanes(const FPar& cur, int32_t s, bool pend) {
+  const uint64_t pb0 = __ballot(pend);
+  if (!pb0) return;
+  const uint32_t w = (uint32_t)s >> 6;
+  const uint32_t wf = (uint32_t)__shfl((int)w, __ffsll((unsigned long long)pb0) - 1, kWave);
+  if (__popcll(__ballot(pend && w == wf)) > 1) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const uint64_t pb = __ballot(pend);
+      if (!pb) return;
+      const int f = __ffsll((unsigned long long)pb) - 1;
+      const uint32_t w0 = (uint32_t)__shfl((int)w, f, kWave);
+      const bool mine = pend && w == w0;
+      const uint64_t bits = wave_or_u64(mine ? 1ull << (s & 63) : 0ull);
+      if ((int)lane() == f) atomicOr((unsigned long long*)&cur.tb[w0], (unsigned long long)bits);
+      pend = pend && !mine;
+    }
+  }
+  if (pend) atomicOr((unsigned long long*)&cur.tb[w], 1ull << (s & 63));
+}
+
+// Per-workgroup table of sources whose marks are combined in LDS and written
+// once, after the workgroup's last chunk.  The combining marking runs on LTSs
+// with a state of at least kHotDegree outgoing transitions (one such state
+// can fill a wave with the same source); elsewhere each lane marks its own.
+constexpr int kHot = 4;
+constexpr uint32_t kHotDegree = 64;
+struct HotTab {
+  int32_t* s;             // [kHot] source, -1 while free
+  unsigned long long* b;  // [kHot] its slot bits
+};
+
+// Mark the transitions held by the lanes of a wave (valid lanes: source s,
+// action rank o; wave-uniform call).  When the first lane's source recurs in
+// the wave (a state with transitions into many of C's members, like
+// Fan_out_n's states 0 and 1), the lanes of the first two sources are
+// combined and their bits go to the workgroup's table: one atomic per
+// transition, or even per wave, would serialise on that state's words.
+__device__ __forceinline__ void mark_lanes(const Args& a, const FPar& cur, const uint64_t* prev_sb,
+                                           uint32_t slot, uint32_t k, int32_t s, int32_t o,
+                                           bool valid, const HotTab& ht) {
+  if (!a.uniform) {  // a state's slots may span several words
+    if (valid)
+      mark_word(a, cur, prev_sb, slot, k, s, (uint64_t)a.woff[s] + (uint32_t)(o >> 6),
+                1ull << (o & 63));
+    touch_lanes(cur, s, valid);
+    return;
+  }
+  const uint64_t vb = __ballot(valid);
+  if (!vb) return;
+  const int32_t sf = __shfl(s, __ffsll((unsigned long long)vb) - 1, kWave);
+  bool pending = valid;
+  if (__popcll(__ballot(valid && s == sf)) > 1) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const uint64_t pb = __ballot(pending);
+      if (!pb) return;
+      const int f = __ffsll((unsigned long long)pb) - 1;
+      const int32_t s0 = __shfl(s, f, kWave);
+      const bool mine = pending && s == s0;
+      const uint64_t bits = wave_or_u64(mine ? 1ull << (o & 63) : 0ull);
+      if ((int)lane() == f) {
+        bool put = false;
+        for (int i = 0; i < kHot && !put; ++i) {
+          const int32_t old = atomicCAS(&ht.s[i], -1, s0);
+          if (old == -1 || old == s0) {
+            atomicOr(&ht.b[i], (unsigned long long)bits);
+            put = true;
+          }
+        }
+        if (!put) mark_state(a, cur, prev_sb, slot, k, s0, (uint64_t)s0, bits);
+      }
+      pending = pending && !mine;
+    }
+  }
+  if (pending) mark_word(a, cur, prev_sb, slot, k, s, (uint64_t)s, 1ull << (o & 63));
+  touch_lanes(cur, s, pending);
+}
+
+template <bool Agg>
 __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
   const uint32_t par = k & 1, slot = k % 3;
   const FPar cur = fpar(a, par), prv = fpar(a, par ^ 1);
   uint32_t* cand = &a.ctl->cand[par ^ 1].v[0];
   const uint32_t n = (uint32_t)a.n, nwd = (n + 63u) >> 6;
+  __shared__ int32_t hot_s[kHot];
+  __shared__ unsigned long long hot_b[kHot];
+  const HotTab ht{hot_s, hot_b};
+  if (Agg) {
+    if (threadIdx.x < (uint32_t)kHot) {
+      hot_s[threadIdx.x] = -1;
+      hot_b[threadIdx.x] = 0;
+    }
+    __syncthreads();
+  }
   if (p.gwave == p.gwaves - 1) {  // clear C, search the next smallest unstable label
     // (on the last wave, which has the least scan work; the previous splitter
     // is unstable again if anything split, unless it is C itself; it is
@@ -684,35 +792,64 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
         const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
         const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
         const uint32_t edge = jb + (ee - (ji - jd));
-        if (valid) mark_slot3(a, cur, prv.sb, slot, k, a.in_src[edge], a.in_ord[edge]);
+        int32_t s = 0, o = 0;
+        if (valid) {
+          s = a.in_src[edge];
+          o = a.in_ord[edge];
+        }
+        if (Agg) {
+          mark_lanes(a, cur, prv.sb, slot, k, s, o, valid, ht);
+        } else if (valid) {
+          mark_state(a, cur, prv.sb, slot, k, s,
+                     a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6),
+                     1ull << (o & 63));
+        }
       }
     }
   }
+  if (!Agg) return;
+  __syncthreads();  // write the workgroup's combined marks
+  if (threadIdx.x < (uint32_t)kHot && hot_s[threadIdx.x] >= 0)
+    mark_state(a, cur, prv.sb, slot, k, hot_s[threadIdx.x], (uint64_t)hot_s[threadIdx.x],
+               hot_b[threadIdx.x]);
 }
 
-// a split state s of block b (wave-uniform call); every atomic here is
-// fire-and-forget
+// Split states s = base + lane of one 64-state chunk of Y's scan (wave-uniform
+// call; b = block[s]).  Atomics are aggregated per wave: one split-flag word,
+// and one bid for the block of the first split lane (usually the only block:
+// a large block that loses most of its states bids from every wave of the
+// scan), with a read first so that later, larger bids are skipped.
 __device__ __forceinline__ void split2(const Args& a, const FPar& cur, uint32_t slot, uint32_t par,
-                                       uint32_t C, int32_t s, int32_t b, bool sp, uint64_t epoch) {
-  if (sp) {
+                                       uint32_t C, uint32_t base, int32_t b, bool sp,
+                                       uint64_t epoch) {
+  const uint64_t bal = __ballot(sp);
+  if (!bal) return;
+  const uint32_t s = base + lane();
+  const int first = __ffsll((unsigned long long)bal) - 1;
+  const int32_t b0 = __shfl(b, first, kWave);
+  const uint32_t m0 = wave_min_u32(sp && b == b0 ? s : kNone);
+  if ((int)lane() == first) {
+    const uint64_t v = epoch | (uint64_t)(kNone - m0);
+    if (__hip_atomic_load(&a.nlw[b0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v)
+      atomicMax((unsigned long long*)&a.nlw[b0], (unsigned long long)v);
+    atomicOr((unsigned long long*)&cur.sb[base >> 6], (unsigned long long)bal);
+  }
+  if (sp && b != b0)
     atomicMax((unsigned long long*)&a.nlw[b],
-              (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
-    atomicOr((unsigned long long*)&cur.sb[s >> 6], 1ull << (s & 63));
+              (unsigned long long)(epoch | (uint64_t)(kNone - s)));
+  if (sp) {  // old label unstable (sets only in this step)
     const uint32_t w = (uint32_t)b >> 6;
-    if (!((a.ub[w] >> (b & 63)) & 1ull)) {  // old label unstable (sets only in this step)
+    if (!((a.ub[w] >> (b & 63)) & 1ull)) {
       atomicOr((unsigned long long*)&a.ub[w], 1ull << (b & 63));
       atomicOr((unsigned long long*)&a.us[w >> 6], 1ull << (w & 63));
     }
   }
-  const uint64_t bal = __ballot(sp);
-  if (bal) {
-    const uint32_t mb = wave_min_u32(sp ? (uint32_t)b : kNone);
-    if (lane() == 0) {
-      atomicAdd(&a.ctl->fS[slot].v[0], (uint32_t)__popcll(bal));
-      // anything split: C is a candidate again (its unstable bit is set by
-      // the next step's selection) -- not in Algorithm 2
-      atomicMin(&a.ctl->cand[par ^ 1].v[0], (mb < C || a.rcpp) ? mb : C);
-    }
+  const uint32_t mb = wave_min_u32(sp ? (uint32_t)b : kNone);
+  if (lane() == 0) {
+    atomicAdd(&a.ctl->fS[slot].v[0], (uint32_t)__popcll(bal));
+    // anything split: C is a candidate again (its unstable bit is set by
+    // the next step's selection) -- not in Algorithm 2
+    atomicMin(&a.ctl->cand[par ^ 1].v[0], (mb < C || a.rcpp) ? mb : C);
   }
 }
 
@@ -760,7 +897,7 @@ __device__ void phase_y(const Args& a, uint32_t k, const Part& p) {
           sp = test_bit(cur.lt, (uint32_t)b);
         }
       }
-      split2(a, cur, slot, par, C, (int32_t)s, b, sp, epoch);
+      split2(a, cur, slot, par, C, base, b, sp, epoch);
       if (a.trace_work && lane() == 0 && tw[u])
         atomicAdd(&a.ctl->fW[slot].v[2], (uint32_t)__popcll(tw[u]));
       if (pw[u]) {  // iteration k-1's marks in this chunk

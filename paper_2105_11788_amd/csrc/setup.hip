@@ -184,6 +184,14 @@ __global__ void k_indeg(const int32_t* __restrict__ dst, int64_t m, uint32_t* __
   GSTRIDE(i, m) { atomicAdd(&deg[dst[i]], 1u); }
 }
 
+__global__ void k_max_u32(int32_t n, const uint32_t* __restrict__ v, uint32_t* mx_out) {
+  uint32_t mx = 0;
+  GSTRIDE(s, (int64_t)n) { mx = max(mx, v[s]); }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+  if (lane() == 0) atomicMax(mx_out, mx);
+}
+
 __global__ void k_in_scatter(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                              const int32_t* __restrict__ ord, int64_t m,
                              uint32_t* __restrict__ cursor, int32_t* __restrict__ in_src,
@@ -363,9 +371,17 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
     h->nwords = nw;
   }
 
-  // 6. transitions grouped by target
+  // 6. largest out-degree, then transitions grouped by target
   uint32_t* deg;
   BISIM_TRY(tmp.get(&deg, (size_t)n));
+  BISIM_TRY_HIP(hipMemsetAsync(deg, 0, sizeof(uint32_t) * (size_t)n, st));
+  BISIM_TRY_HIP(hipMemsetAsync(red, 0, sizeof(uint32_t), st));
+  if (m > 0) {
+    hipLaunchKernelGGL(k_indeg, dim3(grid_for(m, cu)), dim3(kT), 0, st, src, m, deg);
+    hipLaunchKernelGGL(k_max_u32, dim3(gn), dim3(kT), 0, st, n, deg, red);
+  }
+  BISIM_TRY_HIP(hipMemcpyAsync(&h->max_out, red, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  BISIM_TRY_HIP(hipStreamSynchronize(st));
   BISIM_TRY_HIP(hipMemsetAsync(deg, 0, sizeof(uint32_t) * (size_t)n, st));
   if (m > 0) hipLaunchKernelGGL(k_indeg, dim3(grid_for(m, cu)), dim3(kT), 0, st, dst, m, deg);
   BISIM_TRY(exclusive_scan_u32(deg, h->in_ptr, n, st));

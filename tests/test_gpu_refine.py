@@ -114,6 +114,31 @@ def test_fan_out(B, n):
         assert (r["block"] == exp).all()
 
 
+def hubs_lts(n: int, m: int, K: int, hubs: int, seed: int):
+    """A sparse random LTS plus `hubs` states with transitions into long runs
+    of consecutive states: waves of the mark step then hold the same source
+    many times, with more such sources than a workgroup combines."""
+    rng = np.random.default_rng(seed)
+    base = gen.random_lts(n, m, K, seed)
+    src, lab, dst = [base.src], [base.lab], [base.dst]
+    for h in range(hubs):
+        w = int(rng.integers(600, 2000))
+        lo = int(rng.integers(0, n - w))
+        src.append(np.full(w, h, np.int64))
+        dst.append(np.arange(lo, lo + w, dtype=np.int64))
+        lab.append(rng.integers(0, 3, w))
+    cat = lambda xs: np.concatenate(xs).astype(np.int64)
+    return gen.LTS(n, K, cat(src), cat(lab), cat(dst), None,
+                   name=f"hubs(n={n},m={m},K={K},hubs={hubs},seed={seed})")
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_high_out_degree_sources(B, seed):
+    L = hubs_lts(6000, 24000, 4, 12, seed)
+    assert np.bincount(L.src, minlength=L.n).max() >= 64  # takes the combining marking
+    assert_parity(B, L)
+
+
 @pytest.mark.parametrize("n", [3, 1000, 20000])
 def test_chain(B, n):
     L = gen.chain_tail(n)
