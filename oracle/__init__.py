@@ -17,6 +17,9 @@ Contents
   enumerate_coarsest   exhaustive search over all partitions refining pi_0
                    for the one with fewest blocks that is a bisimulation
                    (the problem statement of section 2), tiny inputs.
+  signature_rounds multi-way signature refinement from pi_pre (the
+                   signature-based approach the paper compares against in
+                   section 5), pure Python: rounds to the fixpoint.
   mlp_*            fp64 reference of the splitter-scoring network (separate
                    module, oracle.mlp).
 """
@@ -282,3 +285,41 @@ def enumerate_coarsest(n, src, lab, dst, init=None):
                 if c[s] == c[t]:
                     assert top[s] == top[t]
     return canonical_from_classes(n, best[1])
+
+
+def signature_rounds(n, K, src, lab, dst, init=None, keep_blocks=False):
+    """Multi-way signature refinement (the signature-based splitting of the
+    comparison systems in section 5): starting from pi_pre (section 4.1),
+    every round gives each state the signature {(a, block(t)) : s -a-> t},
+    and states stay together iff they were together and their signatures are
+    equal; every new block is named by its smallest state.  Stops after the
+    first round that changes nothing.  Returns dict: block (canonical),
+    rounds (including the final unchanged one), blocks (per-round partitions,
+    if keep_blocks).  Pure Python: meant for m up to about 10^5."""
+    pre = preprocess(n, K, src, lab, dst, init)["pre_block"]
+    part = [int(x) for x in pre]
+    out = {(int(a), int(b), int(c)) for a, b, c in zip(src, lab, dst)}
+    succ = [[] for _ in range(n)]
+    for s_, a, t in out:
+        succ[s_].append((a, t))
+    nblocks = len(set(part))
+    rounds = 0
+    hist = []
+    while True:
+        rounds += 1
+        leader = {}
+        new = [0] * n
+        for s_ in range(n):
+            key = (part[s_], frozenset((a, part[t]) for a, t in succ[s_]))
+            new[s_] = leader.setdefault(key, s_)  # states are visited in increasing order
+        part = new
+        if keep_blocks:
+            hist.append(np.array(part, np.int32))
+        nb = len(leader)
+        if nb == nblocks:
+            break
+        nblocks = nb
+    res = {"block": np.array(part, np.int32), "rounds": rounds}
+    if keep_blocks:
+        res["blocks"] = hist
+    return res
