@@ -316,6 +316,42 @@ def form_plain(bisim, gen, args):
     return res
 
 
+def form_signature(bisim, gen, args):
+    """The multi-way signature refinement baseline on the same workload (the
+    splitting style of the paper's section 5 comparison systems): time to the
+    fixpoint and rounds, beside the labelled algorithm's figures."""
+    wl = workload(args.workload)
+    L = wl["make"](gen)
+    log(f"workload {args.workload}: n={L.n} m={L.m} K={L.K}")
+    src, lab, dst, init = upload(bisim, L)
+    h = bisim.LTS(src, lab, dst, L.n, L.K, init)
+    h.set_option(bisim.OPT_ALGORITHM, bisim.ALGORITHM_SIGNATURE)
+    out = bisim.DeviceArray(L.n, np.int32)
+    for w in range(args.warmup):
+        _, st = h.run(out)
+        log(f"warmup {w}: rounds={st.iterations} blocks={st.blocks} t_alg={st.t_alg_ms:.1f} ms")
+    bisim.synchronize()
+    t0 = time.perf_counter()
+    alg_ms = []
+    for _ in range(args.steps):
+        _, st = h.run(out)
+        alg_ms.append(st.t_alg_ms)
+    bisim.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    h.close()
+    log(f"{ms:.2f} ms/step, rounds={st.iterations}, blocks={st.blocks}")
+    cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
+           "rounds": st.iterations, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
+           "form": "signature", "algorithm": "multi-way signature refinement (baseline)"}
+    res = base_record(args, "transitions*rounds/sec (signature baseline to fixpoint)",
+                      L.m * st.iterations / (ms * 1e-3), ms, cfg)
+    res.update({"seconds_to_fixpoint": ms / 1000.0, "t_pre_ms": st.t_pre_ms,
+                "t_alg_ms": float(np.mean(alg_ms)), "roofline": None,
+                "note": "a comparison baseline, not the paper's method; its time is "
+                        "dominated by library radix sorts"})
+    return res
+
+
 def form_batched(bisim, gen, args):
     t = time.perf_counter()
     insts = gen.batch(count=args.count, n_lo=100, n_hi=args.n_hi, seed=1)
@@ -414,7 +450,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "signature"])
     ap.add_argument("--workload", default="planted-quotient-1M",
                     help="one of " + ", ".join(sorted(WORKLOADS)) + ", or fan-out-<n>")
     ap.add_argument("--engine", type=int, default=0,
@@ -450,7 +486,8 @@ def main():
     if bisim.device_count() < 1:
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
-    res = {"plain": form_plain, "batched": form_batched, "learned": form_learned}[args.form](
+    res = {"plain": form_plain, "batched": form_batched, "learned": form_learned,
+           "signature": form_signature}[args.form](
         bisim, gen, args)
     print(json.dumps(res), flush=True)
 

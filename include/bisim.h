@@ -145,7 +145,24 @@ const char* bisim_last_error(void);
                                      leader-normalised pi_0 without preprocessing, keeps
                                      one mark per state, and does not make the splitter
                                      unstable again after a split.  Same result, its own
-                                     iteration count; the plain policy only. */
+                                     iteration count; the plain policy only.
+                                     BISIM_ALGORITHM_SIGNATURE: multi-way signature
+                                     refinement, the signature-based splitting of the
+                                     systems the paper compares against (section 5), an
+                                     in-house baseline: from pi_pre, every round regroups
+                                     the states by (block, {(action, block of target)})
+                                     until a round changes nothing; iterations = rounds.
+                                     Set hashes, checked at the fixpoint with a second
+                                     independent hash (BISIM_E_DEVICE if three seeds
+                                     fail); no splitter policy or trace
+                                     (BISIM_E_UNSUPPORTED), m < 2^31 and (distinct
+                                     actions per state) * n < 2^32 (else
+                                     BISIM_E_UNSUPPORTED).  Device memory during a run:
+                                     20 bytes per transition and 48 per state, plus the
+                                     radix sort's scratch. */
+#define BISIM_ALGORITHM_RCPP 2
+#define BISIM_ALGORITHM_LABELLED 3
+#define BISIM_ALGORITHM_SIGNATURE 100
 bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
 
 /*

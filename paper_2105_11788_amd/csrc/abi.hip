@@ -133,7 +133,8 @@ bisim_status coarsest_partition(bisim_lts* h, int32_t* block_id, bisim_stats* st
     set_error("coarsest_partition: NULL handle or output");
     return BISIM_E_INVALID;
   }
-  bisim_status rc = refine_run(h, block_id);
+  bisim_status rc = h->algorithm == BISIM_ALGORITHM_SIGNATURE ? signature_run(h, block_id)
+                                                               : refine_run(h, block_id);
   if (st) {
     st->iterations = h->last_iters;
     st->blocks = h->last_blocks;
@@ -174,7 +175,9 @@ bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value) {
       h->profile_every = value;
       return BISIM_OK;
     case BISIM_OPT_ALGORITHM:
-      if (value != 2 && value != 3) break;
+      if (value != BISIM_ALGORITHM_RCPP && value != BISIM_ALGORITHM_LABELLED &&
+          value != BISIM_ALGORITHM_SIGNATURE)
+        break;
       if (value == 2 && (h->K != 1 || (h->n > 0 && !h->init_block))) {
         set_error("bisim_set_option: Algorithm 2 needs a one-action LTS (num_actions = 1)");
         return BISIM_E_UNSUPPORTED;

@@ -140,6 +140,7 @@ struct bisim_lts {
   uint32_t* woff = nullptr;      // [n+1] mark-word offsets (only when !uniform)
   int uniform = 1;               // every state has <= 64 actions: word index = state
   uint32_t max_out = 0;          // largest number of outgoing transitions of a state
+  uint32_t max_ranks = 0;        // largest number of distinct actions of a state
   uint64_t nwords = 0;
   int64_t pre_blocks = 0;
   int64_t mark_length = 0;
@@ -212,6 +213,8 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
 // refine.hip
 bisim_status refine_run(bisim_lts* h, int32_t* block_id);
 bisim_status refine_alloc(bisim_lts* h);
+// signature.hip: multi-way signature refinement (baseline)
+bisim_status signature_run(bisim_lts* h, int32_t* block_id);
 }  // namespace bisim
 
 struct bisim_mlp;

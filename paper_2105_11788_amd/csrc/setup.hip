@@ -357,6 +357,7 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
   h->pre_blocks = red_h[1];
   h->mark_length = (int64_t)red64_h;
   h->uniform = red_h[0] <= 64;
+  h->max_ranks = red_h[0];
   if (h->uniform) {
     h->nwords = (uint64_t)n;
   } else {

@@ -1,0 +1,98 @@
+"""GPU parity of the multi-way signature refinement baseline
+(BISIM_ALGORITHM_SIGNATURE) against the oracle: canonical block ids equal to
+Kanellakis-Smolka's, round counts equal to the oracle's signature_rounds."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_11788_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2105_11788_amd import bisim
+    bisim.load_library()
+    assert bisim.device_count() > 0, "GPU tests need a GPU"
+    return bisim
+
+
+def run_sig(B, L, trace=0):
+    from paper_2105_11788_amd.bisim import DeviceArray
+    t = lambda a: DeviceArray.from_numpy(a, np.int32)
+    init = None if L.init is None else t(L.init)
+    with B.LTS(t(L.src), t(L.lab), t(L.dst), L.n, L.K, init) as h:
+        h.set_option(B.OPT_ALGORITHM, B.ALGORITHM_SIGNATURE)
+        if trace:
+            h.set_trace(trace)
+        blk, st = h.run()
+        return blk.numpy(), st
+
+
+def assert_parity(B, L, rounds=True):
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    blk, st = run_sig(B, L)
+    assert (blk == ks).all(), L.name
+    assert st.blocks == nb
+    if rounds:
+        r = oracle.signature_rounds(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        assert st.iterations == r["rounds"], (L.name, st.iterations, r["rounds"])
+
+
+@pytest.mark.parametrize("n", [4, 5, 64, 300, 2000])
+def test_fan_out(B, n):
+    assert_parity(B, gen.fan_out(n))
+
+
+@pytest.mark.parametrize("n", [2, 3, 1000])
+def test_chain(B, n):
+    assert_parity(B, gen.chain_tail(n))
+
+
+def test_figures(B):
+    assert_parity(B, gen.figure1())
+    assert_parity(B, gen.figure2())
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random(B, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(50, 3000))
+    L = gen.random_lts(n, int(rng.integers(0, 4 * n)), int(rng.integers(1, 6)), seed,
+                       init_blocks=seed % 4)
+    assert_parity(B, L)
+
+
+def test_kripke_and_many_actions(B):
+    assert_parity(B, gen.kripke_uniform(2000, 9000, seed=3))
+    assert_parity(B, gen.uniform_zipf(1500, 8000, K=64, seed=2))
+
+
+def test_planted_quotient_medium(B):
+    assert_parity(B, gen.planted_quotient(q=3000, deg_mean=6.0, K=8, seed=4))
+
+
+def test_planted_quotient_1m_full(B):
+    # round count checked against the C-side oracles only through the result
+    L = gen.planted_quotient()
+    assert_parity(B, L, rounds=False)
+
+
+def test_empty_and_errors(B):
+    from paper_2105_11788_amd.bisim import BisimError
+    e = gen.LTS(0, 1, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0, np.int64),
+                None, name="empty")
+    blk, st = run_sig(B, e)
+    assert blk.size == 0 and st.iterations == 0
+    no_tr = gen.LTS(5, 1, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0, np.int64),
+                    None, name="no transitions")
+    assert_parity(B, no_tr)
+    with pytest.raises(BisimError):
+        run_sig(B, gen.fan_out(10), trace=8)
+    # (distinct actions of a state) * n >= 2^32: refused before any kernel
+    n = 70_000
+    big = gen.LTS(n, n, np.zeros(n, np.int64), np.arange(n, dtype=np.int64),
+                  np.arange(n, dtype=np.int64), None, name="one state, 70000 actions")
+    with pytest.raises(BisimError):
+        run_sig(B, big)
