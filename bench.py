@@ -174,7 +174,29 @@ def cpu_baseline(L, target_s: float = 12.0):
         "sample": f"lock-step simulation of the labelled algorithm (CPU oracle), iterations "
                   f"2..{1 + X_done} of the same workload, {el:.1f} s after subtracting the "
                   f"preprocessing + first iteration ({t1:.2f} s); single thread",
+        "host": host_cpu(),
     }
+
+
+def host_cpu():
+    """CPU model and logical core count of the host that ran the baseline."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def sem(xs):
+    """Standard error of the mean (None for fewer than two samples)."""
+    if len(xs) < 2:
+        return None
+    return float(np.std(xs, ddof=1) / np.sqrt(len(xs)))
 
 
 def upload(bisim, L):
@@ -221,14 +243,17 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
                      max(1, st.iterations // 200) if st is not None else 256)
     bisim.synchronize()
     t0 = time.perf_counter()
-    alg_ms = []
+    alg_ms, step_ms = [], []
     for _ in range(args.steps):
-        _, st = h.run(out)
+        ts = time.perf_counter()
+        _, st = h.run(out)  # returns after the fixpoint is on the host
+        step_ms.append((time.perf_counter() - ts) * 1000.0)
         alg_ms.append(st.t_alg_ms)
     bisim.synchronize()
     t1 = time.perf_counter()
     res = {"ms_per_step": (t1 - t0) * 1000.0 / args.steps, "stats": st,
-           "kern_ms": float(np.mean(alg_ms)), "block": out.numpy()}
+           "kern_ms": float(np.mean(alg_ms)), "block": out.numpy(),
+           "ms_per_step_sem": sem(step_ms), "t_alg_ms_sem": sem(alg_ms)}
     if engine != 1:
         res["phase_ms"], res["phase_samples"] = h.phase_times()
         h.set_option(bisim.OPT_PROFILE_EVERY, 0)
@@ -290,6 +315,9 @@ def form_plain(bisim, gen, args):
                       L.m * iters / (r["ms_per_step"] * 1e-3), r["ms_per_step"], cfg)
     res.update({
         "seconds_to_fixpoint": r["ms_per_step"] / 1000.0,
+        "ms_per_step_sem": r["ms_per_step_sem"],
+        "t_alg_ms": r["kern_ms"],
+        "t_alg_ms_sem": r["t_alg_ms_sem"],
         "t_pre_ms": st.t_pre_ms,
         "us_per_iteration": r["kern_ms"] * 1000.0 / iters,
         "roofline": {
@@ -448,7 +476,7 @@ def form_learned(bisim, gen, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "signature"])
     ap.add_argument("--workload", default="planted-quotient-1M",

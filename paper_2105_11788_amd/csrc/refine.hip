@@ -82,17 +82,28 @@ __global__ void __launch_bounds__(kT) k_phase_c(Args a, uint32_t k) {
   phase_c<L, T>(a, k & 1, k, a.ctl->state.v[3], part());
 }
 // plain policy: two kernels per iteration
+// The per-phase kernels load the control words and their first scan chunk
+// together, before any branch.
 template <bool Agg>
 __global__ void __launch_bounds__(kT) k_fused_x(Args a, uint32_t k) {
-  if (a.ctl->state.v[1]) return;
   const Part p = part();
-  const uint32_t C = head2(a, k, p);
+  XChunk ch;
+  load_xchunk(a, k, p.gwave * kWave * kFusedU, ch);
+  const uint32_t done = a.ctl->state.v[1];
+  const uint32_t cand = a.ctl->cand[k & 1].v[0];
+  if (done) return;
+  const uint32_t C = head2(a, k, p, cand);
   if (C == kNone) return;
-  phase_x<Agg>(a, k, C, p);
+  phase_x<Agg>(a, k, C, p, &ch);
 }
 __global__ void __launch_bounds__(kT) k_fused_y(Args a, uint32_t k) {
-  if (a.ctl->state.v[1]) return;
-  phase_y(a, k, part());
+  const Part p = part();
+  YChunk ch;
+  load_ychunk(a, k, p.gwave * kWave * kFusedU, ch);
+  const uint32_t done = a.ctl->state.v[1];
+  const uint32_t C = a.ctl->state.v[3];
+  if (done) return;
+  phase_y(a, k, p, C, &ch);
 }
 
 constexpr int kST = 1024;  // re-scoring + selection workgroup (learned policy)
@@ -192,7 +203,7 @@ __global__ void __launch_bounds__(kPT) k_persistent(Args a) {
       else
         phase_x<false>(a, k, C, p);
       if (!grid_barrier(a.ctl, gen)) break;
-      phase_y(a, k, p);
+      phase_y(a, k, p, a.ctl->state.v[3]);
       if (!grid_barrier(a.ctl, gen)) break;
     }
     return;

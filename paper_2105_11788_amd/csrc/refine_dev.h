@@ -516,8 +516,7 @@ __device__ __forceinline__ int32_t lazy_label(const Args& a, const uint64_t* pre
   return (uint32_t)(v >> 32) == k ? (int32_t)(kNone - (uint32_t)v) : b;
 }
 
-__device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
-  const uint32_t C = a.ctl->cand[k & 1].v[0];
+__device__ uint32_t head2(const Args& a, uint32_t k, const Part& p, uint32_t C) {
   const bool over = (k + 1 > a.iter_cap);
   if (p.gtid == 0) {
     Ctl* c = a.ctl;
@@ -555,10 +554,50 @@ __device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
   }
   return (C == kNone || over) ? kNone : C;
 }
+__device__ uint32_t head2(const Args& a, uint32_t k, const Part& p) {
+  return head2(a, k, p, a.ctl->cand[k & 1].v[0]);
+}
 
 // chunks of 64 states per wave and step of the two-step engine's scans; all
 // their loads are issued before any is used
 constexpr uint32_t kFusedU = 2;
+
+// The loads of a wave's first scan step, which depend on nothing the step
+// computes: the per-phase kernels issue them at entry, beside the control
+// block's, so that they are not one more round trip on the kernel's chain.
+struct XChunk {
+  int32_t bv[kFusedU];  // block[] of the chunk's states
+  uint64_t fw[kFusedU]; // their split flags of the previous iteration
+};
+__device__ __forceinline__ void load_xchunk(const Args& a, uint32_t k, uint32_t base0,
+                                            XChunk& c) {
+  const uint32_t n = (uint32_t)a.n;
+  const uint64_t* prv_sb = fpar(a, (k & 1) ^ 1).sb;
+#pragma unroll
+  for (uint32_t u = 0; u < kFusedU; ++u) {
+    const uint32_t base = base0 + u * kWave, t = base + lane();
+    c.bv[u] = t < n ? a.block[t] : -1;
+    c.fw[u] = base < n ? prv_sb[base >> 6] : 0ull;
+  }
+}
+struct YChunk {
+  int32_t bv[kFusedU];  // block[] of the chunk's states
+  uint64_t tw[kFusedU]; // touched bits of this iteration
+  uint64_t pw[kFusedU]; // touched bits of the previous one (marks to clear)
+};
+__device__ __forceinline__ void load_ychunk(const Args& a, uint32_t k, uint32_t base0,
+                                            YChunk& c) {
+  const uint32_t n = (uint32_t)a.n;
+  const uint64_t* ctb = fpar(a, k & 1).tb;
+  const uint64_t* ptb = fpar(a, (k & 1) ^ 1).tb;
+#pragma unroll
+  for (uint32_t u = 0; u < kFusedU; ++u) {
+    const uint32_t base = base0 + u * kWave, s = base + lane();
+    c.bv[u] = s < n ? a.block[s] : 0;
+    c.tw[u] = base < n ? ctb[base >> 6] : 0ull;
+    c.pw[u] = base < n ? ptb[base >> 6] : 0ull;
+  }
+}
 
 // Marks of source s (slots `bits` of its word wi): the mark word, and the
 // touched-leader bit when s leads its block.  Every atomic is fire-and-forget
@@ -678,7 +717,8 @@ __device__ __forceinline__ void mark_lanes(const Args& a, const FPar& cur, const
 }
 
 template <bool Agg>
-__device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
+__device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p,
+                        const XChunk* first = nullptr) {
   const uint32_t par = k & 1, slot = k % 3;
   const FPar cur = fpar(a, par), prv = fpar(a, par ^ 1);
   uint32_t* cand = &a.ctl->cand[par ^ 1].v[0];
@@ -735,22 +775,19 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p) {
     if (pc < next) next = pc;  // its bit may not be visible to this search yet
     if (lane() == 0 && next != kNone) atomicMin(cand, next);
   }
-  for (uint32_t base0 = p.gwave * kWave * kFusedU; base0 < n;
-       base0 += p.gwaves * kWave * kFusedU) {
-    int32_t bv[kFusedU];
-    uint64_t fw[kFusedU];
+  const uint32_t b00 = p.gwave * kWave * kFusedU;
+  for (uint32_t base0 = b00; base0 < n; base0 += p.gwaves * kWave * kFusedU) {
+    XChunk ch;
+    if (first && base0 == b00)
+      ch = *first;
+    else
+      load_xchunk(a, k, base0, ch);
 #pragma unroll
     for (uint32_t u = 0; u < kFusedU; ++u) {
       const uint32_t base = base0 + u * kWave, t = base + lane();
-      bv[u] = t < n ? a.block[t] : -1;
-      fw[u] = base < n ? prv.sb[base >> 6] : 0ull;
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < kFusedU; ++u) {
-      const uint32_t base = base0 + u * kWave, t = base + lane();
-      int32_t lab = bv[u];
+      int32_t lab = ch.bv[u];
       bool lead = false;
-      if (t < n && ((fw[u] >> lane()) & 1ull)) {  // split in k-1: relabel now
+      if (t < n && ((ch.fw[u] >> lane()) & 1ull)) {  // split in k-1: relabel now
         const uint64_t v = a.nlw[lab];
         if ((uint32_t)(v >> 32) == k) {
           lab = (int32_t)(kNone - (uint32_t)v);
@@ -856,23 +893,22 @@ __device__ __forceinline__ void split2(const Args& a, const FPar& cur, uint32_t 
 // Y(k): one pass over all states.  A touched state (tb) splits iff its marks
 // differ from its leader's; an untouched one iff its leader was touched (lt).
 // The same pass clears what iteration k-1 left in the other half.
-__device__ void phase_y(const Args& a, uint32_t k, const Part& p) {
+__device__ void phase_y(const Args& a, uint32_t k, const Part& p, uint32_t C,
+                        const YChunk* first = nullptr) {
   const uint32_t par = k & 1, slot = k % 3;
   const FPar cur = fpar(a, par), prv = fpar(a, par ^ 1);
   const uint64_t epoch = (uint64_t)(k + 1) << 32;
-  const uint32_t C = a.ctl->state.v[3];
   const uint32_t n = (uint32_t)a.n;
-  for (uint32_t base0 = p.gwave * kWave * kFusedU; base0 < n;
-       base0 += p.gwaves * kWave * kFusedU) {
-    int32_t bv[kFusedU];
-    uint64_t tw[kFusedU], pw[kFusedU];
-#pragma unroll
-    for (uint32_t u = 0; u < kFusedU; ++u) {
-      const uint32_t base = base0 + u * kWave, s = base + lane();
-      bv[u] = s < n ? a.block[s] : 0;
-      tw[u] = base < n ? cur.tb[base >> 6] : 0ull;
-      pw[u] = base < n ? prv.tb[base >> 6] : 0ull;
-    }
+  const uint32_t b00 = p.gwave * kWave * kFusedU;
+  for (uint32_t base0 = b00; base0 < n; base0 += p.gwaves * kWave * kFusedU) {
+    YChunk ch;
+    if (first && base0 == b00)
+      ch = *first;
+    else
+      load_ychunk(a, k, base0, ch);
+    const int32_t* bv = ch.bv;
+    const uint64_t* tw = ch.tw;
+    const uint64_t* pw = ch.pw;
 #pragma unroll
     for (uint32_t u = 0; u < kFusedU; ++u) {
       const uint32_t base = base0 + u * kWave, s = base + lane();
