@@ -568,6 +568,8 @@ constexpr uint32_t kFusedU = 2;
 struct XChunk {
   int32_t bv[kFusedU];  // block[] of the chunk's states
   uint64_t fw[kFusedU]; // their split flags of the previous iteration
+  uint32_t ib[kFusedU]; // in_ptr[t], in_ptr[t + 1]: their in-transition ranges
+  uint32_t ie[kFusedU];
 };
 __device__ __forceinline__ void load_xchunk(const Args& a, uint32_t k, uint32_t base0,
                                             XChunk& c) {
@@ -578,6 +580,8 @@ __device__ __forceinline__ void load_xchunk(const Args& a, uint32_t k, uint32_t 
     const uint32_t base = base0 + u * kWave, t = base + lane();
     c.bv[u] = t < n ? a.block[t] : -1;
     c.fw[u] = base < n ? prv_sb[base >> 6] : 0ull;
+    c.ib[u] = t < n ? a.in_ptr[t] : 0u;
+    c.ie[u] = t < n ? a.in_ptr[t + 1] : 0u;
   }
 }
 struct YChunk {
@@ -737,11 +741,20 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p,
     // (on the last wave, which has the least scan work; the previous splitter
     // is unstable again if anything split, unless it is C itself; it is
     // folded in here, where nothing else writes the set)
-    uint32_t pc = kNone;
-    if (k > 0 && !a.rcpp && a.ctl->fS[(k - 1) % 3].v[0] != 0) pc = a.ctl->fC[(k - 1) % 3].v[0];
-    if (pc == C) pc = kNone;
+    // all loads that do not depend on each other first: the previous
+    // splitter's slots, C's word and the first window of summary words
     const uint32_t w0 = C >> 6;
-    uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
+    const uint32_t from = (k == 0) ? 0u : w0;  // a forced first splitter need not be the smallest
+    const uint32_t nsw = (nwd + 63u) >> 6;
+    const uint32_t q0 = from >> 6;
+    const uint32_t fs1 = k > 0 ? a.ctl->fS[(k - 1) % 3].v[0] : 0u;
+    const uint32_t fc1 = k > 0 ? a.ctl->fC[(k - 1) % 3].v[0] : kNone;
+    const uint64_t ubw = a.ub[w0];
+    const uint64_t sv0 = q0 + lane() < nsw ? a.us[q0 + lane()] : 0ull;
+    uint32_t pc = kNone;
+    if (k > 0 && !a.rcpp && fs1 != 0) pc = fc1;
+    if (pc == C) pc = kNone;
+    uint64_t bits = ubw & ~(1ull << (C & 63));
     if (pc != kNone && (pc >> 6) == w0) bits |= 1ull << (pc & 63);
     if (lane() == 0) {
       a.ub[w0] = bits;
@@ -751,12 +764,10 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p,
         atomicOr((unsigned long long*)&a.us[pc >> 12], 1ull << ((pc >> 6) & 63));
       }
     }
-    const uint32_t from = (k == 0) ? 0u : w0;  // a forced first splitter need not be the smallest
-    const uint32_t nsw = (nwd + 63u) >> 6;
     uint32_t next = kNone;
-    for (uint32_t q = from >> 6; q < nsw; q += kWave) {
+    for (uint32_t q = q0; q < nsw; q += kWave) {
       const uint32_t qq = q + lane();
-      uint64_t sv = qq < nsw ? a.us[qq] : 0ull;
+      uint64_t sv = q == q0 ? sv0 : (qq < nsw ? a.us[qq] : 0ull);
       if (qq == (from >> 6)) sv &= ~0ull << (from & 63);
       if (qq == (w0 >> 6)) {
         const uint64_t b0 = 1ull << (w0 & 63);
@@ -806,8 +817,8 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p,
       if (hits == 0) continue;
       uint32_t beg = 0, deg = 0;
       if (hit) {
-        beg = a.in_ptr[t];
-        deg = a.in_ptr[t + 1] - beg;
+        beg = ch.ib[u];
+        deg = ch.ie[u] - beg;
       }
       const uint32_t incl = wave_incl_scan_u32(deg);
       const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
