@@ -568,8 +568,6 @@ constexpr uint32_t kFusedU = 2;
 struct XChunk {
   int32_t bv[kFusedU];  // block[] of the chunk's states
   uint64_t fw[kFusedU]; // their split flags of the previous iteration
-  uint32_t ib[kFusedU]; // in_ptr[t], in_ptr[t + 1]: their in-transition ranges
-  uint32_t ie[kFusedU];
 };
 __device__ __forceinline__ void load_xchunk(const Args& a, uint32_t k, uint32_t base0,
                                             XChunk& c) {
@@ -580,8 +578,6 @@ __device__ __forceinline__ void load_xchunk(const Args& a, uint32_t k, uint32_t 
     const uint32_t base = base0 + u * kWave, t = base + lane();
     c.bv[u] = t < n ? a.block[t] : -1;
     c.fw[u] = base < n ? prv_sb[base >> 6] : 0ull;
-    c.ib[u] = t < n ? a.in_ptr[t] : 0u;
-    c.ie[u] = t < n ? a.in_ptr[t + 1] : 0u;
   }
 }
 struct YChunk {
@@ -817,8 +813,8 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p,
       if (hits == 0) continue;
       uint32_t beg = 0, deg = 0;
       if (hit) {
-        beg = ch.ib[u];
-        deg = ch.ie[u] - beg;
+        beg = a.in_ptr[t];
+        deg = a.in_ptr[t + 1] - beg;
       }
       const uint32_t incl = wave_incl_scan_u32(deg);
       const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
