@@ -88,7 +88,7 @@ template <bool Agg>
 __global__ void __launch_bounds__(kT) k_fused_x(Args a, uint32_t k) {
   const Part p = part();
   XChunk ch;
-  load_xchunk(a, k, p.gwave * kWave * kFusedU, ch);
+  load_xchunk<x_chunks<Agg>()>(a, k, p.gwave * kWave * x_chunks<Agg>(), ch);
   const uint32_t done = a.ctl->state.v[1];
   const uint32_t cand = a.ctl->cand[k & 1].v[0];
   if (done) return;

@@ -569,12 +569,19 @@ struct XChunk {
   int32_t bv[kFusedU];  // block[] of the chunk's states
   uint64_t fw[kFusedU]; // their split flags of the previous iteration
 };
+// chunks per wave and step of X: the combining variant takes one, so that
+// twice as many waves share the marks of a large splitter
+template <bool Agg>
+constexpr uint32_t x_chunks() {
+  return Agg ? 1u : kFusedU;
+}
+template <uint32_t U>
 __device__ __forceinline__ void load_xchunk(const Args& a, uint32_t k, uint32_t base0,
                                             XChunk& c) {
   const uint32_t n = (uint32_t)a.n;
   const uint64_t* prv_sb = fpar(a, (k & 1) ^ 1).sb;
 #pragma unroll
-  for (uint32_t u = 0; u < kFusedU; ++u) {
+  for (uint32_t u = 0; u < U; ++u) {
     const uint32_t base = base0 + u * kWave, t = base + lane();
     c.bv[u] = t < n ? a.block[t] : -1;
     c.fw[u] = base < n ? prv_sb[base >> 6] : 0ull;
@@ -669,51 +676,128 @@ struct HotTab {
   unsigned long long* b;  // [kHot] its slot bits
 };
 
-// Mark the transitions held by the lanes of a wave (valid lanes: source s,
-// action rank o; wave-uniform call).  When the first lane's source recurs in
-// the wave (a state with transitions into many of C's members, like
-// Fan_out_n's states 0 and 1), the lanes of the first two sources are
-// combined and their bits go to the workgroup's table: one atomic per
-// transition, or even per wave, would serialise on that state's words.
-__device__ __forceinline__ void mark_lanes(const Args& a, const FPar& cur, const uint64_t* prev_sb,
-                                           uint32_t slot, uint32_t k, int32_t s, int32_t o,
-                                           bool valid, const HotTab& ht) {
-  if (!a.uniform) {  // a state's slots may span several words
-    if (valid)
-      mark_word(a, cur, prev_sb, slot, k, s, (uint64_t)a.woff[s] + (uint32_t)(o >> 6),
-                1ull << (o & 63));
-    touch_lanes(cur, s, valid);
-    return;
+// Mark the transitions held by the lanes of a wave when a state's slots may
+// span several words (valid lanes: source s, action rank o; wave-uniform
+// call): one mark atomic per lane, touched bits combined per word.
+__device__ __forceinline__ void mark_lanes_wide(const Args& a, const FPar& cur,
+                                                const uint64_t* prev_sb, uint32_t slot, uint32_t k,
+                                                int32_t s, int32_t o, bool valid) {
+  if (valid)
+    mark_word(a, cur, prev_sb, slot, k, s, (uint64_t)a.woff[s] + (uint32_t)(o >> 6),
+              1ull << (o & 63));
+  touch_lanes(cur, s, valid);
+}
+
+// Transition index of entry ee of a wave's in-transition list, whose lane l
+// owns entries [incl_l - deg_l, incl_l) starting at in_ptr position beg_l
+// (wave-uniform call: shuffles only).
+__device__ __forceinline__ uint32_t edge_of(uint32_t incl, uint32_t beg, uint32_t deg,
+                                            uint32_t ee) {
+  uint32_t j = 0;  // owner lane: the first with incl > ee
+#pragma unroll
+  for (uint32_t step = 32; step >= 1; step >>= 1) {
+    const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
+    if (probe <= ee) j += step;
   }
+  const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
+  const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
+  const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
+  return jb + (ee - (ji - jd));
+}
+
+// Combining of recurring sources: lanes of the wave's first two
+// sources, when the first recurs, go to the workgroup's table; returns
+// whether this lane is still to be marked (wave-uniform call).
+__device__ __forceinline__ bool take_recurring(const Args& a, const FPar& cur,
+                                               const uint64_t* prev_sb, uint32_t slot, uint32_t k,
+                                               int32_t s, int32_t o, bool valid, const HotTab& ht) {
   const uint64_t vb = __ballot(valid);
-  if (!vb) return;
+  if (!vb) return false;
   const int32_t sf = __shfl(s, __ffsll((unsigned long long)vb) - 1, kWave);
   bool pending = valid;
-  if (__popcll(__ballot(valid && s == sf)) > 1) {
+  if (__popcll(__ballot(valid && s == sf)) <= 1) return pending;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const uint64_t pb = __ballot(pending);
-      if (!pb) return;
-      const int f = __ffsll((unsigned long long)pb) - 1;
-      const int32_t s0 = __shfl(s, f, kWave);
-      const bool mine = pending && s == s0;
-      const uint64_t bits = wave_or_u64(mine ? 1ull << (o & 63) : 0ull);
-      if ((int)lane() == f) {
-        bool put = false;
-        for (int i = 0; i < kHot && !put; ++i) {
-          const int32_t old = atomicCAS(&ht.s[i], -1, s0);
-          if (old == -1 || old == s0) {
-            atomicOr(&ht.b[i], (unsigned long long)bits);
-            put = true;
-          }
+  for (int r = 0; r < 2; ++r) {
+    const uint64_t pb = __ballot(pending);
+    if (!pb) break;
+    const int f = __ffsll((unsigned long long)pb) - 1;
+    const int32_t s0 = __shfl(s, f, kWave);
+    const bool mine = pending && s == s0;
+    const uint64_t bits = wave_or_u64(mine ? 1ull << (o & 63) : 0ull);
+    if ((int)lane() == f) {
+      bool put = false;
+      for (int i = 0; i < kHot && !put; ++i) {
+        const int32_t old = atomicCAS(&ht.s[i], -1, s0);
+        if (old == -1 || old == s0) {
+          atomicOr(&ht.b[i], (unsigned long long)bits);
+          put = true;
         }
-        if (!put) mark_state(a, cur, prev_sb, slot, k, s0, (uint64_t)s0, bits);
       }
-      pending = pending && !mine;
+      if (!put) mark_state(a, cur, prev_sb, slot, k, s0, (uint64_t)s0, bits);
+    }
+    pending = pending && !mine;
+  }
+  return pending;
+}
+
+// The combining marking of a chunk's in-transitions (uniform layout): up to
+// kRounds wave-rounds at a time, with every load of the group (sources,
+// ranks, labels) issued before any of its atomics.  On CDNA a load waits for
+// the wave's earlier memory operations, atomics included, so marking round by
+// round would put a full memory round trip per round on the wave's chain,
+// and a large splitter gives a wave many rounds (wave-uniform call).
+constexpr uint32_t kRounds = 4;
+__device__ __forceinline__ void mark_rounds(const Args& a, const FPar& cur, const uint64_t* prev_sb,
+                                            uint32_t slot, uint32_t k, uint32_t incl,
+                                            uint32_t beg, uint32_t deg, uint32_t total,
+                                            const HotTab& ht) {
+  for (uint32_t e0 = 0; e0 < total; e0 += kWave * kRounds) {
+    int32_t s[kRounds], o[kRounds], lab[kRounds];
+    bool pend[kRounds], fl[kRounds];
+#pragma unroll
+    for (uint32_t g = 0; g < kRounds; ++g) {
+      s[g] = 0;
+      o[g] = 0;
+      pend[g] = false;
+      const uint32_t eg = e0 + g * kWave;
+      if (eg >= total) continue;  // wave-uniform
+      const uint32_t e = eg + lane();
+      const bool valid = e < total;
+      const uint32_t edge = edge_of(incl, beg, deg, valid ? e : total - 1);
+      if (valid) {
+        s[g] = a.in_src[edge];
+        o[g] = a.in_ord[edge];
+      }
+      pend[g] = valid;
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < kRounds; ++g)
+      if (e0 + g * kWave < total)
+        pend[g] = take_recurring(a, cur, prev_sb, slot, k, s[g], o[g], pend[g], ht);
+#pragma unroll
+    for (uint32_t g = 0; g < kRounds; ++g) {
+      lab[g] = pend[g] ? a.block[s[g]] : -1;
+      fl[g] = pend[g] && test_bit(prev_sb, (uint32_t)s[g]);
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < kRounds; ++g) {
+      if (fl[g]) {  // lazy_label
+        const uint64_t v = a.nlw[lab[g]];
+        if ((uint32_t)(v >> 32) == k) lab[g] = (int32_t)(kNone - (uint32_t)v);
+      }
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < kRounds; ++g) {
+      if (pend[g]) {
+        atomicOr((unsigned long long*)&cur.mw[s[g]], 1ull << (o[g] & 63));
+        if (lab[g] == s[g]) {  // a touched leader
+          atomicOr((unsigned long long*)&cur.lt[s[g] >> 6], 1ull << (s[g] & 63));
+          a.ctl->fL[slot].v[0] = 1;
+        }
+      }
+      if (e0 + g * kWave < total) touch_lanes(cur, s[g], pend[g]);
     }
   }
-  if (pending) mark_word(a, cur, prev_sb, slot, k, s, (uint64_t)s, 1ull << (o & 63));
-  touch_lanes(cur, s, pending);
 }
 
 template <bool Agg>
@@ -782,15 +866,16 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p,
     if (pc < next) next = pc;  // its bit may not be visible to this search yet
     if (lane() == 0 && next != kNone) atomicMin(cand, next);
   }
-  const uint32_t b00 = p.gwave * kWave * kFusedU;
-  for (uint32_t base0 = b00; base0 < n; base0 += p.gwaves * kWave * kFusedU) {
+  constexpr uint32_t U = x_chunks<Agg>();
+  const uint32_t b00 = p.gwave * kWave * U;
+  for (uint32_t base0 = b00; base0 < n; base0 += p.gwaves * kWave * U) {
     XChunk ch;
     if (first && base0 == b00)
       ch = *first;
     else
-      load_xchunk(a, k, base0, ch);
+      load_xchunk<U>(a, k, base0, ch);
 #pragma unroll
-    for (uint32_t u = 0; u < kFusedU; ++u) {
+    for (uint32_t u = 0; u < U; ++u) {
       const uint32_t base = base0 + u * kWave, t = base + lane();
       int32_t lab = ch.bv[u];
       bool lead = false;
@@ -822,27 +907,21 @@ __device__ void phase_x(const Args& a, uint32_t k, uint32_t C, const Part& p,
         atomicAdd(&a.ctl->fW[slot].v[0], (uint32_t)__popcll(hits));
         atomicAdd(&a.ctl->fW[slot].v[1], total);
       }
+      if (Agg && a.uniform) {
+        mark_rounds(a, cur, prv.sb, slot, k, incl, beg, deg, total, ht);
+        continue;
+      }
       for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
         const uint32_t e = e0 + lane();
         const bool valid = e < total;
-        const uint32_t ee = valid ? e : total - 1;
-        uint32_t j = 0;  // owner lane: the first with incl > ee
-#pragma unroll
-        for (uint32_t step = 32; step >= 1; step >>= 1) {
-          const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
-          if (probe <= ee) j += step;
-        }
-        const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
-        const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
-        const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
-        const uint32_t edge = jb + (ee - (ji - jd));
+        const uint32_t edge = edge_of(incl, beg, deg, valid ? e : total - 1);
         int32_t s = 0, o = 0;
         if (valid) {
           s = a.in_src[edge];
           o = a.in_ord[edge];
         }
         if (Agg) {
-          mark_lanes(a, cur, prv.sb, slot, k, s, o, valid, ht);
+          mark_lanes_wide(a, cur, prv.sb, slot, k, s, o, valid);
         } else if (valid) {
           mark_state(a, cur, prv.sb, slot, k, s,
                      a.uniform ? (uint64_t)s : (uint64_t)a.woff[s] + (uint32_t)(o >> 6),
