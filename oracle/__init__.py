@@ -20,6 +20,10 @@ Contents
   signature_rounds multi-way signature refinement from pi_pre (the
                    signature-based approach the paper compares against in
                    section 5), pure Python: rounds to the fixpoint.
+  hybrid_trace     signature rounds while each splits many blocks, then
+                   Algorithm 3 from the partition reached (the combination of
+                   multi-way splitting with the linear bound that section 6
+                   leaves as future work).
   mlp_*            fp64 reference of the splitter-scoring network (separate
                    module, oracle.mlp).
 """
@@ -287,15 +291,18 @@ def enumerate_coarsest(n, src, lab, dst, init=None):
     return canonical_from_classes(n, best[1])
 
 
-def signature_rounds(n, K, src, lab, dst, init=None, keep_blocks=False):
+def signature_rounds(n, K, src, lab, dst, init=None, keep_blocks=False, stall=0):
     """Multi-way signature refinement (the signature-based splitting of the
     comparison systems in section 5): starting from pi_pre (section 4.1),
     every round gives each state the signature {(a, block(t)) : s -a-> t},
     and states stay together iff they were together and their signatures are
     equal; every new block is named by its smallest state.  Stops after the
-    first round that changes nothing.  Returns dict: block (canonical),
-    rounds (including the final unchanged one), blocks (per-round partitions,
-    if keep_blocks).  Pure Python: meant for m up to about 10^5."""
+    first round that changes nothing, or, with stall > 0, after the second
+    of two consecutive rounds that each add fewer than `stall` blocks.
+    Returns dict: block (canonical), rounds (including that last
+    round), fixpoint (whether the last round changed nothing), blocks
+    (per-round partitions, if keep_blocks).  Pure Python: meant for m up to
+    about 10^5."""
     pre = preprocess(n, K, src, lab, dst, init)["pre_block"]
     part = [int(x) for x in pre]
     out = {(int(a), int(b), int(c)) for a, b, c in zip(src, lab, dst)}
@@ -305,6 +312,7 @@ def signature_rounds(n, K, src, lab, dst, init=None, keep_blocks=False):
     nblocks = len(set(part))
     rounds = 0
     hist = []
+    prev_few = False
     while True:
         rounds += 1
         leader = {}
@@ -317,9 +325,31 @@ def signature_rounds(n, K, src, lab, dst, init=None, keep_blocks=False):
             hist.append(np.array(part, np.int32))
         nb = len(leader)
         if nb == nblocks:
+            fixpoint = True
             break
+        few = nb - nblocks < stall
+        if stall and few and prev_few:
+            fixpoint = False
+            break
+        prev_few = few
         nblocks = nb
-    res = {"block": np.array(part, np.int32), "rounds": rounds}
+    res = {"block": np.array(part, np.int32), "rounds": rounds, "fixpoint": fixpoint}
     if keep_blocks:
         res["blocks"] = hist
     return res
+
+
+def hybrid_trace(n, K, src, lab, dst, init=None, stall=64):
+    """Multi-way signature rounds (signature_rounds with `stall`) followed,
+    unless they reached the fixpoint, by Algorithm 3 started from the
+    partition they reached with every block unstable.  That partition refines
+    pi_pre and is coarser than the coarsest stable one, so Algorithm 3 ends in
+    the same result; section 4.1's preprocessing leaves it unchanged.  Returns
+    dict: block, rounds, alg3_iters, iters (= rounds + alg3_iters)."""
+    r = signature_rounds(n, K, src, lab, dst, init, stall=stall)
+    if r["fixpoint"]:
+        return {"block": r["block"], "rounds": r["rounds"], "alg3_iters": 0,
+                "iters": r["rounds"]}
+    a = alg3_trace(n, K, src, lab, dst, r["block"])
+    return {"block": a["block"], "rounds": r["rounds"], "alg3_iters": a["iters"],
+            "iters": r["rounds"] + a["iters"]}

@@ -83,3 +83,39 @@ def test_chain_rounds(n):
     r = oracle.signature_rounds(L.n, L.K, L.src, L.lab, L.dst)
     assert r["rounds"] == max(n - 2, 1)
     assert (r["block"] == np.arange(n)).all()
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_hybrid_equals_kanellakis_smolka(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 400))
+    L = gen.random_lts(n, int(rng.integers(0, 4 * n)), int(rng.integers(1, 4)), seed,
+                       init_blocks=seed % 3)
+    for stall in (1, 2, 64):
+        h = oracle.hybrid_trace(L.n, L.K, L.src, L.lab, L.dst, L.init, stall=stall)
+        ks, _ = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        assert (h["block"] == ks).all(), (seed, stall)
+        assert h["iters"] == h["rounds"] + h["alg3_iters"]
+
+
+@pytest.mark.parametrize("n", [7, 8, 20, 300])
+def test_hybrid_fan_out(n):
+    # rounds 1 and 2 each peel one chain state (one new block each), so the
+    # switch comes after round 2, from {0,1}, {2..n-4}, {n-3}, {n-2}, {n-1}.
+    # Algorithm 3 from there: C = 0 (no split), n - 6 peels of the chain block,
+    # the chain block {2} once more, the n - 3 singletons 3..n-1 once each, and
+    # the final pass: 2n - 6 iterations; 2n - 4 in all, as for Algorithm 3 alone.
+    L = gen.fan_out(n)
+    h = oracle.hybrid_trace(L.n, L.K, L.src, L.lab, L.dst)
+    assert h["rounds"] == 2 and h["alg3_iters"] == 2 * n - 6 and h["iters"] == 2 * n - 4
+    exp = np.arange(n)
+    exp[1] = 0
+    assert (h["block"] == exp).all()
+
+
+def test_hybrid_stops_at_a_signature_fixpoint():
+    # a planted quotient refines in a few large multi-way rounds: no switch
+    L = gen.planted_quotient(q=2000, deg_mean=6.0, K=8, seed=7)
+    s = oracle.signature_rounds(L.n, L.K, L.src, L.lab, L.dst)
+    h = oracle.hybrid_trace(L.n, L.K, L.src, L.lab, L.dst)
+    assert s["fixpoint"] and h["alg3_iters"] == 0 and h["iters"] == s["rounds"]
