@@ -159,10 +159,21 @@ const char* bisim_last_error(void);
                                      actions per state) * n < 2^32 (else
                                      BISIM_E_UNSUPPORTED).  Device memory during a run:
                                      20 bytes per transition and 48 per state, plus the
-                                     radix sort's scratch. */
+                                     radix sort's scratch.
+                                     BISIM_ALGORITHM_HYBRID: signature rounds while they
+                                     split many blocks, then Algorithm 3 (multi-way
+                                     splitting combined with the linear bound, left as
+                                     future work in section 6): the rounds stop at the
+                                     fixpoint, or after two consecutive rounds that each
+                                     add fewer than 64 blocks, and Algorithm 3 (plain
+                                     policy) continues from the partition reached with
+                                     every block unstable.  iterations = rounds +
+                                     Algorithm 3 iterations; limits and errors as for
+                                     BISIM_ALGORITHM_SIGNATURE. */
 #define BISIM_ALGORITHM_RCPP 2
 #define BISIM_ALGORITHM_LABELLED 3
 #define BISIM_ALGORITHM_SIGNATURE 100
+#define BISIM_ALGORITHM_HYBRID 101
 bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
 
 /*

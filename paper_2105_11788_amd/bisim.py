@@ -37,7 +37,7 @@ OPT_ITER_LIMIT = 3
 OPT_GRID = 4
 OPT_PROFILE_EVERY = 5
 OPT_ALGORITHM = 6  # 3: labelled (Algorithm 3, default); 2: one-action RCPP (Algorithm 2)
-ALGORITHM_RCPP, ALGORITHM_LABELLED, ALGORITHM_SIGNATURE = 2, 3, 100  # values of OPT_ALGORITHM
+ALGORITHM_RCPP, ALGORITHM_LABELLED, ALGORITHM_SIGNATURE, ALGORITHM_HYBRID = 2, 3, 100, 101  # OPT_ALGORITHM values
 
 ENGINE_AUTO = 0
 ENGINE_PERSISTENT = 1

@@ -133,8 +133,10 @@ bisim_status coarsest_partition(bisim_lts* h, int32_t* block_id, bisim_stats* st
     set_error("coarsest_partition: NULL handle or output");
     return BISIM_E_INVALID;
   }
-  bisim_status rc = h->algorithm == BISIM_ALGORITHM_SIGNATURE ? signature_run(h, block_id)
-                                                               : refine_run(h, block_id);
+  bisim_status rc = (h->algorithm == BISIM_ALGORITHM_SIGNATURE ||
+                     h->algorithm == BISIM_ALGORITHM_HYBRID)
+                        ? signature_run(h, block_id, h->algorithm == BISIM_ALGORITHM_HYBRID)
+                        : refine_run(h, block_id);
   if (st) {
     st->iterations = h->last_iters;
     st->blocks = h->last_blocks;
@@ -176,7 +178,7 @@ bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value) {
       return BISIM_OK;
     case BISIM_OPT_ALGORITHM:
       if (value != BISIM_ALGORITHM_RCPP && value != BISIM_ALGORITHM_LABELLED &&
-          value != BISIM_ALGORITHM_SIGNATURE)
+          value != BISIM_ALGORITHM_SIGNATURE && value != BISIM_ALGORITHM_HYBRID)
         break;
       if (value == 2 && (h->K != 1 || (h->n > 0 && !h->init_block))) {
         set_error("bisim_set_option: Algorithm 2 needs a one-action LTS (num_actions = 1)");

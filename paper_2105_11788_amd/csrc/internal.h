@@ -166,6 +166,8 @@ struct bisim_lts {
   int engine = 0;
   int algorithm = 3;  // 3: labelled (Algorithm 3); 2: one-action RCPP (Algorithm 2)
   int64_t run_pre_blocks = 0;  // blocks the last run started from
+  const int32_t* start_override = nullptr;  // device: a partition refining pi_pre to start from
+  int64_t start_override_blocks = 0;
   int64_t first_splitter = -1;
   int64_t iter_limit = 0;
   int grid = 0;
@@ -213,8 +215,9 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
 // refine.hip
 bisim_status refine_run(bisim_lts* h, int32_t* block_id);
 bisim_status refine_alloc(bisim_lts* h);
-// signature.hip: multi-way signature refinement (baseline)
-bisim_status signature_run(bisim_lts* h, int32_t* block_id);
+// signature.hip: multi-way signature refinement (baseline), or signature
+// rounds followed by Algorithm 3 (hybrid)
+bisim_status signature_run(bisim_lts* h, int32_t* block_id, bool hybrid);
 }  // namespace bisim
 
 struct bisim_mlp;

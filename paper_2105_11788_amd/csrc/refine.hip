@@ -389,6 +389,10 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   const int32_t* start = rcpp ? h->init_block : h->pre_block;
   h->run_pre_blocks = h->pre_blocks;
   if (rcpp) BISIM_TRY(count_labels(h, start, &h->run_pre_blocks));
+  if (h->start_override && !rcpp && !learned) {  // a refinement of pi_pre (hybrid runs)
+    start = h->start_override;
+    h->run_pre_blocks = h->start_override_blocks;
+  }
   int64_t cap = 3 * (int64_t)n - h->run_pre_blocks + 1;
   if (cap < 1) cap = 1;
   if (h->iter_limit > 0 && h->iter_limit < cap) cap = h->iter_limit;

@@ -24,6 +24,13 @@
 // independent seed and compared with its block leader's (and the pi_pre block
 // with the leader's): if all agree the partition is stable and refines pi_0,
 // hence it is the coarsest one; if not, the run is repeated with new seeds.
+//
+// The hybrid run (the combination of multi-way splitting with the linear
+// bound that section 6 leaves open) stops the rounds after two consecutive
+// ones that each add fewer than kHybridStall blocks, and continues with
+// Algorithm 3 from the partition reached, every block unstable.  That
+// partition refines pi_pre (checked) and is at least as coarse as the
+// coarsest stable one, so Algorithm 3 ends in the same result.
 #include <hipcub/hipcub.hpp>
 
 #include "internal.h"
@@ -117,14 +124,16 @@ __global__ void k_assign(int32_t n, const int32_t* __restrict__ idxs,
   SSTRIDE(i, (int64_t)n) { nb[idxs[i]] = idxs[hp[i]]; }
 }
 
+// bad += states whose block leader is not its own leader, lies in another
+// block of pi_pre, or (stable) has another signature hash
 __global__ void __launch_bounds__(kT) k_check(int32_t n, const int32_t* __restrict__ blk,
                                               const int32_t* __restrict__ pre,
-                                              const uint64_t* __restrict__ sig2,
+                                              const uint64_t* __restrict__ sig2, int stable,
                                               unsigned long long* __restrict__ bad) {
   uint32_t c = 0;
   SSTRIDE(s, (int64_t)n) {
     const int32_t l = blk[s];
-    c += (sig2[s] != sig2[l]) || (pre[s] != pre[l]) || (blk[l] != l);
+    c += (stable && sig2[s] != sig2[l]) || (pre[s] != pre[l]) || (blk[l] != l);
   }
   if (c) atomicAdd(bad, (unsigned long long)c);
 }
@@ -163,19 +172,17 @@ struct Bufs {
 
 }  // namespace
 
-bisim_status signature_run(bisim_lts* h, int32_t* block_id) {
+constexpr int64_t kHybridStall = 64;
+
+// Signature rounds from pi_pre into out (device int32[n]): to the fixpoint
+// (stall = 0), or until two consecutive rounds each add fewer than stall
+// blocks.  Reports the rounds run, the blocks reached, whether the last round
+// changed nothing, and the time (ms).  Needs n > 0.
+bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* rounds_out,
+                            int64_t* blocks_out, bool* fixpoint_out, double* ms_out) {
   hipStream_t st = h->stream;
   const int32_t n = h->n;
   const int64_t m = h->m;
-  h->run_pre_blocks = h->pre_blocks;
-  h->last_iters = 0;
-  h->last_blocks = h->pre_blocks;
-  h->t_alg_ms = 0.0;
-  if ((h->policy == 1 && h->policy_w) || h->trace_cap > 0) {
-    set_error("signature refinement has no splitter: no splitter policy or trace");
-    return BISIM_E_UNSUPPORTED;
-  }
-  if (n == 0) return BISIM_OK;
   if (m >= (1ll << 31) || (uint64_t)h->max_ranks * (uint64_t)n > 0xFFFFFFFFull) {
     set_error("signature refinement: needs m < 2^31 and (actions per state) * n < 2^32");
     return BISIM_E_UNSUPPORTED;
@@ -215,11 +222,13 @@ bisim_status signature_run(bisim_lts* h, int32_t* block_id) {
   BISIM_TRY_HIP(hipEventRecord(h->ev0, st));
   int64_t rounds = 0;
   unsigned long long blocks = (unsigned long long)h->pre_blocks;
+  bool fixpoint = false;
   uint64_t seed = 0x2545F4914F6CDD1Dull;
   for (int attempt = 0;; ++attempt) {
     BISIM_TRY_HIP(hipMemcpyAsync(blk, h->pre_block, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     blocks = (unsigned long long)h->pre_blocks;
     rounds = 0;
+    bool prev_few = false;
     for (;;) {
       ++rounds;
       size_t tb1 = tb;
@@ -247,21 +256,31 @@ bisim_status signature_run(bisim_lts* h, int32_t* block_id) {
       int32_t* t = blk;
       blk = nb;
       nb = t;
-      if (c == blocks) break;  // new refines old: same count, same partition
+      if (c == blocks) {  // new refines old: same count, same partition
+        fixpoint = true;
+        break;
+      }
+      const bool few = (int64_t)(c - blocks) < stall;
       blocks = c;
+      if (stall > 0 && few && prev_few) {
+        fixpoint = false;
+        break;
+      }
+      prev_few = few;
       if (rounds > (int64_t)n + 1) {
         set_error("signature refinement: no fixpoint after %lld rounds", (long long)rounds);
         return BISIM_E_DEVICE;
       }
     }
-    // check with an independent hash: keys still hold the final partition's
+    // check with an independent hash (at the fixpoint the keys still hold the
+    // final partition's), or, after a stall, only that pi_pre is refined
     BISIM_TRY_HIP(hipMemsetAsync(sig, 0, sizeof(uint64_t) * n, st));
     BISIM_TRY_HIP(hipMemsetAsync(cnt + 1, 0, sizeof(unsigned long long), st));
-    if (m > 0)
+    if (m > 0 && fixpoint)
       hipLaunchKernelGGL(k_sig_sum, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, keys,
                          seed ^ 0xD1B54A32D192ED03ull, sig);
     hipLaunchKernelGGL(k_check, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, blk, h->pre_block, sig,
-                       cnt + 1);
+                       fixpoint ? 1 : 0, cnt + 1);
     BISIM_TRY_HIP(hipGetLastError());
     unsigned long long bad = 0;
     BISIM_TRY_HIP(hipMemcpyAsync(&bad, cnt + 1, sizeof(bad), hipMemcpyDeviceToHost, st));
@@ -274,13 +293,47 @@ bisim_status signature_run(bisim_lts* h, int32_t* block_id) {
     seed = seed * 6364136223846793005ull + 1442695040888963407ull;
   }
   BISIM_TRY_HIP(hipEventRecord(h->ev1, st));
-  BISIM_TRY_HIP(hipMemcpyAsync(block_id, blk, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  BISIM_TRY_HIP(hipMemcpyAsync(out, blk, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
   BISIM_TRY_HIP(hipStreamSynchronize(st));
   float ms = 0.f;
   BISIM_TRY_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  *ms_out = ms;
+  *rounds_out = rounds;
+  *blocks_out = (int64_t)blocks;
+  *fixpoint_out = fixpoint;
+  return BISIM_OK;
+}
+
+bisim_status signature_run(bisim_lts* h, int32_t* block_id, bool hybrid) {
+  h->run_pre_blocks = h->pre_blocks;
+  h->last_iters = 0;
+  h->last_blocks = h->pre_blocks;
+  h->t_alg_ms = 0.0;
+  if ((h->policy == 1 && h->policy_w) || h->trace_cap > 0) {
+    set_error("signature refinement has no splitter: no splitter policy or trace");
+    return BISIM_E_UNSUPPORTED;
+  }
+  if (h->n == 0) return BISIM_OK;
+  int64_t rounds = 0, blocks = 0;
+  bool fixpoint = false;
+  double ms = 0.0;
+  BISIM_TRY(signature_core(h, hybrid ? kHybridStall : 0, block_id, &rounds, &blocks, &fixpoint,
+                           &ms));
+  if (!fixpoint) {  // continue with Algorithm 3 from the partition in block_id
+    h->start_override = block_id;
+    h->start_override_blocks = blocks;
+    const bisim_status rc = refine_run(h, block_id);
+    h->start_override = nullptr;
+    h->start_override_blocks = 0;
+    h->run_pre_blocks = h->pre_blocks;
+    BISIM_TRY(rc);
+    h->last_iters += rounds;
+    h->t_alg_ms += ms;
+    return BISIM_OK;
+  }
   h->t_alg_ms = ms;
   h->last_iters = rounds;
-  h->last_blocks = (int64_t)blocks;
+  h->last_blocks = blocks;
   return BISIM_OK;
 }
 

@@ -1,6 +1,8 @@
 """GPU parity of the multi-way signature refinement baseline
-(BISIM_ALGORITHM_SIGNATURE) against the oracle: canonical block ids equal to
-Kanellakis-Smolka's, round counts equal to the oracle's signature_rounds."""
+(BISIM_ALGORITHM_SIGNATURE) and of the hybrid (BISIM_ALGORITHM_HYBRID:
+signature rounds, then Algorithm 3) against the oracle: canonical block ids
+equal to Kanellakis-Smolka's, round and iteration counts equal to the
+oracle's signature_rounds and hybrid_trace."""
 import numpy as np
 import pytest
 
@@ -18,12 +20,14 @@ def B():
     return bisim
 
 
-def run_sig(B, L, trace=0):
+def run_sig(B, L, trace=0, hybrid=False, engine=0):
     from paper_2105_11788_amd.bisim import DeviceArray
     t = lambda a: DeviceArray.from_numpy(a, np.int32)
     init = None if L.init is None else t(L.init)
     with B.LTS(t(L.src), t(L.lab), t(L.dst), L.n, L.K, init) as h:
-        h.set_option(B.OPT_ALGORITHM, B.ALGORITHM_SIGNATURE)
+        h.set_option(B.OPT_ALGORITHM, B.ALGORITHM_HYBRID if hybrid else B.ALGORITHM_SIGNATURE)
+        if engine:
+            h.set_option(B.OPT_ENGINE, engine)
         if trace:
             h.set_trace(trace)
         blk, st = h.run()
@@ -96,3 +100,49 @@ def test_empty_and_errors(B):
                   np.arange(n, dtype=np.int64), None, name="one state, 70000 actions")
     with pytest.raises(BisimError):
         run_sig(B, big)
+
+
+def assert_hybrid(B, L, engines=(1, 2)):
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    ref = oracle.hybrid_trace(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    for e in engines:
+        blk, st = run_sig(B, L, hybrid=True, engine=e)
+        assert (blk == ks).all(), (L.name, e)
+        assert st.blocks == nb
+        assert st.iterations == ref["iters"], (L.name, e, st.iterations, ref)
+    return ref
+
+
+@pytest.mark.parametrize("n", [7, 64, 300, 3000])
+def test_hybrid_fan_out(B, n):
+    ref = assert_hybrid(B, gen.fan_out(n))
+    assert ref["alg3_iters"] > 0  # switched to Algorithm 3
+
+
+def test_hybrid_chain_and_figures(B):
+    assert_hybrid(B, gen.chain_tail(1000))
+    assert_hybrid(B, gen.figure1())
+    assert_hybrid(B, gen.figure2())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hybrid_random(B, seed):
+    rng = np.random.default_rng(50 + seed)
+    n = int(rng.integers(50, 3000))
+    assert_hybrid(B, gen.random_lts(n, int(rng.integers(0, 4 * n)), int(rng.integers(1, 6)),
+                                    seed, init_blocks=seed % 4))
+
+
+def test_hybrid_no_switch_and_large(B):
+    ref = assert_hybrid(B, gen.planted_quotient(q=3000, deg_mean=6.0, K=8, seed=4))
+    assert ref["alg3_iters"] == 0
+    L = gen.planted_quotient()
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    blk, st = run_sig(B, L, hybrid=True)
+    assert (blk == ks).all() and st.blocks == nb
+
+
+def test_hybrid_errors(B):
+    from paper_2105_11788_amd.bisim import BisimError
+    with pytest.raises(BisimError):
+        run_sig(B, gen.fan_out(10), trace=8, hybrid=True)
