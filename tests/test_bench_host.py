@@ -1,0 +1,46 @@
+"""Host-side logic of bench.py: workload names, the byte models behind the
+roofline figures, the standard error and the stored-traffic lookup (no GPU)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def test_workload_names():
+    assert bench.workload("planted-quotient-1M")["make"]
+    L = bench.workload("fan-out-12")["make"](__import__("paper_2105_11788_amd.gen").gen)
+    assert L.n == 12 and L.m == 3 * 12 - 3  # section 5: n states, 3n - 3 transitions
+    with pytest.raises(KeyError):
+        bench.workload("no-such-workload")
+
+
+def test_sem():
+    assert bench.sem([1.0]) is None
+    xs = [1.0, 2.0, 3.0, 4.0]
+    assert bench.sem(xs) == pytest.approx(np.std(xs, ddof=1) / 2.0)
+
+
+def test_phase_bytes_model():
+    # two iterations and the final pass; work columns: members, in-transitions, touched
+    n = 1000
+    work = np.array([[10, 50, 30, 0], [5, 20, 12, 0], [0, 0, 0, 0]])
+    nsplit = np.array([4, 2, 0])
+    pb = bench.phase_bytes(n, work, nsplit)
+    assert pb.shape == (3, 2) and (pb[-1] == 0).all()
+    assert pb[0, 0] == 4 * n + n / 4 + 0 * 20 + 8 * 10 + 40 * 50
+    assert pb[1, 0] == 4 * n + n / 4 + 20 * 4 + 8 * 5 + 40 * 20
+    assert pb[1, 1] == 4 * n + n / 4 + n / 8 + 16 * 12 + 20 * 2 + 24 * 30
+
+
+def test_method_bytes_positive_and_final_pass_zero():
+    work = np.array([[10, 50, 30, 0], [0, 0, 0, 0]])
+    mb = bench.method_bytes(1000, 8000, 5000, work, np.array([3, 0]))
+    assert mb.shape == (2, 2) and (mb[0] > 0).all() and (mb[-1] == 0).all()
+
+
+def test_stored_traffic_unknown_kernel_is_null():
+    assert bench.stored_traffic("k_no_such_kernel", "planted-quotient-1M") is None
