@@ -178,6 +178,52 @@ def cpu_baseline(L, target_s: float = 12.0):
     }
 
 
+def _oracle_prefix(job):
+    """One instance's lock-step oracle run, capped at `cap` iterations:
+    (transition*iterations done, seconds)."""
+    import oracle
+    n, K, src, lab, dst, init, cap = job
+    t = time.perf_counter()
+    r = oracle.alg3_trace(n, K, src, lab, dst, init, max_iters=cap)
+    return len(src) * r["iters"], time.perf_counter() - t
+
+
+def cpu_baseline_batch(insts, target_s: float = 10.0, cap: int = 200, workers: int = 16):
+    """The lock-step oracle on a seeded sample of the batch's instances, each
+    run capped at `cap` iterations (a bounded prefix), one instance after
+    another on one core until about target_s seconds, then the same sample
+    over a process pool of up to `workers` host cores."""
+    import multiprocessing as mp
+    import oracle
+    oracle.lib()
+    rng = np.random.default_rng(7)
+    order = rng.permutation(len(insts))
+    jobs, done, el = [], 0.0, 0.0
+    for k in order:
+        L = insts[int(k)]
+        job = (L.n, L.K, L.src, L.lab, L.dst, L.init, cap)
+        w, t = _oracle_prefix(job)
+        jobs.append(job)
+        done += w
+        el += t
+        if el >= target_s:
+            break
+    cores = max(1, min(workers, os.cpu_count() or 1))
+    t = time.perf_counter()
+    # fresh interpreters: the workers import only numpy and the oracle and
+    # never touch the GPU this process has opened
+    with mp.get_context("spawn").Pool(cores) as pool:
+        done_all = sum(w for w, _ in pool.map(_oracle_prefix, jobs, chunksize=1))
+    el_all = time.perf_counter() - t
+    sample = (f"lock-step simulation of the labelled algorithm (CPU oracle) on {len(jobs)} "
+              f"randomly chosen instances of the batch, each capped at {cap} iterations")
+    return {"value": done / el, "unit": "transition*iterations/s", "cores": 1, "kind": "oracle",
+            "sample": sample + f"; {el:.1f} s on one thread", "host": host_cpu(),
+            "all_cores": {"value": done_all / el_all, "cores": cores,
+                          "sample": sample + f"; {el_all:.1f} s over {cores} processes, "
+                                             "their start included"}}
+
+
 def host_cpu():
     """CPU model and logical core count of the host that ran the baseline."""
     model = "unknown"
@@ -445,6 +491,9 @@ def form_batched(bisim, gen, args):
                 "speedup_vs_plain": plain_est_ms / ms,
                 "iteration_count": {"batched_critical_path": int(its.max()),
                                     "plain_sequential_total": int(its.sum())}})
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        res["cpu_baseline"] = cpu_baseline_batch(insts, args.cpu_seconds)
     return res
 
 

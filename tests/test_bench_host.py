@@ -44,3 +44,11 @@ def test_method_bytes_positive_and_final_pass_zero():
 
 def test_stored_traffic_unknown_kernel_is_null():
     assert bench.stored_traffic("k_no_such_kernel", "planted-quotient-1M") is None
+
+
+def test_cpu_baseline_batch_small():
+    from paper_2105_11788_amd import gen
+    insts = gen.batch(count=8, n_lo=50, n_hi=300, seed=3)
+    r = bench.cpu_baseline_batch(insts, target_s=0.2, cap=20, workers=2)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0
+    assert r["all_cores"]["cores"] == 2 and r["all_cores"]["value"] > 0
