@@ -146,3 +146,38 @@ def test_hybrid_errors(B):
     from paper_2105_11788_amd.bisim import BisimError
     with pytest.raises(BisimError):
         run_sig(B, gen.fan_out(10), trace=8, hybrid=True)
+
+
+def test_many_actions_per_state(B):
+    # states with more than 64 distinct actions (multi-word mark slots for
+    # Algorithm 3; ranks up to 90 in the signature keys) and every state of
+    # out-degree 90, so the hybrid's Algorithm 3 part marks with combining
+    rng = np.random.default_rng(3)
+    n, K = 300, 200
+    src = np.repeat(np.arange(n), 90)
+    L = gen.LTS(n, K, src, rng.integers(0, K, size=src.size), rng.integers(0, n, size=src.size),
+                None, name="300 states, 90 transitions each, 200 actions")
+    assert oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst)["nr_marks"].max() > 64
+    assert_parity(B, L)
+    assert_hybrid(B, L)
+    Q = gen.LTS(20, 150, np.repeat(np.arange(20), 100), rng.integers(0, 150, 2000),
+                rng.integers(0, 20, 2000), None, name="quotient with >64-action sets")
+    P, _ = gen.expand_quotient(Q, np.random.default_rng(1), 1, 6)
+    assert_parity(B, P)
+    assert_hybrid(B, P)
+    # a chain whose states also loop on 70 actions of their own: the signature
+    # rounds stall, and Algorithm 3 continues on multi-word mark slots
+    C = gen.chain_tail(400)
+    loops = np.repeat(np.arange(400), 70)
+    W = gen.LTS(400, 72, np.concatenate([C.src, loops]),
+                np.concatenate([C.lab, np.tile(np.arange(2, 72), 400)]),
+                np.concatenate([C.dst, loops]), None, name="chain with 70 self-loop actions")
+    ref = assert_hybrid(B, W)
+    assert ref["alg3_iters"] > 0
+    assert_parity(B, W)
+
+
+def test_kripke_with_propositions_hybrid(B):
+    # one action and a proposition partition: pi_pre is the leader-normalised pi_0
+    assert_hybrid(B, gen.kripke_uniform(2000, 9000, seed=5))
+    assert_parity(B, gen.kripke_uniform(2000, 9000, seed=5))
