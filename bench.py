@@ -8,22 +8,24 @@ second, m * #It / (seconds per step); for a batch, sum_k m_k * #It_k over
 the wall time of the batch.
 
 Forms (--form):
-  plain    (default) the plain method, smallest-label splitter, on the
-           planted-quotient LTS with ~1.03M states / ~8.2M transitions
-           (50,000 quotient nodes, Poisson(8) out-degree, Zipf(1.1) labels
-           over 16 actions, U{1..40} copies per node, seed 1);
-  batched  4096 independent LTSs in one launch (sizes log-uniform in
-           [100, n_hi], Poisson(6), K ~ U{1..32}, half planted), against
-           running each instance alone with the plain engine (timed on a
-           sample of instances and scaled);
+  batched  (default) 4096 independent LTSs in one launch, sizes log-uniform
+           in [100, n_hi] (n_hi = 200,000 by default: ~108M states and
+           ~648M transitions in all), Poisson(6) out-degree, K ~ U{1..32},
+           half with planted quotients; against running each instance alone
+           with the plain engine (timed on a sample of instances and scaled);
+  plain    the plain method, smallest-label splitter, on one LTS (default
+           the planted quotient with ~1.03M states / ~8.2M transitions;
+           --workload planted-quotient-10M is the ~10M-state one);
   learned  the learned splitter policy (network trained on the GPU first)
-           against the plain policy on the same LTS.
+           against the plain policy on the same LTS;
+  signature  the multi-way signature baseline (or --hybrid).
 
 Prints one JSON line.  Extra fields: `roofline` for the dominant kernel
-(algorithmic bytes per launch from the per-iteration work counters / its
-HIP-event-timed duration, against 8 TB/s, with the measured copy bandwidth
-beside it), and `cpu_baseline` (the CPU oracle timed on a bounded prefix of
-the same workload, single-threaded).
+(bytes it moves per launch, from a byte model of its loads and stores and
+per-iteration work counters, over its HIP-event-timed duration, against
+8 TB/s, with the measured copy bandwidth beside it), and `cpu_baseline` (the
+Kanellakis-Smolka CPU oracle built -O3 -march=native, timed to the fixpoint
+on one thread, and for the batch also over the host's cores).
 """
 from __future__ import annotations
 
@@ -39,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ENGINE_NAMES = {0: "automatic", 1: "persistent", 2: "per-phase kernels"}
 
 WORKLOADS = {
     "planted-quotient-1M": dict(
@@ -148,80 +151,101 @@ def stored_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(L, target_s: float = 12.0):
-    """The lock-step oracle (Algorithm 3 simulation) on a bounded prefix of
-    the same workload: time(1 + X iterations) - time(1 iteration)."""
+def cpu_baseline(L, iterations: int, gpu_block=None, target_s: float = 12.0):
+    """The Kanellakis-Smolka CPU oracle (compiled -O3 -march=native on this
+    host, one thread) solving the same LTS to its fixpoint, repeated until
+    about target_s seconds have passed (at least once).  Its time includes
+    building the reverse transition index (its preprocessing).  The value is
+    expressed in the benchmark's unit: m * #It (the GPU method's iteration
+    count on this LTS) over the oracle's seconds per solve, so that the ratio
+    of the two values is the ratio of the times to the fixpoint.  When the
+    GPU's partition is given it is compared with the oracle's, element by
+    element."""
     import oracle
-    oracle.lib()
-
-    def timed(k):
+    ks = oracle.native_ks()
+    times, blk = [], None
+    while not times or sum(times) < target_s:
         t = time.perf_counter()
-        r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init, max_iters=k)
-        return time.perf_counter() - t, r
-
-    t1, _ = timed(1)
-    t5, _ = timed(6)
-    per_it = max((t5 - t1) / 5, 1e-6)
-    X = int(max(5, min(100000, target_s / per_it)))
-    tX, rX = timed(1 + X)
-    X_done = X if rX["truncated"] else rX["iters"] - 1
-    el = max(tX - t1, 1e-9)
-    return {
-        "value": L.m * X_done / el,
+        blk, nb = ks(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        times.append(time.perf_counter() - t)
+    per = float(np.mean(times))
+    res = {
+        "value": L.m * iterations / per,
         "unit": "transition*iterations/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"lock-step simulation of the labelled algorithm (CPU oracle), iterations "
-                  f"2..{1 + X_done} of the same workload, {el:.1f} s after subtracting the "
-                  f"preprocessing + first iteration ({t1:.2f} s); single thread",
+        "sample": f"Kanellakis-Smolka refinement (the CPU oracle, gcc -O3 -march=native) on the "
+                  f"whole workload, {len(times)} solve(s) of {per:.2f} s each (reverse index "
+                  f"included), single thread; value = m x the GPU method's #It / seconds per "
+                  f"solve",
+        "seconds_to_fixpoint": per,
+        "seconds_sem": sem(times),
+        "blocks": nb,
         "host": host_cpu(),
+        "note": "a single LTS is one sequential fixpoint: no multi-core figure",
     }
+    if gpu_block is not None:
+        res["partition_equal_to_gpu"] = bool((np.asarray(gpu_block) == blk).all())
+    return res
 
 
-def _oracle_prefix(job):
-    """One instance's lock-step oracle run, capped at `cap` iterations:
-    (transition*iterations done, seconds)."""
+def _ks_job(job):
+    """One batch instance through the native Kanellakis-Smolka oracle:
+    (k, seconds)."""
     import oracle
-    n, K, src, lab, dst, init, cap = job
+    from paper_2105_11788_amd import gen
+    k, count, n_lo, n_hi, seed = job
+    L = gen.batch_instance(k, count=count, n_lo=n_lo, n_hi=n_hi, seed=seed)
+    ks = oracle.native_ks()
     t = time.perf_counter()
-    r = oracle.alg3_trace(n, K, src, lab, dst, init, max_iters=cap)
-    return len(src) * r["iters"], time.perf_counter() - t
+    ks(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    return k, time.perf_counter() - t
 
 
-def cpu_baseline_batch(insts, target_s: float = 10.0, cap: int = 200, workers: int = 16):
-    """The lock-step oracle on a seeded sample of the batch's instances, each
-    run capped at `cap` iterations (a bounded prefix), one instance after
-    another on one core until about target_s seconds, then the same sample
-    over a process pool of up to `workers` host cores."""
+def cpu_baseline_batch(insts, its, count, n_hi, target_s: float = 12.0, workers: int = 16):
+    """The Kanellakis-Smolka oracle (-O3 -march=native) on a seeded sample of
+    the batch's instances: one instance after another on one thread until
+    about target_s seconds, then the same sample over a pool of up to
+    `workers` host processes (each regenerates its instances from the batch
+    seed; the pool's wall time includes that and the process start).  Values
+    are sum over the sample of m_k * #It_k (the GPU method's counts) per
+    second, comparable with the GPU's whole-batch figure."""
     import multiprocessing as mp
     import oracle
-    oracle.lib()
+    ks = oracle.native_ks()
     rng = np.random.default_rng(7)
     order = rng.permutation(len(insts))
-    jobs, done, el = [], 0.0, 0.0
+    sample, done, el = [], 0.0, 0.0
     for k in order:
         L = insts[int(k)]
-        job = (L.n, L.K, L.src, L.lab, L.dst, L.init, cap)
-        w, t = _oracle_prefix(job)
-        jobs.append(job)
-        done += w
-        el += t
+        t = time.perf_counter()
+        ks(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        el += time.perf_counter() - t
+        done += L.m * float(its[int(k)])
+        sample.append(int(k))
         if el >= target_s:
             break
+    frac = sum(insts[k].m for k in sample) / max(1, sum(x.m for x in insts))
     cores = max(1, min(workers, os.cpu_count() or 1))
     t = time.perf_counter()
-    # fresh interpreters: the workers import only numpy and the oracle and
-    # never touch the GPU this process has opened
+    # fresh interpreters: the workers import only numpy, the generator and
+    # the oracle, and never touch the GPU this process has opened
     with mp.get_context("spawn").Pool(cores) as pool:
-        done_all = sum(w for w, _ in pool.map(_oracle_prefix, jobs, chunksize=1))
+        list(pool.imap_unordered(_ks_job, [(k, count, 100, n_hi, 1) for k in sample]))
     el_all = time.perf_counter() - t
-    sample = (f"lock-step simulation of the labelled algorithm (CPU oracle) on {len(jobs)} "
-              f"randomly chosen instances of the batch, each capped at {cap} iterations")
+    desc = (f"Kanellakis-Smolka refinement (the CPU oracle, gcc -O3 -march=native) to the "
+            f"fixpoint of {len(sample)} randomly chosen instances of the batch "
+            f"({100 * frac:.1f} % of its transitions)")
     return {"value": done / el, "unit": "transition*iterations/s", "cores": 1, "kind": "oracle",
-            "sample": sample + f"; {el:.1f} s on one thread", "host": host_cpu(),
-            "all_cores": {"value": done_all / el_all, "cores": cores,
-                          "sample": sample + f"; {el_all:.1f} s over {cores} processes, "
-                                             "their start included"}}
+            "sample": desc + f"; {el:.1f} s on one thread; value = sum m_k x #It_k (the GPU "
+                             f"method's counts) / seconds",
+            "seconds_whole_batch_estimate": el / frac if frac > 0 else None,
+            "host": host_cpu(),
+            "all_cores": {"value": done / el_all, "cores": cores,
+                          "sample": f"the same instances over {cores} processes, "
+                                    f"{el_all:.1f} s wall (process start and instance "
+                                    f"generation included)",
+                          "seconds_whole_batch_estimate": el_all / frac if frac > 0 else None}}
 
 
 def host_cpu():
@@ -347,16 +371,16 @@ def form_plain(bisim, gen, args):
                                 if ms[i] > 0 else None,
                                 "samples": int(r["phase_samples"][i])} for i in range(2)}
     # (a run of a few iterations may sample none)
-    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
-    touched_gbs = touched_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    achieved = touched_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    method_rate = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
     fmt = lambda v: "n/a" if v is None else f"{v:.1f}"
     log(f"{r['ms_per_step']:.2f} ms/step, #It={iters}, {kernel}: {kern_ms * 1e3:.2f} us/launch, "
-        f"method bytes {fmt(achieved)} GB/s, touched bytes {fmt(touched_gbs)} GB/s; "
+        f"bytes moved {fmt(achieved)} GB/s (method passes completed at {fmt(method_rate)} GB/s); "
         f"copy {copy_gbs:.0f} GB/s")
     cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
            "iterations": iters, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
            "mark_length": st.mark_length, "form": "plain", "algorithm": args.algorithm,
-           "engine": "persistent" if args.engine == 1 else "per-phase kernels"}
+           "engine": ENGINE_NAMES.get(args.engine, str(args.engine))}
     res = base_record(args, "transitions*iterations/sec (plain refinement to fixpoint)",
                       L.m * iters / (r["ms_per_step"] * 1e-3), r["ms_per_step"], cfg)
     res.update({
@@ -374,19 +398,28 @@ def form_plain(bisim, gen, args):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
             "traffic": stored_traffic(kernel.split(" ")[0], args.workload),
-            "bytes_per_launch": bytes_launch,
-            "bytes_definition": "method bytes: each pass of Algorithm 3 over all "
-                                "transitions/states with int32 ids and byte flags",
-            "touched_bytes_per_launch": touched_launch,
-            "touched_GBs": touched_gbs,
+            "bytes_per_launch": touched_launch,
+            "bytes_definition": "bytes the kernel moves per launch: the byte model of its "
+                                "loads and stores (int32 ids, 64-bit mark words and bids, "
+                                "1-bit flags) times the work counters of each iteration "
+                                "(members and in-transitions of the splitter, touched, split "
+                                "states), averaged over the iterations",
             "kernel_ms": kern_ms,
             "measured_copy_GBs": copy_gbs,
+            "method_bytes_per_launch": bytes_launch,
+            "method_pass_rate_GBs": method_rate,
+            "method_pass_rate_definition": "bytes of Algorithm 3's passes over all transitions "
+                                           "and states completed per second (these kernels "
+                                           "skip most of them, so this rate can exceed the "
+                                           "memory bandwidth; it is not a bandwidth)",
             "per_phase": per_phase,
         },
     })
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        res["cpu_baseline"] = cpu_baseline(L, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(L, iters, r["block"], args.cpu_seconds)
+        if not res["cpu_baseline"].get("partition_equal_to_gpu", True):
+            raise SystemExit("the GPU partition differs from the oracle's")
     return res
 
 
@@ -493,7 +526,8 @@ def form_batched(bisim, gen, args):
                                     "plain_sequential_total": int(its.sum())}})
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        res["cpu_baseline"] = cpu_baseline_batch(insts, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline_batch(insts, its, args.count, args.n_hi,
+                                                 args.cpu_seconds)
     return res
 
 
@@ -530,7 +564,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "signature"])
+    ap.add_argument("--form", default="batched",
+                    choices=["plain", "batched", "learned", "signature"])
     ap.add_argument("--workload", default="planted-quotient-1M",
                     help="one of " + ", ".join(sorted(WORKLOADS)) + ", or fan-out-<n>")
     ap.add_argument("--engine", type=int, default=0,
@@ -543,7 +578,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--count", type=int, default=4096)
-    ap.add_argument("--n-hi", type=int, default=10_000)
+    ap.add_argument("--n-hi", type=int, default=200_000,
+                    help="batched form: largest instance size (log-uniform from 100)")
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--batch-wg", type=int, default=0,
                     help="batched form: fixed workgroup size instead of the autotuner")

@@ -52,6 +52,36 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+_native = None
+
+
+def native_ks():
+    """ks_coarsest from the same source compiled with -O3 -march=native for
+    the host that runs it (the timed CPU baseline), built once per process in
+    a temporary directory.  Returns a callable with ks_coarsest's signature."""
+    global _native
+    if _native is None:
+        import tempfile
+        d = tempfile.mkdtemp(prefix="oracle_native_")
+        so = os.path.join(d, "liboracle_native.so")
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared",
+                               "-Wall", "-Wno-unused-result", _SRC, "-o", so])
+        L = ctypes.CDLL(so)
+        P = ctypes.c_void_p
+        L.orc_ks_coarsest.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]
+        L.orc_ks_coarsest.restype = ctypes.c_int64
+        _native = L
+
+    def run(n, K, src, lab, dst, init=None):
+        src, lab, dst, init = _i32(src), _i32(lab), _i32(dst), _i32(init)
+        out = np.empty(max(n, 0), dtype=np.int32)
+        r = _native.orc_ks_coarsest(n, src.size, K, _p(src), _p(lab), _p(dst), _p(init), _p(out))
+        if r < 0:
+            raise OracleError(f"orc_ks_coarsest: {r}")
+        return out, int(r)
+    return run
+
+
 def lib():
     global _lib
     if _lib is None:

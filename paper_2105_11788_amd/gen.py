@@ -288,27 +288,43 @@ def uniform_lts(n: int, deg_mean: float, K: int, seed: int) -> LTS:
 # ---------------------------------------------------------------------------
 # Batch of uneven instances
 # ---------------------------------------------------------------------------
+def _batch_plan(count: int, n_lo: int, n_hi: int, K_hi: int, seed: int):
+    """Sizes, action counts and per-instance seeds of a batch (the master
+    generator's first three draws)."""
+    rng = _rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=count))).astype(np.int64)
+    Ks = rng.integers(1, K_hi + 1, size=count)
+    seeds = rng.integers(0, 2**62, size=count)
+    return sizes, Ks, seeds
+
+
+def _batch_member(k: int, nk: int, Kk: int, sk: int, deg_mean: float) -> LTS:
+    sub = _rng(sk)
+    if k % 2 == 0:
+        q = max(1, int(np.ceil(nk / 20.5)))
+        Q = random_quotient(q, deg_mean, Kk, sub)
+        lts, s2q = expand_quotient(Q, sub)
+        lts.meta = {"Q": Q, "state_to_q": s2q}
+    else:
+        lts = uniform_lts(nk, deg_mean, Kk, sk ^ 0x5bd1e995)
+    lts.name = f"batch[{k}]"
+    return lts
+
+
 def batch(count: int = 4096, n_lo: int = 100, n_hi: int = 200_000,
           deg_mean: float = 6.0, K_hi: int = 32, seed: int = 1) -> List[LTS]:
     """`count` independent LTSs with log-uniform sizes in [n_lo, n_hi],
     Poisson(deg_mean) out-degree and K ~ U{1..K_hi}.  Even-indexed instances
     have planted quotients (ceil(n/20.5) quotient nodes, copies U{1..40},
     Zipf(1.1) labels); odd-indexed ones are uniform."""
-    rng = _rng(seed)
-    out = []
-    sizes = np.floor(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=count))).astype(np.int64)
-    Ks = rng.integers(1, K_hi + 1, size=count)
-    seeds = rng.integers(0, 2**62, size=count)
-    for k in range(count):
-        sub = _rng(int(seeds[k]))
-        nk, Kk = int(sizes[k]), int(Ks[k])
-        if k % 2 == 0:
-            q = max(1, int(np.ceil(nk / 20.5)))
-            Q = random_quotient(q, deg_mean, Kk, sub)
-            lts, s2q = expand_quotient(Q, sub)
-            lts.meta = {"Q": Q, "state_to_q": s2q}
-        else:
-            lts = uniform_lts(nk, deg_mean, Kk, int(seeds[k]) ^ 0x5bd1e995)
-        lts.name = f"batch[{k}]"
-        out.append(lts)
-    return out
+    sizes, Ks, seeds = _batch_plan(count, n_lo, n_hi, K_hi, seed)
+    return [_batch_member(k, int(sizes[k]), int(Ks[k]), int(seeds[k]), deg_mean)
+            for k in range(count)]
+
+
+def batch_instance(k: int, count: int = 4096, n_lo: int = 100, n_hi: int = 200_000,
+                   deg_mean: float = 6.0, K_hi: int = 32, seed: int = 1) -> LTS:
+    """Instance k of batch(count, n_lo, n_hi, deg_mean, K_hi, seed), drawn
+    alone (identical to the list's element k)."""
+    sizes, Ks, seeds = _batch_plan(count, n_lo, n_hi, K_hi, seed)
+    return _batch_member(k, int(sizes[k]), int(Ks[k]), int(seeds[k]), deg_mean)

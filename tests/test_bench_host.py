@@ -49,6 +49,20 @@ def test_stored_traffic_unknown_kernel_is_null():
 def test_cpu_baseline_batch_small():
     from paper_2105_11788_amd import gen
     insts = gen.batch(count=8, n_lo=50, n_hi=300, seed=3)
-    r = bench.cpu_baseline_batch(insts, target_s=0.2, cap=20, workers=2)
+    its = np.arange(8) + 10
+    r = bench.cpu_baseline_batch(insts, its, 8, 300, target_s=0.2, workers=2)
     assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0
     assert r["all_cores"]["cores"] == 2 and r["all_cores"]["value"] > 0
+
+
+def test_cpu_baseline_single_checks_partition():
+    import oracle
+    from paper_2105_11788_amd import gen
+    L = gen.kripke_uniform(300, 1500, seed=2)
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    r = bench.cpu_baseline(L, 500, ks, target_s=0.05)
+    assert r["partition_equal_to_gpu"] and r["blocks"] == nb and r["cores"] == 1
+    assert r["value"] == pytest.approx(L.m * 500 / r["seconds_to_fixpoint"])
+    wrong = ks.copy()
+    wrong[-1] = wrong[-1] + 1 if wrong[-1] + 1 < L.n else 0
+    assert not bench.cpu_baseline(L, 500, wrong, target_s=0.0)["partition_equal_to_gpu"]

@@ -114,34 +114,45 @@ def test_batch_errors(B):
     assert e.value.status == B.E_UNSUPPORTED
 
 
-def test_batch_4096_up_to_200k_sampled(B):
+def test_batch_4096_up_to_200k_full(B):
     """The full batch shape (4096 instances, log-uniform 100..200k states,
-    ~0.65G transitions) in the configuration the benchmark times: canonical
-    labels for every instance, the partition of a sample (always including the
-    largest instance) vs the oracle, #It vs the lock-step oracle on small ones."""
-    insts = gen.batch(count=4096, n_lo=100, n_hi=200_000, seed=1)
+    ~0.65G transitions): every instance's partition against the oracle
+    (computed over a pool of host processes), in two launch configurations
+    at the ends of the autotuner's range (the largest workgroups with the
+    whole LDS, so most instances are LDS-resident; the smallest workgroups
+    with a 16 KiB LDS budget, so most take the global-memory tier), with
+    identical per-instance iteration counts; #It vs the lock-step oracle on
+    a sample of small instances."""
+    import ks_workers
+    count, n_lo, n_hi = 4096, 100, 200_000
+    insts = gen.batch(count=count, n_lo=n_lo, n_hi=n_hi, seed=1)
     print(f"[batch-200k] generated {len(insts)} instances", flush=True)
+    runs = []
     with B.Batch(insts) as b:
-        b.set_option(B.BOPT_WG_SIZE, 1024)
-        out, its, st = b.run()
-        blocks = b.split(out.numpy())
-    print(f"[batch-200k] ran: max #It {its.max()}, global instances {st['global_instances']}",
-          flush=True)
-    assert st["global_instances"] > 0
-    for k, (L, blk) in enumerate(zip(insts, blocks)):
-        ids = np.arange(L.n)
-        assert (blk <= ids).all() and (blk[blk] == blk).all(), k  # smallest member labels
-        assert its[k] >= len(np.unique(blk)) + 1, k
+        for wg, lds in [(1024, 0), (256, 16384)]:
+            b.set_option(B.BOPT_WG_SIZE, wg)
+            b.set_option(B.BOPT_LDS_LIMIT, lds)
+            out, its, st = b.run()
+            runs.append((b.split(out.numpy()), its.copy(), dict(st)))
+            print(f"[batch-200k] wg {wg} lds {lds}: max #It {its.max()}, lds/global instances "
+                  f"{st['lds_instances']}/{st['global_instances']}, {st['t_alg_ms']:.0f} ms",
+                  flush=True)
+    assert runs[0][2]["global_instances"] > 0 and runs[1][2]["global_instances"] > \
+        runs[0][2]["global_instances"]
+    assert (runs[0][1] == runs[1][1]).all()
+    ref = ks_workers.ks_batch(range(count), count, n_lo, n_hi, seed=1)
+    print("[batch-200k] oracle done", flush=True)
+    for k in range(count):
+        ks, nb = ref[k]
+        for blocks, its, _ in runs:
+            assert (blocks[k] == ks).all(), (k, insts[k].n)
+        assert runs[0][1][k] >= nb + 1, k
     rng = np.random.default_rng(7)
-    sizes = np.array([x.n for x in insts])
-    sample = set(rng.choice(len(insts), 20, replace=False).tolist()) | {int(np.argmax(sizes))}
-    for k in sorted(sample):
-        L = insts[k]
-        ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
-        assert (blocks[k] == ks).all(), (k, L.n)
-        if L.n <= 3000:
-            r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init)
-            assert its[k] == r["iters"], (k, its[k], r["iters"])
+    small = [k for k in range(count) if insts[k].n <= 3000]
+    for k in rng.choice(small, 24, replace=False):
+        L = insts[int(k)]
+        r = oracle.alg3_trace(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        assert runs[0][1][int(k)] == r["iters"], (int(k), r["iters"])
 
 
 def test_batch_4096_up_to_10k_full(B):

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from ks_workers import lifted_quotient
 from paper_2105_11788_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -262,38 +263,82 @@ def test_repeat_runs_and_grids_deterministic(B):
 
 
 # --------------------------------------------------------------------------
-# full-size workloads
+# full-size workloads (both engines; the per-phase engine is the one the
+# benchmark times).  The coarsest partition is unique (Theorem 1 with the
+# uniqueness argument of section 4.2), so element-wise equality with the
+# Kanellakis-Smolka oracle is the complete check.
 # --------------------------------------------------------------------------
-def test_planted_quotient_1m_full(B):
-    """~1M states, ~8.2M transitions, 16 actions (Zipf 1.1), copies U{1..40}:
-    whole partition vs the Kanellakis-Smolka oracle and the lifted quotient;
-    the first 64 iterations' trace vs the lock-step oracle; Theorem 3 bounds."""
+@pytest.fixture(scope="module")
+def pq1m():
     P = gen.planted_quotient(q=50_000, deg_mean=8.0, K=16, seed=1)
     ks, nb = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
     Q = P.meta["Q"]
     qb, qn = oracle.ks_coarsest(Q.n, Q.K, Q.src, Q.lab, Q.dst)
-    assert nb == qn
-    r = run_gpu(B, P, engine=1, trace=64)
+    assert nb == qn and (ks == lifted_quotient(P, qb)).all()
+    return P, ks, nb
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_planted_quotient_1m_full(B, pq1m, engine):
+    """~1M states, ~8.2M transitions, 16 actions (Zipf 1.1), copies U{1..40}:
+    whole partition vs the Kanellakis-Smolka oracle and the lifted quotient;
+    the first 64 iterations' trace vs the lock-step oracle; Theorem 3 bounds."""
+    P, ks, nb = pq1m
+    r = run_gpu(B, P, engine=engine, trace=64)
     assert (r["block"] == ks).all()
     st = r["stats"]
+    assert st.blocks == nb
     assert nb + 1 <= st.iterations <= 3 * P.n - st.pre_blocks + 1
     ref = oracle.alg3_trace(P.n, P.K, P.src, P.lab, P.dst, trace_cap=64, max_iters=64)
     assert (r["C"] == ref["C"]).all() and (r["nsplit"] == ref["nsplit"]).all()
 
 
-def test_chain_100k_full(B):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_chain_100k_full(B, engine):
     L = gen.chain_tail(100_000)
-    r = run_gpu(B, L, engine=1)
+    r = run_gpu(B, L, engine=engine)
     assert r["stats"].iterations == 199_998
     assert (r["block"] == np.arange(100_000)).all()
 
 
-def test_sync_product_full(B):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_sync_product_full(B, engine):
     P = gen.sync_product(seed=1)
     ks, nb = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
-    r = run_gpu(B, P, engine=1)
+    r = run_gpu(B, P, engine=engine, trace=64)
+    assert (r["block"] == ks).all() and r["stats"].blocks == nb
+    assert nb + 1 <= r["stats"].iterations <= 3 * P.n - r["stats"].pre_blocks + 1
+    ref = oracle.alg3_trace(P.n, P.K, P.src, P.lab, P.dst, trace_cap=64, max_iters=64)
+    assert (r["C"] == ref["C"]).all() and (r["nsplit"] == ref["nsplit"]).all()
+
+
+@pytest.fixture(scope="module")
+def pq10m():
+    """The 10M-state workload: 487,805 quotient nodes, Poisson(10), Zipf(1.1)
+    over 64 actions, copies U{1..40} (~10M states, ~100M transitions)."""
+    P = gen.planted_quotient(q=487_805, deg_mean=10.0, K=64, seed=1)
+    print(f"[pq10m] n={P.n} m={P.m}", flush=True)
+    ks, nb = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
+    Q = P.meta["Q"]
+    qb, qn = oracle.ks_coarsest(Q.n, Q.K, Q.src, Q.lab, Q.dst)
+    assert nb == qn and (ks == lifted_quotient(P, qb)).all()
+    print(f"[pq10m] oracle: {nb} blocks", flush=True)
+    return P, ks, nb
+
+
+def test_planted_quotient_10m_full(B, pq10m):
+    """The 10M-state workload on the per-phase engine: partition bit-exact
+    against the oracle, block count, Theorem 3 bounds, and the first 64
+    iterations' splitters against the lock-step oracle."""
+    P, ks, nb = pq10m
+    r = run_gpu(B, P, engine=2, trace=64)
+    st = r["stats"]
+    print(f"[pq10m] GPU: #It={st.iterations} in {st.t_alg_ms:.0f} ms", flush=True)
     assert (r["block"] == ks).all()
-    assert r["stats"].iterations <= 3 * P.n - r["stats"].pre_blocks + 1
+    assert st.blocks == nb
+    assert nb + 1 <= st.iterations <= 3 * P.n - st.pre_blocks + 1
+    ref = oracle.alg3_trace(P.n, P.K, P.src, P.lab, P.dst, trace_cap=64, max_iters=64)
+    assert (r["C"] == ref["C"]).all() and (r["nsplit"] == ref["nsplit"]).all()
 
 
 # --------------------------------------------------------------------------
