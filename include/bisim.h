@@ -108,6 +108,36 @@ bisim_status coarsest_partition(bisim_lts* h, int32_t* block_id, bisim_stats* st
 /* lts_free — release a handle and its device memory (NULL is a no-op). */
 void lts_free(bisim_lts* h);
 
+/*
+ * coarsest_partition_noalloc — lts_load + coarsest_partition + lts_free in
+ * one call that allocates no device or pinned host memory, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Loading and refinement run the same
+ * kernels as the handle-based calls (plain splitter policy, Algorithm 3,
+ * default engine), with all their working memory taken from one static
+ * device region of BISIM_NOALLOC_SCRATCH_BYTES per GPU, held from the first
+ * call on that GPU until the process ends.
+ *   src, label, dst, n, m, num_actions, init_partition, hip_stream
+ *                 as for lts_load (device pointers; inputs are only read).
+ *   block_id      device, n entries: the result, as for coarsest_partition.
+ *   st            host, nullable: statistics (t_pre_ms = loading time).
+ * Size limit: the call needs at most about 16m + 100n + 8K bytes plus a few
+ * KiB (an exact upper bound is computed from n, m and K before any work);
+ * inputs beyond BISIM_NOALLOC_SCRATCH_BYTES are rejected with
+ * BISIM_E_UNSUPPORTED before anything is enqueued.
+ * The region keeps the last call's contents; every buffer is initialised by
+ * the call that uses it.  All calls on one GPU share the region: calls that
+ * overlap on one GPU (other host threads, other streams) race and must not
+ * be made.  Returns after synchronising hip_stream.
+ * Errors: BISIM_E_INVALID, BISIM_E_RANGE, BISIM_E_UNSUPPORTED, BISIM_E_DEVICE,
+ * BISIM_E_ITERCAP.
+ */
+#define BISIM_NOALLOC_SCRATCH_BYTES (64ll << 20)
+bisim_status coarsest_partition_noalloc(const int32_t* src, const int32_t* label,
+                                        const int32_t* dst, int32_t n, int64_t m,
+                                        int32_t num_actions, const int32_t* init_partition,
+                                        int32_t* block_id, bisim_stats* st, void* hip_stream);
+
 /* bisim_last_error — text for the last failure on the calling thread; valid
    until the next library call on that thread.  Never NULL. */
 const char* bisim_last_error(void);

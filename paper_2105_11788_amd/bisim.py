@@ -48,7 +48,11 @@ EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
            "lts_batch_load", "coarsest_partition_batch", "lts_batch_free",
            "bisim_batch_set_option", "mlp_num_params", "mlp_create", "mlp_free",
            "mlp_get_params", "mlp_forward", "mlp_train_step", "bisim_set_splitter_policy",
-           "bisim_collect_training", "bisim_get_phase_times", "bisim_device_copy"]
+           "bisim_collect_training", "bisim_get_phase_times", "bisim_device_copy",
+           "coarsest_partition_noalloc"]
+
+# size of the static device region of coarsest_partition_noalloc (bisim.h)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class BisimError(RuntimeError):
@@ -91,6 +95,9 @@ def load_library(path: str = LIB_PATH):
     L.bisim_set_trace.restype = i32
     L.bisim_get_preprocessed.argtypes = [P, P, P]
     L.bisim_get_preprocessed.restype = i32
+    L.coarsest_partition_noalloc.argtypes = [P, P, P, i32, i64, i32, P, P,
+                                             ctypes.POINTER(bisim_stats), P]
+    L.coarsest_partition_noalloc.restype = i32
     _lib = L
     return L
 
@@ -553,3 +560,24 @@ def coarsest_partition(src, lab, dst, n: int, num_actions: int, init=None,
             h.set_option(OPT_ENGINE, engine)
         out, st = h.run()
         return out.numpy(), st
+
+
+def coarsest_partition_noalloc(src, lab, dst, n: int, num_actions: int, init=None, out=None,
+                               stream: Optional[int] = None):
+    """coarsest_partition_noalloc: load + refine in the library's static
+    device region, allocating nothing.  src/lab/dst/init/out are device
+    buffers (DeviceArray or anything with an integer `ptr`), allocated by the
+    caller; `out` (n int32 entries) receives the result.  Returns Stats."""
+    L = load_library()
+    m = int(getattr(src, "count"))
+    n = int(n)
+    ps, pl, pd = (_dptr(x, nm, m) if m else None
+                  for x, nm in ((src, "src"), (lab, "label"), (dst, "dst")))
+    pi = _dptr(init, "init_partition", n) if (init is not None and n) else None
+    po = _dptr(out, "block_id", n) if n else None
+    st = bisim_stats()
+    _check(L.coarsest_partition_noalloc(ps, pl, pd, n, m, int(num_actions), pi, po,
+                                        ctypes.byref(st),
+                                        ctypes.c_void_p(stream) if stream else None))
+    return Stats(st.iterations, st.blocks, st.pre_blocks, st.mark_length, st.t_pre_ms,
+                 st.t_alg_ms)

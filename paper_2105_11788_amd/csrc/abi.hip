@@ -8,6 +8,7 @@
 
 namespace bisim {
 static thread_local char g_err[512] = "";
+void clear_error() { g_err[0] = 0; }
 
 void set_error(const char* fmt, ...) {
   va_list ap;
@@ -34,6 +35,52 @@ static void free_handle(bisim_lts* h) {
   delete[] h->pev;
   delete h;
 }
+// argument checks of lts_load (and of the allocation-free entry point)
+bisim_status check_load_args(const int32_t* src, const int32_t* label, const int32_t* dst,
+                                    int32_t n, int64_t m, int32_t num_actions, const char* who) {
+  if (n < 0 || m < 0 || num_actions < 1) {
+    set_error("%s: need n >= 0, m >= 0, num_actions >= 1 (got %d, %lld, %d)", who, n,
+              (long long)m, num_actions);
+    return BISIM_E_INVALID;
+  }
+  if (m > 0 && (!src || !label || !dst)) {
+    set_error("%s: NULL transition array", who);
+    return BISIM_E_INVALID;
+  }
+  if (m >= 0xFFFFFFFFll || n >= 0x7FFFFFFF) {
+    set_error("%s: sizes beyond n < 2^31-1, m < 2^32-1", who);
+    return BISIM_E_UNSUPPORTED;
+  }
+  return BISIM_OK;
+}
+
+// Fill a handle whose sizes and stream are set: device and CU count, timing
+// events (unless given), preprocessing, and the run state.  Records T_pre.
+bisim_status load_into(bisim_lts* h, const int32_t* src, const int32_t* label,
+                       const int32_t* dst, const int32_t* init_partition, bool with_run_state) {
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+  if (e == hipSuccess && !h->ev0) e = hipEventCreate(&h->ev0);
+  if (e == hipSuccess && !h->ev1) e = hipEventCreate(&h->ev1);
+  if (e != hipSuccess) {
+    set_error("lts_load: no usable HIP device (%s)", hipGetErrorString(e));
+    return BISIM_E_DEVICE;
+  }
+  BISIM_TRY_HIP(hipEventRecord(h->ev0, h->stream));
+  BISIM_TRY(setup_load(h, src, label, dst, init_partition));
+  if (with_run_state) BISIM_TRY(refine_alloc(h));
+  float ms = 0.f;
+  if (hipEventRecord(h->ev1, h->stream) != hipSuccess ||
+      hipEventSynchronize(h->ev1) != hipSuccess ||
+      hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) {
+    set_error("lts_load: %s", hipGetErrorString(hipGetLastError()));
+    return BISIM_E_DEVICE;
+  }
+  h->t_pre_ms = ms;
+  return BISIM_OK;
+}
+
 static bisim_status load_impl(const int32_t* src, const int32_t* label, const int32_t* dst,
                               int32_t n, int64_t m, int32_t num_actions,
                               const int32_t* init_partition, void* hip_stream, bisim_lts** out,
@@ -44,19 +91,7 @@ static bisim_status load_impl(const int32_t* src, const int32_t* label, const in
     return BISIM_E_INVALID;
   }
   *out = nullptr;
-  if (n < 0 || m < 0 || num_actions < 1) {
-    set_error("lts_load: need n >= 0, m >= 0, num_actions >= 1 (got %d, %lld, %d)", n,
-              (long long)m, num_actions);
-    return BISIM_E_INVALID;
-  }
-  if (m > 0 && (!src || !label || !dst)) {
-    set_error("lts_load: NULL transition array");
-    return BISIM_E_INVALID;
-  }
-  if (m >= 0xFFFFFFFFll || n >= 0x7FFFFFFF) {
-    set_error("lts_load: sizes beyond n < 2^31-1, m < 2^32-1");
-    return BISIM_E_UNSUPPORTED;
-  }
+  BISIM_TRY(check_load_args(src, label, dst, n, m, num_actions, "lts_load"));
   bisim_lts* h = new (std::nothrow) bisim_lts;
   if (!h) {
     set_error("lts_load: host allocation failed");
@@ -66,38 +101,7 @@ static bisim_status load_impl(const int32_t* src, const int32_t* label, const in
   h->m = m;
   h->K = num_actions;
   h->stream = (hipStream_t)hip_stream;
-  bisim_status st = BISIM_OK;
-  do {
-    hipError_t e = hipGetDevice(&h->device);
-    if (e == hipSuccess)
-      e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device);
-    if (e == hipSuccess) e = hipEventCreate(&h->ev0);
-    if (e == hipSuccess) e = hipEventCreate(&h->ev1);
-    if (e != hipSuccess) {
-      set_error("lts_load: no usable HIP device (%s)", hipGetErrorString(e));
-      st = BISIM_E_DEVICE;
-      break;
-    }
-    if (hipEventRecord(h->ev0, h->stream) != hipSuccess) {
-      st = BISIM_E_DEVICE;
-      break;
-    }
-    st = setup_load(h, src, label, dst, init_partition);
-    if (st != BISIM_OK) break;
-    if (with_run_state) {
-      st = refine_alloc(h);
-      if (st != BISIM_OK) break;
-    }
-    float ms = 0.f;
-    if (hipEventRecord(h->ev1, h->stream) != hipSuccess ||
-        hipEventSynchronize(h->ev1) != hipSuccess ||
-        hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) {
-      set_error("lts_load: %s", hipGetErrorString(hipGetLastError()));
-      st = BISIM_E_DEVICE;
-      break;
-    }
-    h->t_pre_ms = ms;
-  } while (0);
+  const bisim_status st = load_into(h, src, label, dst, init_partition, with_run_state);
   if (st != BISIM_OK) {
     free_handle(h);
     return st;

@@ -34,6 +34,33 @@ void set_error(const char* fmt, ...);
   } while (0)
 
 // ---------------------------------------------------------------------------
+// device memory of the library's buffers.  dev_alloc takes stream-ordered
+// memory (hipMallocAsync), or, while an ArenaScope is open on the calling
+// thread, a 256-byte aligned piece of the scope's region (bump allocation,
+// nothing is returned before the scope closes); dev_free releases the former
+// and ignores the latter.
+// ---------------------------------------------------------------------------
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s);
+hipError_t dev_free(void* p, hipStream_t s);
+class ArenaScope {
+ public:
+  ArenaScope(char* base, size_t capacity);
+  ~ArenaScope();
+  size_t used() const { return used_; }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+
+ private:
+  friend hipError_t dev_alloc(void**, size_t, hipStream_t);
+  friend hipError_t dev_free(void*, hipStream_t);
+  char* base_;
+  size_t cap_, used_ = 0;
+  ArenaScope* outer_;
+};
+// true while an ArenaScope is open on this thread (allocation-free calls)
+bool arena_active();
+
+// ---------------------------------------------------------------------------
 // device control block of one refinement run.  Fields written by atomics from
 // many workgroups sit on their own 128-byte lines.
 // ---------------------------------------------------------------------------
@@ -206,9 +233,18 @@ struct bisim_lts {
 };
 
 namespace bisim {
+// abi.hip
+void clear_error();
+bisim_status check_load_args(const int32_t* src, const int32_t* label, const int32_t* dst,
+                             int32_t n, int64_t m, int32_t num_actions, const char* who);
+bisim_status load_into(bisim_lts* h, const int32_t* src, const int32_t* label,
+                       const int32_t* dst, const int32_t* init_partition, bool with_run_state);
 // scan.hip: out[0..count] = exclusive prefix sums of in[0..count), out[count] = total
 bisim_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count,
                                 hipStream_t stream);
+// upper bound of the device memory exclusive_scan_u32 takes for `count`
+// values (as dev_alloc counts it: each piece rounded up to 256 bytes)
+size_t exclusive_scan_scratch_bytes(int64_t count);
 // setup.hip
 bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
                         const int32_t* dst, const int32_t* init);

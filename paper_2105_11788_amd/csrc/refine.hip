@@ -233,9 +233,8 @@ __global__ void __launch_bounds__(kPT) k_persistent(Args a) {
 
 template <class T>
 bisim_status dalloc(T** p, size_t count, hipStream_t s) {
-  *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMallocAsync((void**)p, sizeof(T) * count, s);
+  hipError_t e = dev_alloc((void**)p, sizeof(T) * count, s);
   if (e != hipSuccess) {
     set_error("device allocation of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
     return BISIM_E_NOMEM;
@@ -262,7 +261,8 @@ bisim_status refine_alloc(bisim_lts* h) {
   BISIM_TRY(dalloc(&h->tlist, n, s));
   BISIM_TRY(dalloc(&h->slist, n, s));
   BISIM_TRY(dalloc(&h->ctl, 1, s));
-  BISIM_TRY_HIP(hipHostMalloc((void**)&h->ctl_host, sizeof(Ctl), hipHostMallocDefault));
+  if (!h->ctl_host)  // the allocation-free entry point brings its own host mirror
+    BISIM_TRY_HIP(hipHostMalloc((void**)&h->ctl_host, sizeof(Ctl), hipHostMallocDefault));
   return BISIM_OK;
 }
 
@@ -370,7 +370,7 @@ bisim_status count_labels(bisim_lts* h, const int32_t* block, int64_t* out) {
     hipLaunchKernelGGL(k_count_leaders, dim3((unsigned)g), dim3(kT), 0, st, block, h->n, cnt);
   unsigned long long nb = 0;
   BISIM_TRY_HIP(hipMemcpyAsync(&nb, cnt, sizeof(nb), hipMemcpyDeviceToHost, st));
-  BISIM_TRY_HIP(hipFreeAsync(cnt, st));
+  BISIM_TRY_HIP(dev_free(cnt, st));
   BISIM_TRY_HIP(hipStreamSynchronize(st));
   *out = (int64_t)nb;
   return BISIM_OK;

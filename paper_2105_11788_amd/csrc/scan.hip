@@ -57,6 +57,17 @@ __global__ void __launch_bounds__(kThreads) k_scan_add(uint32_t* __restrict__ ou
 }
 }  // namespace
 
+size_t exclusive_scan_scratch_bytes(int64_t count) {
+  size_t total = 0;
+  for (int64_t c = count; c > kTile;) {  // c needs two tiles or more
+    const int64_t tiles = (c + kTile - 1) / kTile;
+    total += (sizeof(uint32_t) * (size_t)tiles + 255) / 256 * 256;
+    total += (sizeof(uint32_t) * (size_t)(tiles + 1) + 255) / 256 * 256;
+    c = tiles;
+  }
+  return total;
+}
+
 bisim_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count,
                                 hipStream_t stream) {
   if (count <= 0) {
@@ -74,8 +85,8 @@ bisim_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count
   // tiles >= 2: the recursion below runs on ceil(count / kTile) < count values
   uint32_t* sums = nullptr;
   uint32_t* offs = nullptr;
-  BISIM_TRY_HIP(hipMallocAsync((void**)&sums, sizeof(uint32_t) * tiles, stream));
-  BISIM_TRY_HIP(hipMallocAsync((void**)&offs, sizeof(uint32_t) * (tiles + 1), stream));
+  BISIM_TRY_HIP(dev_alloc((void**)&sums, sizeof(uint32_t) * tiles, stream));
+  BISIM_TRY_HIP(dev_alloc((void**)&offs, sizeof(uint32_t) * (tiles + 1), stream));
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kThreads), 0, stream, in, out, sums,
                      count);
   BISIM_TRY_HIP(hipGetLastError());
@@ -86,8 +97,8 @@ bisim_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count
   BISIM_TRY_HIP(hipGetLastError());
   BISIM_TRY_HIP(hipMemcpyAsync(out + count, offs + tiles, sizeof(uint32_t),
                                hipMemcpyDeviceToDevice, stream));
-  BISIM_TRY_HIP(hipFreeAsync(sums, stream));
-  BISIM_TRY_HIP(hipFreeAsync(offs, stream));
+  BISIM_TRY_HIP(dev_free(sums, stream));
+  BISIM_TRY_HIP(dev_free(offs, stream));
   return BISIM_OK;
 }
 

@@ -217,9 +217,8 @@ __global__ void k_static_features(const int32_t* __restrict__ src, const int32_t
 
 template <class T>
 bisim_status dalloc(T** p, size_t count, hipStream_t s) {
-  *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMallocAsync((void**)p, sizeof(T) * count, s);
+  hipError_t e = dev_alloc((void**)p, sizeof(T) * count, s);
   if (e != hipSuccess) {
     set_error("device allocation of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
     return BISIM_E_NOMEM;
@@ -233,11 +232,11 @@ struct Temps {
   template <class T>
   bisim_status get(T** p, size_t count) {
     BISIM_TRY(dalloc(p, count, s));
-    ptrs.push_back((void*)*p);
+    if (!arena_active()) ptrs.push_back((void*)*p);  // arena memory is never freed singly
     return BISIM_OK;
   }
   ~Temps() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    for (void* p : ptrs) (void)dev_free(p, s);
   }
 };
 }  // namespace
@@ -305,9 +304,6 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
     hipLaunchKernelGGL(k_lab_scatter, dim3(chunks), dim3(kT), 0, st, lab, m, K, cursor, idx);
     BISIM_TRY_HIP(hipGetLastError());
   }
-  std::vector<uint32_t> lp((size_t)K + 1);
-  BISIM_TRY_HIP(hipMemcpyAsync(lp.data(), lab_ptr, sizeof(uint32_t) * (K + 1),
-                               hipMemcpyDeviceToHost, st));
 
   // 3. leaders of pi_0
   const unsigned gn = grid_for(n, cu);
@@ -328,19 +324,27 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
   BISIM_TRY_HIP(hipMemsetAsync(flag, 0, (size_t)n, st));
   BISIM_TRY_HIP(hipMemsetAsync(h->nr_marks, 0, sizeof(int32_t) * (size_t)n, st));
   BISIM_TRY_HIP(hipMemsetAsync(nlw, 0, sizeof(uint64_t) * (size_t)n, st));
-  BISIM_TRY_HIP(hipStreamSynchronize(st));  // lp is ready
+  // the host reads the action buckets' bounds a piece at a time
+  constexpr int32_t kLp = 2048;
+  uint32_t lp[kLp + 1];
   uint64_t epoch = 0;
-  for (int32_t a = 0; a < K; ++a) {
-    const uint32_t b0 = lp[a], b1 = lp[a + 1];
-    if (b1 == b0) continue;
-    ++epoch;
-    hipLaunchKernelGGL(k_round_mark, dim3(grid_for(b1 - b0, cu)), dim3(kT), 0, st, idx, b0, b1,
-                       src, h->nr_marks, ord, has);
-    hipLaunchKernelGGL(k_round_split, dim3(gn), dim3(kT), 0, st, n, h->pre_block, has, nlw, flag,
-                       epoch << 32);
-    hipLaunchKernelGGL(k_round_relabel, dim3(gn), dim3(kT), 0, st, n, h->pre_block, nlw, flag, has,
-                       h->nr_marks);
-    BISIM_TRY_HIP(hipGetLastError());
+  for (int32_t a0 = 0; a0 < K; a0 += kLp) {
+    const int32_t cnt = K - a0 < kLp ? K - a0 : kLp;
+    BISIM_TRY_HIP(hipMemcpyAsync(lp, lab_ptr + a0, sizeof(uint32_t) * (size_t)(cnt + 1),
+                                 hipMemcpyDeviceToHost, st));
+    BISIM_TRY_HIP(hipStreamSynchronize(st));
+    for (int32_t j = 0; j < cnt; ++j) {
+      const uint32_t b0 = lp[j], b1 = lp[j + 1];
+      if (b1 == b0) continue;
+      ++epoch;
+      hipLaunchKernelGGL(k_round_mark, dim3(grid_for(b1 - b0, cu)), dim3(kT), 0, st, idx, b0, b1,
+                         src, h->nr_marks, ord, has);
+      hipLaunchKernelGGL(k_round_split, dim3(gn), dim3(kT), 0, st, n, h->pre_block, has, nlw,
+                         flag, epoch << 32);
+      hipLaunchKernelGGL(k_round_relabel, dim3(gn), dim3(kT), 0, st, n, h->pre_block, nlw, flag,
+                         has, h->nr_marks);
+      BISIM_TRY_HIP(hipGetLastError());
+    }
   }
 
   // 5. slot statistics and mark-word layout
@@ -393,7 +397,9 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
                        cursor, h->in_src, h->in_ord);
   BISIM_TRY_HIP(hipGetLastError());
 
-  // 7. per-state transition counts by label bucket (block features)
+  // 7. per-state transition counts by label bucket (block features; not
+  // kept by the allocation-free entry point, which runs the plain policy)
+  if (arena_active()) return BISIM_OK;
   BISIM_TRY(dalloc(&h->sfeat, 16 * (size_t)n, st));
   BISIM_TRY_HIP(hipMemsetAsync(h->sfeat, 0, sizeof(uint32_t) * 16 * (size_t)n, st));
   if (m > 0)

@@ -1,8 +1,38 @@
-// Measurement helper: a plain streaming copy, used to measure the bandwidth
-// the device actually sustains and to calibrate memory-traffic counters.
+// The library's device allocator (stream-ordered memory, or a caller's
+// region for the allocation-free entry point) and a measurement helper: a
+// plain streaming copy, used to measure the bandwidth the device actually
+// sustains and to calibrate memory-traffic counters.
 #include "internal.h"
 
 namespace bisim {
+
+static thread_local ArenaScope* g_arena = nullptr;
+
+ArenaScope::ArenaScope(char* base, size_t capacity) : base_(base), cap_(capacity), outer_(g_arena) {
+  g_arena = this;
+}
+ArenaScope::~ArenaScope() { g_arena = outer_; }
+bool arena_active() { return g_arena != nullptr; }
+
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 1;
+  ArenaScope* a = g_arena;
+  if (!a) return hipMallocAsync(p, bytes, s);
+  const size_t at = (a->used_ + 255) & ~(size_t)255;
+  if (at > a->cap_ || bytes > a->cap_ - at) return hipErrorOutOfMemory;
+  *p = a->base_ + at;
+  a->used_ = at + bytes;
+  return hipSuccess;
+}
+
+hipError_t dev_free(void* p, hipStream_t s) {
+  if (!p) return hipSuccess;
+  for (ArenaScope* a = g_arena; a; a = a->outer_)
+    if ((char*)p >= a->base_ && (char*)p < a->base_ + a->cap_) return hipSuccess;
+  return hipFreeAsync(p, s);
+}
+
 namespace {
 __global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src,
                                                 uint4* __restrict__ dst, uint64_t n16) {

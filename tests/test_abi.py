@@ -42,3 +42,21 @@ def test_last_error_without_gpu():
     assert b"n >= 0" in L.bisim_last_error()
     assert L.lts_load(None, None, None, 1, 0, 0, None, None, ctypes.byref(h)) == bisim.E_INVALID
     assert L.bisim_set_option(None, 1, 0) == bisim.E_INVALID
+
+
+def test_noalloc_rejects_oversize_before_device_work():
+    """The allocation-free entry point checks its static region's bound from
+    n, m and K before any device call (so this runs without a GPU)."""
+    from paper_2105_11788_amd import bisim
+    if not os.path.exists(bisim.LIB_PATH):
+        pytest.skip("libbisim.so not built")
+    import ctypes
+    L = bisim.load_library()
+    st = bisim.bisim_stats()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the size check comes first
+    n = bisim.NOALLOC_SCRATCH_BYTES // 64  # ~100 bytes per state needed: too large
+    rc = L.coarsest_partition_noalloc(None, None, None, n, 0, 1, None, fake, ctypes.byref(st), None)
+    assert rc == bisim.E_UNSUPPORTED
+    assert b"static region" in L.bisim_last_error()
+    rc = L.coarsest_partition_noalloc(None, None, None, 10, 0, 1, None, None, ctypes.byref(st), None)
+    assert rc == bisim.E_INVALID  # NULL output
