@@ -41,7 +41,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ENGINE_NAMES = {0: "automatic", 1: "persistent", 2: "per-phase kernels"}
+ENGINE_NAMES = {0: "automatic", 1: "persistent", 2: "per-phase kernels",
+                3: "member-list kernels"}
 
 WORKLOADS = {
     "planted-quotient-1M": dict(
@@ -104,6 +105,76 @@ def phase_bytes(n: int, work: np.ndarray, nsplit: np.ndarray):
                     4 * n + n / 4 + n / 8 + 16 * touched + 20 * s + 24 * t_prev], axis=1)
     out[-1] = 0.0
     return out
+
+
+LISTS_KERNELS = ["k_l_mark (select+mark)", "k_l_compare (compare+elect+rank)",
+                 "k_l_relabel (relabel+tail, clear marks)", "k_l_swap (swaps+ranges+unstable)"]
+
+
+def lists_bytes(n: int, iters: int, w: dict):
+    """Bytes each kernel of the member-list engine moves per launch, averaged
+    over the iterations: the byte model of its loads, stores and atomics
+    (int32 ids, 64-bit mark words, bids and bitmap words; an atomic counts
+    its read and its write) times the run's work totals:
+      mark     8 (range of C) + 12 per member (perm, in_ptr pair)
+               + 40 per in-transition (source, rank, mark-word and
+                 touched-word atomics) + 12 per touched state (block,
+                 one-state flag) + 16 per listed segment (range, entry)
+      compare  n/8 (touched bitmap scan) + 20 per touched state (block,
+               own and leader mark words) + 48 per split state (bid,
+               rank, split-flag atomics, old block and rank stores)
+               + 16 per segment + 12 per member visited (perm, touched word)
+      relabel  n/4 (split and touched bitmap scans) + 16 per touched state
+               (mark word and touched word cleared) + 100 per split state
+               (its block's bid, range and count, position, label store,
+               front/tail counters, tail state and its flag, pair store,
+               five per-state stores)
+      swap     n/8 (split bitmap scan, words cleared) + 48 per split state
+               (six per-state loads, pair load, four perm/pos stores)
+               + 72 per split block (range, counters, flags, unstable bits)
+    Returns a list of four floats (bytes per launch)."""
+    it = max(1, iters - 1)  # the final pass does no work
+    nb = n / 8.0
+    mark = 8 * it + 12 * w["members"] + 40 * w["in_transitions"] + 12 * w["touched"] \
+        + 16 * w["segments"]
+    comp = nb * it + 20 * w["touched"] + 48 * w["split_states"] + 16 * w["segments"] \
+        + 12 * w["member_visits"]
+    rel = 2 * nb * it + 16 * w["touched"] + 100 * w["split_states"]
+    swp = nb * it + 48 * w["split_states"] + 72 * w["split_blocks"]
+    return [mark / it, comp / it, rel / it, swp / it]
+
+
+def batch_bytes(sizes, st, mask_bytes: int):
+    """Bytes the batched kernel moves in one launch, from its work totals
+    (st["work"], per tier) and a byte model of its global-memory loads,
+    stores and atomics (an atomic counts its read and its write):
+      both tiers   8 per state (preprocessed label in, result out)
+      LDS tier     per iteration only the in-transitions of the splitter
+                   leave LDS: 8 per splitter member (in_ptr pair) + 8 per
+                   in-transition (source, action rank)
+      member lists 56 + mask per state at set-up (labels, marks, bids,
+                   counters, ranges, member list and positions)
+                   + per iteration 8 (splitter range) + 12 per member (perm,
+                   in_ptr pair) + (8 + 2 mask) per in-transition (source,
+                   rank, mark atomic) + (4 + 3 mask) per touched state (block;
+                   own and leader marks; marks cleared) + 8 per touched
+                   leader listed (range) + 4 per member visited (perm)
+                   + 104 per split state (bid and rank atomics; bid, range,
+                   count, position, tail state, counters, pair, label; swap)
+                   + 24 per split block (ranges and counters)
+    Bitmaps and per-iteration lists live in LDS for the member-list tier too
+    (when they fit) and count nothing.  sizes: instance sizes; the member-list
+    tier holds the st["global_instances"] largest."""
+    sz = np.sort(np.asarray(sizes, np.float64))[::-1]
+    g = int(st["global_instances"])
+    n_list = float(sz[:g].sum())
+    n_all = float(sz.sum())
+    w0, w1 = st["work"][0], st["work"][1]
+    lds = 8.0 * w0[1] + 8.0 * w0[2]
+    mk = float(mask_bytes)
+    lists = (56 + mk) * n_list + 8.0 * w1[0] + 12.0 * w1[1] + (8 + 2 * mk) * w1[2] \
+        + (4 + 3 * mk) * w1[3] + 8.0 * w1[4] + 4.0 * w1[5] + 104.0 * w1[6] + 24.0 * w1[7]
+    return 8.0 * n_all + lds + lists
 
 
 def method_bytes(n: int, m: int, mark_length: int, work: np.ndarray, nsplit: np.ndarray):
@@ -327,7 +398,17 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
     if engine != 1:
         res["phase_ms"], res["phase_samples"] = h.phase_times()
         h.set_option(bisim.OPT_PROFILE_EVERY, 0)
-    if trace:
+    if trace and engine == 3:
+        h.set_option(bisim.OPT_COUNT_WORK, 1)
+        _, st_w = h.run(out)
+        h.set_option(bisim.OPT_COUNT_WORK, 0)
+        assert st_w.iterations == st.iterations
+        res["work_totals"] = h.work()
+        tr_ = h.set_trace(st.iterations + 1)
+        h.run(out)
+        res["nsplit"] = tr_[1].numpy()[:st.iterations]
+        h.set_trace(0)
+    elif trace:
         iters = st.iterations
         tr = h.set_trace(iters + 1, work=True)
         _, st_tr = h.run(out)
@@ -347,15 +428,37 @@ def form_plain(bisim, gen, args):
     r = run_single(bisim, L, args, args.engine)
     st = r["stats"]
     iters = st.iterations
-    pb = phase_bytes(L.n, r["work"], r["nsplit"])
-    mb = method_bytes(L.n, L.m, st.mark_length, r["work"], r["nsplit"])
     copy_gbs = bisim.copy_bandwidth(1 << 30)
     names = ["k_fused_x (relabel+select+mark)", "k_fused_y (compare+elect)"]
-    if args.engine == 1:
+    if args.engine == 3:
+        lb = lists_bytes(L.n, iters, r["work_totals"])
+        ms = r["phase_ms"][:4]
+        q = int(np.argmax(ms))
+        kernel = LISTS_KERNELS[q]
+        touched_launch = float(lb[q])
+        kern_ms = float(ms[q])
+        # the method's bytes of a whole iteration (its passes over all
+        # transitions and states), against the time of all four kernels
+        edges = np.zeros((iters, 4))
+        edges[:-1, 1] = r["work_totals"]["in_transitions"] / max(1, iters - 1)
+        mb_it = method_bytes(L.n, L.m, st.mark_length, edges, r["nsplit"]).sum(axis=1)
+        bytes_launch = float(mb_it[:-1].mean()) * kern_ms / max(float(ms.sum()), 1e-12)
+        per_phase = {LISTS_KERNELS[i]: {"avg_us": float(ms[i] * 1e3),
+                                        "bytes_per_launch": float(lb[i]),
+                                        "GBs": float(lb[i] / (ms[i] * 1e-3) / 1e9)
+                                        if ms[i] > 0 else None,
+                                        "samples": int(r["phase_samples"][i])}
+                     for i in range(4)}
+        per_phase["work_totals"] = r["work_totals"]
+    elif args.engine == 1:
+        pb = phase_bytes(L.n, r["work"], r["nsplit"])
+        mb = method_bytes(L.n, L.m, st.mark_length, r["work"], r["nsplit"])
         kernel, kern_ms = "k_persistent", r["kern_ms"]
         bytes_launch, touched_launch = float(mb.sum()), float(pb.sum())
         per_phase = None
     else:
+        pb = phase_bytes(L.n, r["work"], r["nsplit"])
+        mb = method_bytes(L.n, L.m, st.mark_length, r["work"], r["nsplit"])
         ms = r["phase_ms"][:2]
         q = int(np.argmax(ms))  # every phase runs once per iteration
         kernel = names[q]
@@ -474,6 +577,7 @@ def form_batched(bisim, gen, args):
         b.set_option(bisim.BOPT_WG_SIZE, args.batch_wg)
     out = bisim.DeviceArray(b.N, np.int32)
     log(f"batch loaded and preprocessed ({time.perf_counter() - t:.1f}s)")
+    st = None
     for w in range(args.warmup):
         _, its, st = b.run(out)
         log(f"warmup {w}: max #It={st['max_iterations']} t_alg={st['t_alg_ms']:.1f} ms "
@@ -481,11 +585,20 @@ def form_batched(bisim, gen, args):
             f"{st['global_instances']})")
     bisim.synchronize()
     t0 = time.perf_counter()
+    alg = []
     for _ in range(args.steps):
         _, its, st = b.run(out)
+        alg.append(st["t_alg_ms"])
     bisim.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     work = float(sum(x.m * int(i) for x, i in zip(insts, its)))
+    mask_bytes = 8 if max(x.K for x in insts) > 32 else 4
+    moved = batch_bytes([x.n for x in insts], st, mask_bytes)
+    kern_ms = float(np.mean(alg))
+    achieved = moved / (kern_ms * 1e-3) / 1e9
+    copy_gbs = bisim.copy_bandwidth(1 << 30)
+    log(f"k_batch {kern_ms:.1f} ms per launch, {moved / 1e9:.2f} GB moved (byte model) -> "
+        f"{achieved:.1f} GB/s; copy {copy_gbs:.0f} GB/s; work {st['work']}")
     b.close()
     # the same instances one at a time through the plain single-instance engine
     rng = np.random.default_rng(0)
@@ -520,6 +633,28 @@ def form_batched(bisim, gen, args):
     res = base_record(args, "transitions*iterations/sec (batched refinement to fixpoint)",
                       work / (ms * 1e-3), ms, cfg)
     res.update({"seconds_to_fixpoint": ms / 1000.0,
+                "t_alg_ms": kern_ms,
+                "roofline": {
+                    "bound": "hbm",
+                    "kernel": "k_batch",
+                    "achieved": achieved,
+                    "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": stored_traffic("k_batch", cfg["workload"]),
+                    "bytes_per_launch": moved,
+                    "bytes_definition": "bytes the batched kernel moves per launch: the byte "
+                                        "model of its global loads, stores and atomics "
+                                        "(bench.py batch_bytes) times its work totals per "
+                                        "tier; LDS-resident state counts nothing",
+                    "kernel_ms": kern_ms,
+                    "measured_copy_GBs": copy_gbs,
+                    "work_totals": {"lds_tier": st["work"][0], "member_list_tier": st["work"][1]},
+                    "note": "one launch refines every instance; its time is the critical path "
+                            "of the slowest instance (one workgroup, one dependent chain of "
+                            "global-memory round trips per phase), so the kernel is latency-"
+                            "bound and moves little data per second",
+                },
                 "plain_one_by_one_estimate_s": plain_est_ms / 1000.0,
                 "speedup_vs_plain": plain_est_ms / ms,
                 "iteration_count": {"batched_critical_path": int(its.max()),
@@ -569,7 +704,8 @@ def main():
     ap.add_argument("--workload", default="planted-quotient-1M",
                     help="one of " + ", ".join(sorted(WORKLOADS)) + ", or fan-out-<n>")
     ap.add_argument("--engine", type=int, default=0,
-                    help="0 automatic (per-phase kernels), 1 persistent, 2 per-phase kernels")
+                    help="0 automatic, 1 persistent, 2 per-phase kernels (all states), "
+                         "3 per-phase kernels over member lists")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--hybrid", action="store_true",
                     help="signature form: signature rounds, then Algorithm 3")

@@ -147,7 +147,17 @@ const char* bisim_last_error(void);
  *   BISIM_OPT_ENGINE        0 = automatic, 1 = one cooperative persistent
  *                           launch per fixpoint (grid barriers between
  *                           phases), 2 = one kernel per phase, launched in
- *                           batches with a device-side done flag.
+ *                           batches with a device-side done flag, each
+ *                           scanning all states, 3 = four kernels per
+ *                           iteration over member lists (a refinable
+ *                           partition): work per iteration follows the
+ *                           splitter's members and in-transitions and the
+ *                           states they touch, not n; Algorithm 3 with the
+ *                           plain policy only (else BISIM_E_UNSUPPORTED at
+ *                           coarsest_partition); about 68 more bytes of
+ *                           device memory per state, allocated on first use.
+ *   BISIM_OPT_COUNT_WORK    0 (default) or 1: engine 3 accumulates work totals
+ *                           over the run (bisim_get_work).
  *   BISIM_OPT_FIRST_SPLITTER  -1 (default) or a block label of the
  *                           preprocessed partition to use as the first
  *                           splitter instead of the smallest (test hook, used
@@ -167,6 +177,7 @@ const char* bisim_last_error(void);
                                      iterations per run) with events bound to the end of
                                      each kernel; a phase's time is the distance between
                                      the ends of consecutive kernels of the stream */
+#define BISIM_OPT_COUNT_WORK 7
 #define BISIM_OPT_ALGORITHM 6     /* 3 (default): the labelled algorithm (Algorithm 3, with
                                      section 4.1's preprocessing); 2: the algorithm for the
                                      relational coarsest partition problem (section 3.2,
@@ -216,6 +227,16 @@ bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
 bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* samples);
 
 /*
+ * bisim_get_work — work totals of the last run with BISIM_OPT_COUNT_WORK set
+ * (engine 3): out (host, 8 entries) = members of the splitters, their
+ * in-transitions, touched states, listed member segments, members of
+ * leader-touched blocks visited, split states, split blocks, iterations in
+ * which something split.  Zeros for other engines.
+ * Errors: BISIM_E_INVALID.
+ */
+bisim_status bisim_get_work(bisim_lts* h, int64_t* out);
+
+/*
  * bisim_set_trace — record, for each iteration k < cap of subsequent
  * coarsest_partition calls:
  *   trace_C[k]        the splitter label (-1 for the final pass);
@@ -260,6 +281,14 @@ typedef struct {
   int32_t grid;             /* workgroups launched */
   double t_pre_ms;          /* lts_batch_load device time */
   double t_alg_ms;          /* device time of the last coarsest_partition_batch */
+  int64_t work[2][8];       /* work totals of the last run over all instances:
+                               [0] LDS-resident instances: iterations, splitter
+                               members, their in-transitions, touched states, -,
+                               split states, -, instances;
+                               [1] member-list instances: iterations, splitter
+                               members, their in-transitions, touched states,
+                               touched leaders listed, members of their blocks
+                               visited, split states, split blocks */
 } bisim_batch_stats;
 
 /*
@@ -300,7 +329,7 @@ void lts_batch_free(bisim_batch* b);
 
 /*
  * bisim_batch_set_option — per-batch settings.
- *   BISIM_BOPT_WG_SIZE     0 (default: autotuned) or 256, 512, 1024.
+ *   BISIM_BOPT_WG_SIZE     0 (default) or 256: the one size the kernel is built for.
  *   BISIM_BOPT_GRID        0 (default: autotuned) or a workgroup count.
  *   BISIM_BOPT_LDS_LIMIT   0 (default: the device's per-workgroup LDS) or a
  *                          smaller byte budget; instances whose state does
@@ -362,10 +391,23 @@ bisim_status mlp_get_params(const bisim_mlp* w, float* host_fp32);
 /*
  * mlp_forward — y[r] = network(x[r]) for r < rows.
  *   x device fp32 [rows][F] (row-major); y device fp32 [rows].
+ * The forward pass computes with bf16 inputs: each x value is rounded to
+ * bf16 (nearest even) in the kernel, so fp32 features (what the refinement
+ * engines and the training-data collector produce) need no separate
+ * conversion pass; mlp_forward_bf16 takes inputs already in bf16.
  * Synchronises hip_stream.  Errors: BISIM_E_INVALID, BISIM_E_DEVICE.
  */
 bisim_status mlp_forward(const bisim_mlp* w, const float* x, int64_t rows, float* y,
                          void* hip_stream);
+
+/*
+ * mlp_forward_bf16 — as mlp_forward with x device bf16 [rows][F] (IEEE
+ * bfloat16 bit patterns, row-major); y device fp32 [rows].  Results equal
+ * mlp_forward's on the fp32 values of the same bf16 numbers.
+ * Synchronises hip_stream.  Errors: BISIM_E_INVALID, BISIM_E_DEVICE.
+ */
+bisim_status mlp_forward_bf16(const bisim_mlp* w, const void* x_bf16, int64_t rows, float* y,
+                              void* hip_stream);
 
 /*
  * mlp_train_step — one full-batch step on rows (x, target):

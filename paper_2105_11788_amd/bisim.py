@@ -37,11 +37,13 @@ OPT_ITER_LIMIT = 3
 OPT_GRID = 4
 OPT_PROFILE_EVERY = 5
 OPT_ALGORITHM = 6  # 3: labelled (Algorithm 3, default); 2: one-action RCPP (Algorithm 2)
+OPT_COUNT_WORK = 7  # engine 3: accumulate work totals (LTS.work())
 ALGORITHM_RCPP, ALGORITHM_LABELLED, ALGORITHM_SIGNATURE, ALGORITHM_HYBRID = 2, 3, 100, 101  # OPT_ALGORITHM values
 
 ENGINE_AUTO = 0
 ENGINE_PERSISTENT = 1
 ENGINE_PHASES = 2
+ENGINE_LISTS = 3
 
 EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
            "bisim_set_option", "bisim_set_trace", "bisim_get_preprocessed",
@@ -49,7 +51,7 @@ EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
            "bisim_batch_set_option", "mlp_num_params", "mlp_create", "mlp_free",
            "mlp_get_params", "mlp_forward", "mlp_train_step", "bisim_set_splitter_policy",
            "bisim_collect_training", "bisim_get_phase_times", "bisim_device_copy",
-           "coarsest_partition_noalloc"]
+           "coarsest_partition_noalloc", "bisim_get_work", "mlp_forward_bf16"]
 
 # size of the static device region of coarsest_partition_noalloc (bisim.h)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -279,6 +281,21 @@ class LTS:
                                        cnt.ctypes.data_as(ctypes.c_void_p)))
         return ms, cnt
 
+    def work(self):
+        """Work totals of the last run with OPT_COUNT_WORK (engine 3): dict of
+        members, in_transitions, touched, segments, member_visits, split_states,
+        split_blocks, split_iterations."""
+        L = self._L
+        if not getattr(L, "_work_declared", False):
+            L.bisim_get_work.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+            L.bisim_get_work.restype = ctypes.c_int32
+            L._work_declared = True
+        w = np.zeros(8, np.int64)
+        _check(L.bisim_get_work(self._h, w.ctypes.data_as(ctypes.c_void_p)))
+        keys = ("members", "in_transitions", "touched", "segments", "member_visits",
+                "split_states", "split_blocks", "split_iterations")
+        return dict(zip(keys, (int(x) for x in w)))
+
     def preprocessed(self):
         """(pi_pre block ids, nr_marks) as numpy arrays."""
         b = DeviceArray(self.n, np.int32)
@@ -310,7 +327,8 @@ class bisim_batch_stats(ctypes.Structure):
     _fields_ = [("max_iterations", ctypes.c_int64), ("sum_iterations", ctypes.c_int64),
                 ("lds_instances", ctypes.c_int64), ("global_instances", ctypes.c_int64),
                 ("workgroup_size", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("t_pre_ms", ctypes.c_double), ("t_alg_ms", ctypes.c_double)]
+                ("t_pre_ms", ctypes.c_double), ("t_alg_ms", ctypes.c_double),
+                ("work", (ctypes.c_int64 * 8) * 2)]
 
 
 BOPT_WG_SIZE = 1
@@ -383,7 +401,9 @@ class Batch:
         _check(self._L.coarsest_partition_batch(self._h, ctypes.c_void_p(out.ptr),
                                                 its.ctypes.data_as(ctypes.c_void_p),
                                                 ctypes.byref(st)))
-        return out, its, {f: getattr(st, f) for f, _ in bisim_batch_stats._fields_}
+        d = {f: getattr(st, f) for f, _ in bisim_batch_stats._fields_ if f != "work"}
+        d["work"] = [[int(x) for x in row] for row in st.work]
+        return out, its, d
 
     def split(self, flat: np.ndarray):
         """Per-instance views of a concatenated result."""
@@ -426,6 +446,8 @@ def _declare_learned(L):
     L.mlp_get_params.restype = i32
     L.mlp_forward.argtypes = [P, P, i64, P, P]
     L.mlp_forward.restype = i32
+    L.mlp_forward_bf16.argtypes = [P, P, i64, P, P]
+    L.mlp_forward_bf16.restype = i32
     L.mlp_train_step.argtypes = [P, P, P, i64, ctypes.c_float, ctypes.POINTER(ctypes.c_float), P, P]
     L.mlp_train_step.restype = i32
     L.bisim_set_splitter_policy.argtypes = [P, i32, P, i32]
@@ -478,6 +500,16 @@ class MLP:
         y = DeviceArray(rows, np.float32)
         _check(self._L.mlp_forward(self._h, ctypes.c_void_p(xd.ptr), rows, ctypes.c_void_p(y.ptr),
                                    None))
+        return y.numpy()
+
+    def forward_bf16(self, x_bits) -> np.ndarray:
+        """mlp_forward_bf16: x_bits holds bf16 bit patterns (uint16, rows x F)."""
+        xd = x_bits if not isinstance(x_bits, np.ndarray) else \
+            DeviceArray.from_numpy(np.ascontiguousarray(x_bits, np.uint16), np.uint16)
+        rows = xd.count // self.F
+        y = DeviceArray(rows, np.float32)
+        _check(self._L.mlp_forward_bf16(self._h, ctypes.c_void_p(xd.ptr), rows,
+                                        ctypes.c_void_p(y.ptr), None))
         return y.numpy()
 
     def train_step(self, x, t, lr: float, want_grad: bool = False):

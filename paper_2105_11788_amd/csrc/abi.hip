@@ -20,6 +20,7 @@ void set_error(const char* fmt, ...) {
 static void free_handle(bisim_lts* h) {
   if (!h) return;
   hipStream_t s = h->stream;
+  lists_free(h);
   void* ptrs[] = {h->init_block, h->pre_block, h->nr_marks, h->in_ptr, h->in_src, h->in_ord, h->woff,
                   h->block,     h->mw,       h->tb,     h->lt,     h->ub,     h->nlw,
                   h->tlist,     h->slist,    h->ctl,    h->sfeat,  h->acc,    h->born,
@@ -161,8 +162,12 @@ bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value) {
   }
   switch (option) {
     case BISIM_OPT_ENGINE:
-      if (value < 0 || value > 2) break;
+      if (value < 0 || value > 3) break;
       h->engine = (int)value;
+      return BISIM_OK;
+    case BISIM_OPT_COUNT_WORK:
+      if (value != 0 && value != 1) break;
+      h->count_work = (int)value;
       return BISIM_OK;
     case BISIM_OPT_FIRST_SPLITTER:
       if (value < -1 || value >= h->n) break;
@@ -219,6 +224,15 @@ bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* sample
     avg_ms[q] = h->phase_cnt[q] ? h->phase_ms[q] / (double)h->phase_cnt[q] : 0.0;
     if (samples) samples[q] = h->phase_cnt[q];
   }
+  return BISIM_OK;
+}
+
+bisim_status bisim_get_work(bisim_lts* h, int64_t* out) {
+  if (!h || !out) {
+    set_error("bisim_get_work: NULL handle or output");
+    return BISIM_E_INVALID;
+  }
+  for (int i = 0; i < 8; ++i) out[i] = (int64_t)h->lists_work[i];
   return BISIM_OK;
 }
 

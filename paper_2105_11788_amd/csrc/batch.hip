@@ -55,10 +55,12 @@ struct bisim_batch {
   // member-list tier scratch
   int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr, *cnt = nullptr,
           *fc = nullptr, *gc = nullptr, *tmp = nullptr, *rk = nullptr, *fi = nullptr,
-          *ob = nullptr, *nev = nullptr, *ltl = nullptr;
-  uint64_t *sf = nullptr, *us = nullptr;
+          *ob = nullptr, *nev = nullptr, *ltl = nullptr, *tlb = nullptr, *se = nullptr,
+          *sgs = nullptr;
+  uint64_t *sf = nullptr, *us = nullptr, *tmp64 = nullptr;
   uint32_t* iters_d = nullptr;  // [count]
   uint32_t* ctl_d = nullptr;    // [0] queue head, [1] error
+  unsigned long long* work_d = nullptr;  // [16] work totals per tier
   // options / tuning
   int opt_wg = 0, opt_grid = 0, opt_lds = 0, opt_retune = 0;
   int wg = 0, grid = 0, lds_bytes = 0;
@@ -97,11 +99,12 @@ struct BArgs {
   uint64_t* lt;
   int32_t* tl;
   int32_t* sl;
-  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ob, *nev, *ltl;
-  uint64_t *sf, *us;
+  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ob, *nev, *ltl, *tlb, *se, *sgs;
+  uint64_t *sf, *us, *tmp64;
   int32_t* out;
   uint32_t* iters;
   uint32_t* ctl;
+  unsigned long long* work;  // [2][8] totals per tier (see bisim_batch_stats)
   uint32_t lds_bytes;
 };
 
@@ -127,6 +130,7 @@ __host__ __device__ inline uint64_t lds_need(uint32_t n) {
 }
 
 constexpr uint32_t kCU = 4;  // member-list tier: split-list entries per thread and step
+constexpr int kBatchWG = 256;  // the one workgroup size the batched kernel is built for
 
 struct Shared {
   uint32_t cand[2];
@@ -137,30 +141,9 @@ struct Shared {
   uint32_t wsum[16];  // member-list tier: per-wave sums of the block-size scan
   uint32_t bad;       // member-list tier: inconsistent block sizes (never expected)
   uint32_t job;
-};
-
-// Member-list tier (instances too large for LDS): the partition is also kept
-// as a refinable partition, so an iteration visits C's members, the touched
-// states and the members of blocks whose leader was touched instead of all
-// n states.  perm lists the states block by block; block b (a label) owns
-// perm[bs[b] .. be[b]).  A split moves the split-off states to the end of the
-// block's range by swaps and gives that tail to the new label.
-struct GList {
-  int32_t* perm;  // [n] states ordered by block
-  int32_t* pos;   // [n] position of each state in perm
-  int32_t* bs;    // [n] per label: first position of its block
-  int32_t* be;    // [n] per label: one past the last position
-  int32_t* cnt;   // [n] per label: states split off this iteration (0 between iterations)
-  int32_t* fc;    // [n] per label: split states found in the front part
-  int32_t* gc;    // [n] per label: staying states found in the tail
-  int32_t* tmp;   // [n] per position: tail positions of staying states, by index
-  int32_t* rk;    // [n] per split-list entry: rank within its block's split part
-  int32_t* fi;    // [n] per split-list entry: index among front split states, or -1
-  int32_t* ob;    // [n] per split-list entry: old block label
-  int32_t* nev;   // [n] per split-list entry: start of its block's tail
-  int32_t* ltl;   // [n] touched leaders
-  uint64_t* sf;   // [ceil(n/64)] split flags
-  uint64_t* us;   // [ceil(n/4096)] summary of the unstable bitmap
+  // work totals of the current instance: in-transitions of the splitters,
+  // splitter members (LDS tier), member visits and split blocks (member lists)
+  unsigned long long wE, wM, wV, wB;
 };
 
 __device__ __forceinline__ void wg_min(uint32_t* dst, uint32_t v) {
@@ -206,10 +189,12 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
     sh.cand[1] = kNone;
     sh.nT[0] = sh.nT[1] = sh.nS[0] = sh.nS[1] = 0;
     sh.ltany[0] = sh.ltany[1] = 0;
+    sh.wE = sh.wM = 0;
   }
   __syncthreads();
   const uint32_t cap = 3u * n + 1u;
   uint32_t it = 0;
+  uint64_t sT = 0, sS = 0;  // work totals (thread 0)
   for (;; ++it) {
     const uint32_t par = it & 1;
     const uint32_t C = sh.cand[par];
@@ -245,7 +230,8 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
         const uint32_t base = base0 + u * kWave;
         const uint32_t t = base + lane();
         const bool hit = (hm >> u) & 1u;
-        if (__ballot(hit) == 0) continue;
+        const uint64_t hb = __ballot(hit);
+        if (hb == 0) continue;
         uint32_t beg = 0, deg = 0;
         if (hit) {
           beg = a.in_ptr[s0 + t];
@@ -253,6 +239,10 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
         }
         const uint32_t incl = wave_incl_scan_u32(deg);
         const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        if (lane() == 0) {
+          atomicAdd(&sh.wE, (unsigned long long)total);
+          atomicAdd(&sh.wM, (unsigned long long)__popcll(hb));
+        }
         for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
           const uint32_t e = e0 + lane();
           const bool valid = e < total;
@@ -340,6 +330,10 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
     // ---- C: relabel, unstable updates, clear marks
     {
       const uint32_t nS = sh.nS[par], nT = sh.nT[par];
+      if (tid == 0) {
+        sT += nT;
+        sS += nS;
+      }
       uint32_t best = kNone;
       for (uint32_t i = tid; i < nS; i += nthr) {
         const int32_t s = S[i];
@@ -369,8 +363,70 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
     }
     __syncthreads();
   }
+  if (tid == 0) {
+    atomicAdd(&a.work[0], (unsigned long long)(it + 1));
+    atomicAdd(&a.work[1], sh.wM);
+    atomicAdd(&a.work[2], sh.wE);
+    atomicAdd(&a.work[3], (unsigned long long)sT);
+    atomicAdd(&a.work[5], (unsigned long long)sS);
+    atomicAdd(&a.work[7], 1ull);
+  }
   for (uint32_t s = tid; s < n; s += nthr) a.out[s0 + s] = w.blk[s];
   return it + 1;
+}
+
+// Member-list tier (instances too large for LDS): the partition is also kept
+// as a refinable partition, so an iteration visits C's members, the touched
+// states and the members of blocks whose leader was touched instead of all
+// n states.  perm lists the states block by block; block b (a label) owns
+// perm[bs[b] .. be[b]).  A split moves the split-off states to the end of the
+// block's range by swaps and gives that tail to the new label.
+//
+// One workgroup refines the instance; every phase is a chain of dependent
+// global-memory round trips, so the layout keeps that chain short: the
+// unstable, touched and split bitmaps (and the unstable summary) sit in LDS
+// when they fit beside a minimum of list space, and so do the per-iteration
+// lists (touched states with their block, touched leaders, split states with
+// everything the later phases need); list entries beyond the LDS capacity
+// spill to per-instance global arrays.  Ranks within a block's split part are
+// taken when the split is found, so the relabel and the search for staying
+// states in the tail run in one phase, and the staying state found for a
+// tail position is stored with it, so the swap is one more round trip.
+struct GList {
+  int32_t* perm;    // [n] states ordered by block
+  int32_t* pos;     // [n] position of each state in perm
+  int32_t* bs;      // [n] per label: first position of its block
+  int32_t* be;      // [n] per label: one past the last position
+  int32_t* cnt;     // [n] per label: states split off this iteration (0 between iterations)
+  int32_t* fc;      // [n] per label: split states found in the front part
+  int32_t* gc;      // [n] per label: staying states found in the tail
+  uint64_t* tmp64;  // [n] per tail position: (staying state << 32) | its position, by index
+  // global spill of the lists (entry i >= the LDS capacity)
+  int32_t *ts, *tb_, *lb, *ss, *sb_, *sr, *sf_, *sn, *sp, *se, *sgs;
+  uint64_t* sf;     // [ceil(n/64)] split flags (global fallback)
+  uint64_t* sg;     // [ceil(n/64)] labels of one-state blocks (global fallback)
+  uint64_t* us;     // [ceil(n/4096)] summary of the unstable bitmap (global fallback)
+};
+
+// A list field: entry i in LDS when i < cap, else in global memory.
+struct LField {
+  int32_t* l;
+  int32_t* g;
+};
+__device__ __forceinline__ int32_t* ent(const LField& f, uint32_t cap, uint32_t i) {
+  return i < cap ? f.l + i : f.g + i;
+}
+
+// Append one entry for lanes with pred (one LDS atomic per wave); returns the
+// entry's index, or kNone for lanes without pred.  Wave-uniform call.
+__device__ __forceinline__ uint32_t push_idx(uint32_t* cnt, bool pred) {
+  const uint64_t bal = __ballot(pred);
+  if (!bal) return kNone;
+  const int leader = __ffsll((unsigned long long)bal) - 1;
+  uint32_t base = 0;
+  if ((int)lane() == leader) base = atomicAdd(cnt, (uint32_t)__popcll(bal));
+  base = (uint32_t)__shfl((int)base, leader, kWave);
+  return pred ? base + (uint32_t)__popcll(bal & ((1ull << lane()) - 1ull)) : kNone;
 }
 
 // Set unstable bit b and keep the summary exact (sets only; the one clear per
@@ -381,20 +437,54 @@ __device__ __forceinline__ void wg_unstable_set(uint64_t* ub, uint64_t* us, uint
   if (old == 0) atomicOr((unsigned long long*)&us[w >> 6], 1ull << (w & 63));
 }
 
+// bytes of LDS per unit of list capacity: touched (state, block), touched
+// leader, split (state, block, rank, front index, tail start, position, end,
+// start of the block's range)
+constexpr uint32_t kListBytes = 4u * (2 + 1 + 8);
+constexpr uint32_t kMinListCap = 256;
+
 // The refinement loop of one instance by one workgroup, member-list tier.
-// Same phases and the same splitter sequence as wg_refine; the scans over
-// all states are replaced by visits of block ranges.
+// Same phases and the same splitter sequence as wg_refine.
 template <class MaskT>
-__device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, GList g,
-                                    int32_t* T, int32_t* S, uint32_t s0, uint32_t n) {
+__device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, MaskT* mw,
+                                    uint64_t* nlb, GList g, uint64_t* lds, uint32_t lds_bytes,
+                                    uint64_t* gub, uint64_t* gtb, uint32_t s0, uint32_t n) {
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t wid = tid / kWave, nwav = nthr / kWave;
   const uint32_t nw = (n + 63u) >> 6, nsw = (nw + 63u) >> 6;
+  // LDS: bitmaps first (when they fit beside kMinListCap list entries), then lists
+  const uint32_t bm_bytes = 8u * (4u * nw + nsw);
+  const bool bm_lds = bm_bytes + kMinListCap * kListBytes <= lds_bytes;
+  uint64_t *ub, *tb, *sf, *sg, *us;
+  char* lp = reinterpret_cast<char*>(lds);
+  uint32_t lbytes = lds_bytes;
+  if (bm_lds) {
+    ub = lds;
+    tb = lds + nw;
+    sf = lds + 2 * nw;
+    sg = lds + 3 * nw;
+    us = lds + 4 * nw;
+    lp += bm_bytes;
+    lbytes -= bm_bytes;
+  } else {
+    ub = gub;
+    tb = gtb;
+    sf = g.sf;
+    sg = g.sg;
+    us = g.us;
+  }
+  const uint32_t cap = lbytes / kListBytes;
+  int32_t* li = reinterpret_cast<int32_t*>(lp);
+  const LField Ts{li, g.ts}, Tb{li + cap, g.tb_}, Lb{li + 2 * cap, g.lb};
+  const LField Ss{li + 3 * cap, g.ss}, Sb{li + 4 * cap, g.sb_}, Sr{li + 5 * cap, g.sr},
+      Sf{li + 6 * cap, g.sf_}, Sn{li + 7 * cap, g.sn}, Sp{li + 8 * cap, g.sp},
+      Se{li + 9 * cap, g.se}, Sg{li + 10 * cap, g.sgs};
+
   // ---- initial state: blocks of the preprocessed partition, all unstable
   for (uint32_t s = tid; s < n; s += nthr) {
-    w.blk[s] = a.pre_block[s0 + s] - (int32_t)s0;
-    w.mw[s] = 0;
-    w.nlb[s] = 0;
+    blk[s] = a.pre_block[s0 + s] - (int32_t)s0;
+    mw[s] = 0;
+    nlb[s] = 0;
     g.cnt[s] = 0;
     g.fc[s] = 0;
     g.gc[s] = 0;
@@ -404,24 +494,24 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
     for (uint32_t j = 0; j < 64 && (q << 6) + j < n; ++j)
       if ((uint32_t)(a.pre_block[s0 + (q << 6) + j] - (int32_t)s0) == (q << 6) + j)
         bits |= 1ull << j;
-    w.ub[q] = bits;
-    w.tb[q] = 0;
-    w.lt[q] = 0;
-    g.sf[q] = 0;
+    ub[q] = bits;
+    tb[q] = 0;
+    sf[q] = 0;
+    sg[q] = 0;
   }
-  for (uint32_t q = tid; q < nsw; q += nthr) g.us[q] = 0;
+  for (uint32_t q = tid; q < nsw; q += nthr) us[q] = 0;
   if (tid == 0) {
     sh.cand[0] = n ? 0u : kNone;
     sh.cand[1] = kNone;
     sh.nT[0] = sh.nT[1] = sh.nS[0] = sh.nS[1] = 0;
-    sh.ltany[0] = sh.ltany[1] = 0;
     sh.nL[0] = sh.nL[1] = 0;
     sh.bad = 0;
+    sh.wE = sh.wV = sh.wB = 0;
   }
   __syncthreads();
   for (uint32_t q = tid; q < nw; q += nthr)
-    if (w.ub[q]) atomicOr((unsigned long long*)&g.us[q >> 6], 1ull << (q & 63));
-  for (uint32_t s = tid; s < n; s += nthr) atomicAdd(&g.cnt[w.blk[s]], 1);
+    if (ub[q]) atomicOr((unsigned long long*)&us[q >> 6], 1ull << (q & 63));
+  for (uint32_t s = tid; s < n; s += nthr) atomicAdd(&g.cnt[blk[s]], 1);
   __syncthreads();
   // block ranges: exclusive prefix sums of the block sizes in label order
   // (thread-contiguous label ranges; wave scan, then the <= 16 wave totals)
@@ -436,14 +526,16 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
     uint32_t run = incl - sum;
     for (uint32_t q = 0; q < wid; ++q) run += sh.wsum[q];
     for (uint32_t b = lo; b < hi; ++b) {
+      const uint32_t c = (uint32_t)g.cnt[b];
       g.bs[b] = (int32_t)run;
       g.be[b] = (int32_t)run;  // fill cursor, ends at the block's end
-      run += (uint32_t)g.cnt[b];
+      if (c == 1) atomicOr((unsigned long long*)&sg[b >> 6], 1ull << (b & 63));
+      run += c;
     }
   }
   __syncthreads();
   for (uint32_t s = tid; s < n; s += nthr) {
-    const uint32_t p = (uint32_t)atomicAdd(&g.be[w.blk[s]], 1);
+    const uint32_t p = (uint32_t)atomicAdd(&g.be[blk[s]], 1);
     if (p >= n) {  // cannot happen with consistent counts; report, never write
       sh.bad = 1;
       continue;
@@ -459,32 +551,35 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
   for (uint32_t s = tid; s < n; s += nthr) g.cnt[s] = 0;
   __syncthreads();
 
-  const uint32_t cap = 3u * n + 1u;
+  const uint32_t itcap = 3u * n + 1u;
   uint32_t it = 0;
+  uint64_t sM = 0, sT = 0, sL = 0, sS = 0;  // work totals (thread 0)
   for (;; ++it) {
     const uint32_t par = it & 1;
     const uint32_t C = sh.cand[par];
     if (C == kNone) break;
-    if (it + 1 > cap) {
+    if (it + 1 > itcap) {
       if (tid == 0) atomicOr(&a.ctl[1], 1u);
       break;
     }
     const uint64_t epoch = (uint64_t)(it + 1) << 32;
     // ---- A: clear C, next candidate (one wave, through the summary), mark.
     // The search runs on the last wave: marking a small splitter's
-    // in-transitions falls to the first waves.
+    // in-transitions falls to the first waves.  A state's first touch (its
+    // touched bit set by this lane) lists it with its block, and a touched
+    // block leader is listed apart.
     if (wid == nwav - 1) {
       const uint32_t w0 = C >> 6;
-      const uint64_t bits = w.ub[w0] & ~(1ull << (C & 63));
+      const uint64_t bits = ub[w0] & ~(1ull << (C & 63));
       if (lane() == 0) {
-        w.ub[w0] = bits;
-        if (bits == 0) atomicAnd((unsigned long long*)&g.us[w0 >> 6], ~(1ull << (w0 & 63)));
+        ub[w0] = bits;
+        if (bits == 0) atomicAnd((unsigned long long*)&us[w0 >> 6], ~(1ull << (w0 & 63)));
       }
       // C is the smallest unstable label: the next one is the next set bit
       uint32_t next = kNone;
       for (uint32_t q = w0 >> 6; q < nsw; q += kWave) {
         const uint32_t qq = q + lane();
-        uint64_t sv = qq < nsw ? g.us[qq] : 0ull;
+        uint64_t sv = qq < nsw ? us[qq] : 0ull;
         if (qq == (w0 >> 6)) {
           sv &= ~0ull << (w0 & 63);
           const uint64_t b0 = 1ull << (w0 & 63);
@@ -495,7 +590,7 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
           const int l = __ffsll((unsigned long long)bal) - 1;
           const uint64_t v = (uint64_t)__shfl((unsigned long long)sv, l, kWave);
           const uint32_t word = ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)v) - 1);
-          const uint64_t wb = (word == w0) ? bits : w.ub[word];
+          const uint64_t wb = (word == w0) ? bits : ub[word];
           if (wb) next = (word << 6) + (uint32_t)(__ffsll((unsigned long long)wb) - 1);
           break;
         }
@@ -514,6 +609,7 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
         sh.bad = 1;
         csz = 0;
       }
+      if (tid == 0) sM += csz;
       for (uint32_t i0 = wid * kWave; i0 < csz; i0 += nwav * kWave) {
         const uint32_t i = i0 + lane();
         const bool hit = i < csz;
@@ -525,6 +621,7 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
         }
         const uint32_t incl = wave_incl_scan_u32(deg);
         const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        if (lane() == 0 && total) atomicAdd(&sh.wE, (unsigned long long)total);
         for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
           const uint32_t e = e0 + lane();
           const bool valid = e < total;
@@ -539,43 +636,71 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
           const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
           const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
           bool first = false, lead = false;
-          int32_t s = 0;
+          int32_t s = 0, b = 0;
           if (valid) {
             const uint32_t edge = jb + (ee - (ji - jd));
             s = a.in_src[edge] - (int32_t)s0;
             const int32_t o = a.in_ord[edge];
             const MaskT bit = (MaskT)1 << (o & (int)(sizeof(MaskT) * 8 - 1));
-            const int32_t bs_ = w.blk[s];
-            const MaskT old = atomic_or(&w.mw[s], bit);
-            first = (old == 0);
+            atomic_or(&mw[s], bit);
+            const uint64_t tbit = 1ull << (s & 63);
+            const uint64_t old =
+                atomicOr((unsigned long long*)&tb[s >> 6], (unsigned long long)tbit);
+            first = !(old & tbit);
             if (first) {
-              atomicOr((unsigned long long*)&w.tb[s >> 6], (unsigned long long)(1ull << (s & 63)));
-              lead = (bs_ == s);
+              b = blk[s];
+              // a touched leader of a one-state block has no untouched member
+              lead = (b == s) && !test_bit(sg, (uint32_t)s);
             }
           }
-          push(T, &sh.nT[par], s, first);
-          push(g.ltl, &sh.nL[par], s, lead);
+          const uint32_t ti = push_idx(&sh.nT[par], first);
+          if (first) {
+            *ent(Ts, cap, ti) = s;
+            *ent(Tb, cap, ti) = b;
+          }
+          const uint32_t li_ = push_idx(&sh.nL[par], lead);
+          if (lead) *ent(Lb, cap, li_) = s;
         }
       }
     }
     __syncthreads();
     // ---- B: compare touched states with their leader; untouched members of
-    // blocks whose leader was touched differ from it; elect
+    // blocks whose leader was touched differ from it.  A split state bids for
+    // its block's new leader, takes its rank within the block's split part
+    // and sets its split flag.
     {
       const uint32_t nT = sh.nT[par];
-      for (uint32_t i0 = wid * kWave; i0 < nT; i0 += nwav * kWave) {
-        const uint32_t i = i0 + lane();
-        bool sp = false;
-        int32_t s = 0, b = 0;
-        if (i < nT) {
-          s = T[i];
-          b = w.blk[s];
-          sp = (s != b) && (w.mw[s] != w.mw[b]);
+      for (uint32_t i0 = tid; i0 < nT; i0 += nthr * kCU) {
+        int32_t sv[kCU], bv[kCU];
+        MaskT ms[kCU], mb[kCU];
+#pragma unroll
+        for (uint32_t u = 0; u < kCU; ++u) {
+          const uint32_t i = i0 + u * nthr;
+          sv[u] = i < nT ? *ent(Ts, cap, i) : -1;
+          bv[u] = i < nT ? *ent(Tb, cap, i) : 0;
         }
-        if (sp)
-          atomicMax((unsigned long long*)&w.nlb[b],
-                    (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
-        push(S, &sh.nS[par], s, sp);
+#pragma unroll
+        for (uint32_t u = 0; u < kCU; ++u) {
+          ms[u] = sv[u] >= 0 ? mw[sv[u]] : (MaskT)0;
+          mb[u] = sv[u] >= 0 ? mw[bv[u]] : (MaskT)0;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kCU; ++u) {
+          const bool sp = sv[u] >= 0 && sv[u] != bv[u] && ms[u] != mb[u];
+          int32_t r = 0;
+          if (sp) {
+            atomicMax((unsigned long long*)&nlb[bv[u]],
+                      (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)sv[u])));
+            r = atomicAdd(&g.cnt[bv[u]], 1);
+            atomicOr((unsigned long long*)&sf[sv[u] >> 6], 1ull << (sv[u] & 63));
+          }
+          const uint32_t si = push_idx(&sh.nS[par], sp);
+          if (sp) {
+            *ent(Ss, cap, si) = sv[u];
+            *ent(Sb, cap, si) = bv[u];
+            *ent(Sr, cap, si) = r;
+          }
+        }
       }
       // members of the blocks whose leader was touched, 64 blocks at a time:
       // their member slots are spread over all waves by a prefix sum of the
@@ -586,12 +711,13 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
         int32_t b = 0;
         uint32_t lo = 0, sz = 0;
         if (j < nL) {
-          b = g.ltl[j];
+          b = *ent(Lb, cap, j);
           lo = (uint32_t)g.bs[b];
           sz = (uint32_t)g.be[b] - lo;
         }
         const uint32_t incl = wave_incl_scan_u32(sz);
         const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        if (wid == 0 && lane() == 0) atomicAdd(&sh.wV, (unsigned long long)total);
         for (uint32_t e0 = wid * kWave; e0 < total; e0 += nwav * kWave) {
           const uint32_t e = e0 + lane();
           const bool valid = e < total;
@@ -610,157 +736,172 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
           bool sp = false;
           if (valid) {
             s = g.perm[olo + (ee - (oin - osz))];
-            sp = !test_bit(w.tb, (uint32_t)s);
+            sp = !test_bit(tb, (uint32_t)s);
           }
-          if (sp)
-            atomicMax((unsigned long long*)&w.nlb[ob_],
+          int32_t r = 0;
+          if (sp) {
+            atomicMax((unsigned long long*)&nlb[ob_],
                       (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
-          push(S, &sh.nS[par], s, sp);
+            r = atomicAdd(&g.cnt[ob_], 1);
+            atomicOr((unsigned long long*)&sf[s >> 6], 1ull << (s & 63));
+          }
+          const uint32_t si = push_idx(&sh.nS[par], sp);
+          if (sp) {
+            *ent(Ss, cap, si) = s;
+            *ent(Sb, cap, si) = ob_;
+            *ent(Sr, cap, si) = r;
+          }
         }
       }
     }
     __syncthreads();
     const uint32_t nS = sh.nS[par], nT = sh.nT[par];
+    if (tid == 0) {
+      sT += nT;
+      sS += nS;
+      sL += sh.nL[par];
+    }
     // The split phases take kCU entries per thread and step; each stage issues
     // the loads (or atomics) of all of them before using any, so a step waits
     // for one memory latency per stage, not kCU.
-    // ---- C1: rank of each split state within its block's split part, split
-    // flags, relabel (later phases use the old label kept in ob); clear marks
+    // ---- C1: relabel each split state (its block's winning bid); the split
+    // part goes to the tail [ne, be) of the block's range: index the split
+    // states in front of ne, and record each staying state found in the tail
+    // (the state at ne + the split state's rank) under its index; clear the
+    // touched states' marks
     for (uint32_t i0 = tid; i0 < nS; i0 += nthr * kCU) {
-      int32_t sv[kCU], bv[kCU], rv[kCU];
+      int32_t sv[kCU], bv[kCU], rv[kCU], ev[kCU], cv[kCU], pv[kCU], uv[kCU], fv[kCU], gv[kCU];
       uint64_t nv[kCU];
 #pragma unroll
       for (uint32_t u = 0; u < kCU; ++u) {
         const uint32_t i = i0 + u * nthr;
-        sv[u] = i < nS ? S[i] : -1;
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < kCU; ++u) bv[u] = sv[u] >= 0 ? w.blk[sv[u]] : 0;
-#pragma unroll
-      for (uint32_t u = 0; u < kCU; ++u) {
-        nv[u] = sv[u] >= 0 ? w.nlb[bv[u]] : 0ull;
-        rv[u] = sv[u] >= 0 ? atomicAdd(&g.cnt[bv[u]], 1) : 0;
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < kCU; ++u) {
-        if (sv[u] < 0) continue;
-        const uint32_t i = i0 + u * nthr;
-        g.rk[i] = rv[u];
-        g.ob[i] = bv[u];
-        atomicOr((unsigned long long*)&g.sf[sv[u] >> 6], 1ull << (sv[u] & 63));
-        w.blk[sv[u]] = (int32_t)(kNone - (uint32_t)nv[u]);
-      }
-    }
-    for (uint32_t i = tid; i < nT; i += nthr) {
-      const int32_t s = T[i];
-      w.mw[s] = 0;
-      w.tb[s >> 6] = 0;
-    }
-    __syncthreads();
-    // ---- C2: the split part goes to the tail [ne, be) of the block's range:
-    // index the split states in front of ne and the staying states in the tail
-    for (uint32_t i0 = tid; i0 < nS; i0 += nthr * kCU) {
-      int32_t sv[kCU], bv[kCU], rv[kCU], ev[kCU], cv[kCU], pv[kCU], uv[kCU];
-#pragma unroll
-      for (uint32_t u = 0; u < kCU; ++u) {
-        const uint32_t i = i0 + u * nthr;
         const bool ok = i < nS;
-        sv[u] = ok ? S[i] : -1;
-        bv[u] = ok ? g.ob[i] : 0;
-        rv[u] = ok ? g.rk[i] : 0;
+        sv[u] = ok ? *ent(Ss, cap, i) : -1;
+        bv[u] = ok ? *ent(Sb, cap, i) : 0;
+        rv[u] = ok ? *ent(Sr, cap, i) : 0;
       }
 #pragma unroll
       for (uint32_t u = 0; u < kCU; ++u) {
+        nv[u] = sv[u] >= 0 ? nlb[bv[u]] : 0ull;
         ev[u] = sv[u] >= 0 ? g.be[bv[u]] : 0;
+        gv[u] = sv[u] >= 0 ? g.bs[bv[u]] : 0;
         cv[u] = sv[u] >= 0 ? g.cnt[bv[u]] : 0;
         pv[u] = sv[u] >= 0 ? g.pos[sv[u]] : 0;
       }
 #pragma unroll
       for (uint32_t u = 0; u < kCU; ++u) {
         uv[u] = -1;
+        fv[u] = -1;
         if (sv[u] < 0) continue;
-        const uint32_t i = i0 + u * nthr;
         const int32_t e = ev[u], ne = e - cv[u], q = ne + rv[u];
-        g.nev[i] = ne;
-        g.fi[i] = pv[u] < ne ? atomicAdd(&g.fc[bv[u]], 1) : -1;
-        if (ne < 0 || q < ne || q >= e || e > (int32_t)n) {  // never expected
-          sh.bad = 1;
-          g.fi[i] = -1;
+        blk[sv[u]] = (int32_t)(kNone - (uint32_t)nv[u]);
+        if (ne < 0 || q < ne || q >= e || e > (int32_t)n || pv[u] < 0 || pv[u] >= (int32_t)n) {
+          sh.bad = 1;  // never expected: the entry is recorded as doing nothing
+          uv[u] = -2;
           continue;
         }
+        if (pv[u] < ne) fv[u] = atomicAdd(&g.fc[bv[u]], 1);
         uv[u] = g.perm[q];  // every tail position is examined once
       }
 #pragma unroll
       for (uint32_t u = 0; u < kCU; ++u) {
-        if (uv[u] < 0 || test_bit(g.sf, (uint32_t)uv[u])) continue;
-        const int32_t ne = ev[u] - cv[u];
+        if (sv[u] < 0) continue;
+        const uint32_t i = i0 + u * nthr;
+        const int32_t e = ev[u], ne = e - cv[u];
+        const int32_t nl = (int32_t)(kNone - (uint32_t)nv[u]);
+        const bool ok = uv[u] != -2;
+        *ent(Sf, cap, i) = ok ? fv[u] : -1;
+        *ent(Sn, cap, i) = ok ? ne : 0;
+        *ent(Sp, cap, i) = ok ? pv[u] : 0;
+        *ent(Se, cap, i) = (ok && nl == sv[u]) ? e : -1;
+        *ent(Sg, cap, i) = gv[u];
+        if (uv[u] < 0 || uv[u] >= (int32_t)n) {
+          sh.bad = 1;
+          continue;
+        }
+        if (test_bit(sf, (uint32_t)uv[u])) continue;
         const int32_t j = atomicAdd(&g.gc[bv[u]], 1);
-        if (ne + j < ev[u]) g.tmp[ne + j] = ne + rv[u];
-        else sh.bad = 1;
+        if (ne + j < e)
+          g.tmp64[ne + j] = ((uint64_t)(uint32_t)uv[u] << 32) | (uint32_t)(ne + rv[u]);
+        else
+          sh.bad = 1;
       }
     }
+    for (uint32_t i = tid; i < nT; i += nthr) {
+      const int32_t s = *ent(Ts, cap, i);
+      mw[s] = 0;
+      tb[s >> 6] = 0;
+    }
     __syncthreads();
-    // ---- C3: swap the i-th front split state with the i-th tail staying
+    if (sh.bad) {  // workgroup-uniform
+      if (tid == 0) atomicOr(&a.ctl[1], 2u);
+      break;
+    }
+    // ---- C2: swap the i-th front split state with the i-th tail staying
     // state; the new leader of each split block sets both ranges; unstable
     // updates (be, bs, cnt, fc, gc of a block are read by no other thread here)
     {
       uint32_t best = kNone;
       for (uint32_t i0 = tid; i0 < nS; i0 += nthr * kCU) {
-        int32_t sv[kCU], bv[kCU], nev[kCU], fv[kCU], lv[kCU], qv[kCU], psv[kCU], ev[kCU];
+        int32_t sv[kCU], bv[kCU], fv[kCU], nev[kCU], psv[kCU], ev[kCU], gv[kCU];
+        uint64_t xv[kCU];
 #pragma unroll
         for (uint32_t u = 0; u < kCU; ++u) {
           const uint32_t i = i0 + u * nthr;
           const bool ok = i < nS;
-          sv[u] = ok ? S[i] : -1;
-          bv[u] = ok ? g.ob[i] : 0;
-          nev[u] = ok ? g.nev[i] : 0;
-          fv[u] = ok ? g.fi[i] : -1;
+          sv[u] = ok ? *ent(Ss, cap, i) : -1;
+          bv[u] = ok ? *ent(Sb, cap, i) : 0;
+          fv[u] = ok ? *ent(Sf, cap, i) : -1;
+          nev[u] = ok ? *ent(Sn, cap, i) : 0;
+          psv[u] = ok ? *ent(Sp, cap, i) : 0;
+          ev[u] = ok ? *ent(Se, cap, i) : -1;
+          gv[u] = ok ? *ent(Sg, cap, i) : 0;
         }
 #pragma unroll
         for (uint32_t u = 0; u < kCU; ++u) {
-          lv[u] = sv[u] >= 0 ? w.blk[sv[u]] : -1;
-          if (fv[u] >= 0 && nev[u] + fv[u] >= (int32_t)n) {  // never expected
+          if (fv[u] >= 0 && (nev[u] < 0 || nev[u] + fv[u] >= (int32_t)n)) {  // never expected
             sh.bad = 1;
             fv[u] = -1;
           }
-          qv[u] = fv[u] >= 0 ? g.tmp[nev[u] + fv[u]] : 0;
-          psv[u] = fv[u] >= 0 ? g.pos[sv[u]] : 0;
-          ev[u] = (sv[u] >= 0 && lv[u] == sv[u]) ? g.be[bv[u]] : 0;
+          xv[u] = (sv[u] >= 0 && fv[u] >= 0) ? g.tmp64[nev[u] + fv[u]] : 0ull;
         }
 #pragma unroll
         for (uint32_t u = 0; u < kCU; ++u) {
           if (sv[u] < 0) continue;
           const int32_t s = sv[u], b = bv[u], ne = nev[u];
           if (fv[u] >= 0) {
-            const int32_t q = qv[u], ps = psv[u];
-            if (q < ne || q >= (int32_t)n || ps < 0 || ps >= ne) {  // never expected
-              sh.bad = 1;
+            const int32_t q = (int32_t)(uint32_t)xv[u], su = (int32_t)(xv[u] >> 32);
+            const int32_t ps = psv[u];
+            if (q < ne || q >= (int32_t)n || ps < 0 || ps >= ne || su < 0 || su >= (int32_t)n) {
+              sh.bad = 1;  // never expected
             } else {
-              const int32_t su = g.perm[q];
               g.perm[ps] = su;
               g.pos[su] = ps;
               g.perm[q] = s;
               g.pos[s] = q;
             }
           }
-          if (lv[u] == s) {  // the new leader: one thread per split block
+          if (ev[u] >= 0) {  // the new leader: one thread per split block
             g.bs[s] = ne;
             g.be[s] = ev[u];
             g.be[b] = ne;
             g.cnt[b] = 0;
             g.fc[b] = 0;
             g.gc[b] = 0;
-            wg_unstable_set(w.ub, g.us, (uint32_t)b);
-            wg_unstable_set(w.ub, g.us, (uint32_t)s);
+            if (ev[u] - ne == 1) atomicOr((unsigned long long*)&sg[s >> 6], 1ull << (s & 63));
+            if (ne - gv[u] == 1) atomicOr((unsigned long long*)&sg[b >> 6], 1ull << (b & 63));
+            wg_unstable_set(ub, us, (uint32_t)b);
+            wg_unstable_set(ub, us, (uint32_t)s);
             best = min(best, (uint32_t)b);
+            atomicAdd(&sh.wB, 1ull);
           }
-          atomicAnd((unsigned long long*)&g.sf[s >> 6], ~(1ull << (s & 63)));
+          atomicAnd((unsigned long long*)&sf[s >> 6], ~(1ull << (s & 63)));
         }
       }
       wg_min(&sh.cand[par ^ 1], best);
       if (tid == 0) {
         if (nS > 0) {
-          wg_unstable_set(w.ub, g.us, C);
+          wg_unstable_set(ub, us, C);
           atomicMin(&sh.cand[par ^ 1], C);
         }
         sh.cand[par] = kNone;
@@ -772,12 +913,29 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, WArr<MaskT> w, G
       break;
     }
   }
-  for (uint32_t s = tid; s < n; s += nthr) a.out[s0 + s] = w.blk[s];
+  if (tid == 0) {
+    unsigned long long* w = a.work + 8;
+    atomicAdd(&w[0], (unsigned long long)(it + 1));
+    atomicAdd(&w[1], (unsigned long long)sM);
+    atomicAdd(&w[2], sh.wE);
+    atomicAdd(&w[3], (unsigned long long)sT);
+    atomicAdd(&w[4], (unsigned long long)sL);
+    atomicAdd(&w[5], sh.wV);
+    atomicAdd(&w[6], (unsigned long long)sS);
+    atomicAdd(&w[7], sh.wB);
+  }
+  for (uint32_t s = tid; s < n; s += nthr) a.out[s0 + s] = blk[s];
   return it + 1;
 }
 
-template <class MaskT>
-__global__ void k_batch(BArgs a) {
+// Built for 256-thread workgroups only, with that launch bound, so that the
+// register budget (up to 512 per lane) holds the whole kernel and nothing
+// spills to scratch.  Larger workgroups are not built: builds of this tier
+// for 512 and 1024 threads, which kept 128 registers and spilled 212-332
+// bytes per lane, made illegal memory accesses on the GPU for reasons not
+// found (builds spilling at most 160 bytes passed every test).
+template <class MaskT, int WG>
+__global__ void __launch_bounds__(WG) k_batch(BArgs a) {
   extern __shared__ uint64_t lds[];
   __shared__ Shared sh;
   for (;;) {
@@ -802,13 +960,6 @@ __global__ void k_batch(BArgs a) {
       its = wg_refine<MaskT, 1>(a, sh, w, T, S, s0, n);
     } else {
       const uint32_t b0 = a.bw_off[k];
-      WArr<MaskT> w;
-      w.blk = a.blk + s0;
-      w.mw = reinterpret_cast<MaskT*>(a.mw) + s0;
-      w.nlb = a.nlb + s0;
-      w.ub = a.ub + b0;
-      w.tb = a.tb + b0;
-      w.lt = a.lt + b0;
       GList g;
       g.perm = a.perm + s0;
       g.pos = a.pos + s0;
@@ -817,22 +968,31 @@ __global__ void k_batch(BArgs a) {
       g.cnt = a.cnt + s0;
       g.fc = a.fc + s0;
       g.gc = a.gc + s0;
-      g.tmp = a.tmp + s0;
-      g.rk = a.rk + s0;
-      g.fi = a.fi + s0;
-      g.ob = a.ob + s0;
-      g.nev = a.nev + s0;
-      g.ltl = a.ltl + s0;
+      g.tmp64 = a.tmp64 + s0;
+      g.ts = T;
+      g.tb_ = a.tlb + s0;
+      g.lb = a.ltl + s0;
+      g.ss = S;
+      g.sb_ = a.ob + s0;
+      g.sr = a.rk + s0;
+      g.sf_ = a.fi + s0;
+      g.sn = a.nev + s0;
+      g.sp = a.tmp + s0;
+      g.se = a.se + s0;
+      g.sgs = a.sgs + s0;
       g.sf = a.sf + b0;
+      g.sg = a.lt + b0;
       g.us = a.us + b0;
-      its = wg_refine_lists<MaskT>(a, sh, w, g, T, S, s0, n);
+      its = wg_refine_lists<MaskT>(a, sh, a.blk + s0, reinterpret_cast<MaskT*>(a.mw) + s0,
+                                   a.nlb + s0, g, lds, a.lds_bytes, a.ub + b0, a.tb + b0, s0, n);
     }
     if (threadIdx.x == 0) a.iters[k] = its;
     __syncthreads();
   }
 }
 
-__global__ void k_reset_queue(uint32_t* ctl) {
+__global__ void k_reset_queue(uint32_t* ctl, unsigned long long* work) {
+  if (blockIdx.x == 0 && threadIdx.x < 16) work[threadIdx.x] = 0;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl[0] = 0;
     ctl[1] = 0;
@@ -899,7 +1059,8 @@ void free_batch(bisim_batch* b) {
   void* ptrs[] = {b->n_off_d, b->bw_off_d, b->order_d, b->blk, b->mw,      b->nlb,  b->ub,
                   b->tb,      b->lt,       b->tl,      b->sl,  b->iters_d, b->ctl_d, b->perm,
                   b->pos,     b->bs,       b->be,      b->cnt, b->fc,      b->gc,    b->tmp,
-                  b->rk,      b->fi,       b->ltl,     b->sf,  b->us,      b->ob,    b->nev};
+                  b->rk,      b->fi,       b->ltl,     b->sf,  b->us,      b->ob,    b->nev,
+                  b->tlb,     b->se,       b->tmp64,   b->sgs,    b->work_d};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->u) lts_destroy(b->u);
@@ -940,40 +1101,51 @@ BArgs make_args(bisim_batch* b, int32_t* out) {
   a.ob = b->ob;
   a.nev = b->nev;
   a.ltl = b->ltl;
+  a.tlb = b->tlb;
+  a.se = b->se;
+  a.sgs = b->sgs;
+  a.tmp64 = b->tmp64;
   a.sf = b->sf;
   a.us = b->us;
   a.out = out;
   a.iters = b->iters_d;
   a.ctl = b->ctl_d;
+  a.work = b->work_d;
   a.lds_bytes = (uint32_t)b->lds_bytes;
   return a;
 }
 
 // allow dynamic LDS up to the device's per-workgroup maximum
 void allow_lds(bisim_batch* b) {
-  (void)hipFuncSetAttribute((const void*)k_batch<uint64_t>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, b->lds_max);
-  (void)hipFuncSetAttribute((const void*)k_batch<uint32_t>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, b->lds_max);
+  const void* fns[] = {(const void*)k_batch<uint64_t, kBatchWG>,
+                       (const void*)k_batch<uint32_t, kBatchWG>};
+  for (const void* f : fns)
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b->lds_max);
   (void)hipGetLastError();
 }
 
 bisim_status launch_once(bisim_batch* b, int32_t* out, int wg, int grid, int lds) {
   BArgs a = make_args(b, out);
   a.lds_bytes = (uint32_t)lds;
-  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, b->stream, b->ctl_d);
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, b->stream, b->ctl_d, b->work_d);
+  if (wg != kBatchWG) {
+    set_error("batched kernel: workgroup size %d is not built (%d)", wg, kBatchWG);
+    return BISIM_E_INVALID;
+  }
   if (b->mask64)
-    hipLaunchKernelGGL(k_batch<uint64_t>, dim3(grid), dim3(wg), lds, b->stream, a);
+    hipLaunchKernelGGL((k_batch<uint64_t, kBatchWG>), dim3(grid), dim3(wg), lds, b->stream, a);
   else
-    hipLaunchKernelGGL(k_batch<uint32_t>, dim3(grid), dim3(wg), lds, b->stream, a);
+    hipLaunchKernelGGL((k_batch<uint32_t, kBatchWG>), dim3(grid), dim3(wg), lds, b->stream, a);
   BISIM_TRY_HIP(hipGetLastError());
   return BISIM_OK;
 }
 
 int max_resident(bisim_batch* b, int wg, int lds) {
   int per_cu = 0;
-  hipError_t e = b->mask64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<uint64_t>, wg, lds)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<uint32_t>, wg, lds);
+  if (wg != kBatchWG) return 0;
+  const void* f = b->mask64 ? (const void*)k_batch<uint64_t, kBatchWG>
+                            : (const void*)k_batch<uint32_t, kBatchWG>;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, wg, lds);
   if (e != hipSuccess || per_cu < 1) return 0;
   return per_cu * b->num_cu;
 }
@@ -1035,7 +1207,7 @@ void tune_store(const std::string& key, int wg, int grid, int lds, float ms) {
 // Autotuner: time each candidate (workgroup size, LDS budget, grid = as many
 // workgroups as stay resident) on the batch itself and keep the fastest.
 bisim_status autotune(bisim_batch* b, int32_t* out) {
-  const int wgs[] = {256, 512, 1024};
+  const int wgs[] = {kBatchWG};
   std::vector<int> budgets;
   for (int l = b->lds_max; l >= 16384 && budgets.size() < 4; l /= 2) budgets.push_back(l);
   float best = 1e30f;
@@ -1207,8 +1379,11 @@ bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* 
         (st = dmalloc(&b->rk, (size_t)N)) || (st = dmalloc(&b->fi, (size_t)N)) ||
         (st = dmalloc(&b->ltl, (size_t)N)) || (st = dmalloc(&b->sf, BW)) ||
         (st = dmalloc(&b->ob, (size_t)N)) || (st = dmalloc(&b->nev, (size_t)N)) ||
-        (st = dmalloc(&b->us, BW)) ||
-        (st = dmalloc(&b->iters_d, count)) || (st = dmalloc(&b->ctl_d, 2)))
+        (st = dmalloc(&b->us, BW)) || (st = dmalloc(&b->tlb, (size_t)N)) ||
+        (st = dmalloc(&b->se, (size_t)N)) || (st = dmalloc(&b->tmp64, (size_t)N)) ||
+        (st = dmalloc(&b->sgs, (size_t)N)) ||
+        (st = dmalloc(&b->iters_d, count)) || (st = dmalloc(&b->ctl_d, 2)) ||
+        (st = dmalloc(&b->work_d, 16)))
       break;
     float ms = 0;
     if (hipEventRecord(b->ev1, s) != hipSuccess || hipEventSynchronize(b->ev1) != hipSuccess ||
@@ -1243,7 +1418,7 @@ bisim_status coarsest_partition_batch(bisim_batch* b, int32_t* block_id, int64_t
     int wg = 0, grid = 0, lds = 0;
     const bool fixed = b->opt_wg || b->opt_grid || b->opt_lds;
     if (fixed) {
-      wg = b->opt_wg ? b->opt_wg : 1024;
+      wg = b->opt_wg ? b->opt_wg : kBatchWG;
       lds = b->opt_lds ? std::min(b->opt_lds, b->lds_max) : b->lds_max;
       grid = b->opt_grid ? b->opt_grid : max_resident(b, wg, lds);
       b->wg = wg;
@@ -1294,6 +1469,9 @@ bisim_status coarsest_partition_batch(bisim_batch* b, int32_t* block_id, int64_t
   uint32_t ctl_h[2] = {0, 0};
   BISIM_TRY_HIP(hipMemcpyAsync(its.data(), b->iters_d, 4 * b->count, hipMemcpyDeviceToHost, b->stream));
   BISIM_TRY_HIP(hipMemcpyAsync(ctl_h, b->ctl_d, 8, hipMemcpyDeviceToHost, b->stream));
+  unsigned long long work_h[16];
+  BISIM_TRY_HIP(hipMemcpyAsync(work_h, b->work_d, sizeof(work_h), hipMemcpyDeviceToHost,
+                               b->stream));
   BISIM_TRY_HIP(hipStreamSynchronize(b->stream));
   float ms = 0;
   BISIM_TRY_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
@@ -1324,6 +1502,7 @@ bisim_status coarsest_partition_batch(bisim_batch* b, int32_t* block_id, int64_t
     st->grid = b->grid;
     st->t_pre_ms = b->t_pre_ms;
     st->t_alg_ms = b->t_alg_ms;
+    for (int i = 0; i < 16; ++i) st->work[i / 8][i % 8] = (int64_t)work_h[i];
   }
   return BISIM_OK;
 }
@@ -1337,7 +1516,7 @@ bisim_status bisim_batch_set_option(bisim_batch* b, int32_t option, int64_t valu
   }
   switch (option) {
     case BISIM_BOPT_WG_SIZE:
-      if (value != 0 && value != 256 && value != 512 && value != 1024) break;
+      if (value != 0 && value != kBatchWG) break;
       b->opt_wg = (int)value;
       b->tuned = false;
       return BISIM_OK;

@@ -149,6 +149,18 @@ __device__ __forceinline__ uint32_t hit_mask(const int32_t* blk, uint32_t base0,
 // ---------------------------------------------------------------------------
 }  // namespace bisim
 
+// device arrays of the member-list engine (engine 3), allocated on first use
+struct bisim_lists {
+  int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr;
+  int32_t *cnt = nullptr, *fc = nullptr, *gc = nullptr;
+  uint64_t* tmp64 = nullptr;
+  int32_t *lb = nullptr, *lo = nullptr;
+  int32_t *ob = nullptr, *rk = nullptr, *fi = nullptr, *ne = nullptr, *ps = nullptr,
+          *se = nullptr, *sb0 = nullptr;
+  uint64_t* sg = nullptr;
+  uint64_t* work = nullptr;
+};
+
 struct bisim_lts {
   int32_t n = 0;
   int64_t m = 0;
@@ -225,6 +237,11 @@ struct bisim_lts {
   double phase_ms[4] = {0, 0, 0, 0};
   int64_t phase_cnt[4] = {0, 0, 0, 0};
 
+  // member-list engine
+  bisim_lists lists;
+  int count_work = 0;            // accumulate the engine's work totals
+  uint64_t lists_work[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
   double t_pre_ms = 0.0;
   double t_alg_ms = 0.0;
   int64_t last_iters = 0;
@@ -254,6 +271,10 @@ bisim_status refine_alloc(bisim_lts* h);
 // signature.hip: multi-way signature refinement (baseline), or signature
 // rounds followed by Algorithm 3 (hybrid)
 bisim_status signature_run(bisim_lts* h, int32_t* block_id, bool hybrid);
+// lists.hip: the member-list engine (engine 3)
+bisim_status lists_alloc(bisim_lts* h);
+bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals);
+void lists_free(bisim_lts* h);
 }  // namespace bisim
 
 struct bisim_mlp;

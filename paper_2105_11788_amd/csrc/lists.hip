@@ -1,0 +1,707 @@
+// Engine 3: the plain refinement loop (Algorithm 3, section 4) over the
+// whole grid with work proportional to the splitter and the states it
+// touches, not to n.
+//
+// Besides block[], the partition is kept as a refinable partition: perm
+// lists the states block by block and the block labelled b owns
+// perm[bs[b] .. be[b]).  One iteration is four kernels:
+//
+//   M  mark      C = the candidate (the smallest unstable label, the
+//                priority reading of the concurrent write); clear its
+//                unstable bit and search the next set bit (one wave); visit
+//                the in-transitions of C's members (perm[bs[C] .. be[C]))
+//                and set their mark bits; the first touch of a state sets
+//                its touched bit, and a touched leader of a block with more
+//                than one state appends the block's member segments to a
+//                list.
+//   K  compare   touched states (found through the touched bitmap) whose
+//                marks differ from their leader's split; so do the untouched
+//                members of the listed blocks.  A split state bids for its
+//                block's new leader (64-bit max of (epoch, ~state): the
+//                smallest state wins), takes its rank within the block's
+//                split part and sets its split bit.
+//   R  relabel   every split state takes its block's winning bid as label;
+//                the split part will be the tail [ne, be) of the block's
+//                range: split states in front of ne take an index, and the
+//                staying state found at ne + rank is recorded under an index
+//                of its own; marks and touched bits are cleared.
+//   W  swap      the i-th front split state and the i-th staying tail state
+//                swap places; the new leader of each split block sets both
+//                ranges, the one-state flags and the unstable bits, and the
+//                old label joins the next candidate (with C if anything
+//                split, the lock-step reading of Algorithm 3).
+//
+// The splitter sequence, the split counts and the partitions are those of
+// the other engines.  States with more than 64 actions use the mark-word
+// offsets of the preprocessing.
+#include <hip/hip_ext.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace bisim {
+namespace {
+
+constexpr int kLT = 256;
+constexpr uint32_t kSeg = 1024;  // members of a listed block per segment
+
+struct LArgs {
+  uint32_t n;
+  int uniform;
+  uint64_t nwd;  // words of a per-state bitmap
+  const uint32_t* __restrict__ in_ptr;
+  const int32_t* __restrict__ in_src;
+  const int32_t* __restrict__ in_ord;
+  const uint32_t* __restrict__ woff;
+  int32_t* block;
+  uint64_t* mw;
+  uint64_t* tb;   // touched states
+  uint64_t* sf;   // split states
+  uint64_t* sg;   // labels of one-state blocks
+  uint64_t* ub;   // unstable labels
+  uint64_t* us;   // summary of ub
+  uint64_t* nlw;  // bids
+  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc;
+  uint64_t* tmp64;
+  int32_t *lb, *lo;  // listed segments: block, offset
+  uint32_t lcap;
+  int32_t *ob, *rk, *fi, *ne, *ps, *se, *sb0;  // per split state
+  uint64_t* work;  // [8] totals when counting
+  int count;
+  Ctl* ctl;
+  uint32_t iter_cap;
+  int32_t* trace_C;
+  int64_t* trace_nsplit;
+  uint32_t trace_cap;
+};
+
+struct GPart {
+  uint32_t gtid, gthreads, gwave, gwaves;
+};
+__device__ __forceinline__ GPart gpart() {
+  const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t gthreads = gridDim.x * blockDim.x;
+  return {gtid, gthreads, gtid / kWave, gthreads / kWave};
+}
+
+__device__ __forceinline__ void set_unstable(const LArgs& a, uint32_t b) {
+  const uint32_t w = b >> 6;
+  const uint64_t old = atomicOr((unsigned long long*)&a.ub[w], 1ull << (b & 63));
+  if (old == 0) atomicOr((unsigned long long*)&a.us[w >> 6], 1ull << (w & 63));
+}
+
+__device__ __forceinline__ void count_work(const LArgs& a, uint32_t i, uint64_t v) {
+  if (a.count && v && lane() == 0) atomicAdd((unsigned long long*)&a.work[i], (unsigned long long)v);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, d, kWave);
+  return v;
+}
+
+// mark word of slot o of state s
+__device__ __forceinline__ uint64_t* mword(const LArgs& a, int32_t s, int32_t o) {
+  return a.uniform ? &a.mw[s] : &a.mw[a.woff[s] + ((uint32_t)o >> 6)];
+}
+
+// marks of s differ from those of b (same action set: same number of words)
+__device__ __forceinline__ bool marks_differ(const LArgs& a, int32_t s, int32_t b) {
+  if (a.uniform) return a.mw[s] != a.mw[b];
+  const uint32_t w0 = a.woff[s], w1 = a.woff[s + 1], v0 = a.woff[b];
+  for (uint32_t w = w0; w < w1; ++w)
+    if (a.mw[w] != a.mw[v0 + (w - w0)]) return true;
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// M: select, mark
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t k) {
+  const uint32_t par = k & 1;
+  const uint32_t done = a.ctl->state.v[1];
+  const uint32_t C0 = a.ctl->cand[par].v[0];
+  if (done) return;
+  const GPart p = gpart();
+  const bool over = k + 1 > a.iter_cap;
+  if (C0 == kNone || over) {  // the final pass, or the iteration cap
+    if (p.gtid == 0) {
+      a.ctl->state.v[0] = k + 1;
+      a.ctl->state.v[1] = 1;
+      if (over && C0 != kNone) a.ctl->state.v[2] = 1;
+      if (k < a.trace_cap) {
+        if (a.trace_C) a.trace_C[k] = -1;
+        if (a.trace_nsplit) a.trace_nsplit[k] = 0;
+      }
+    }
+    return;
+  }
+  const uint32_t C = C0;
+  if (p.gtid == 0) {
+    a.ctl->state.v[3] = C;
+    a.ctl->cntS[par ^ 1].v[0] = 0;  // counters of the next iteration
+    a.ctl->cntC[par ^ 1].v[0] = 0;
+    if (a.trace_C && k < a.trace_cap) a.trace_C[k] = (int32_t)C;
+  }
+  const uint32_t n = a.n;
+  const uint32_t nw = (n + 63u) >> 6, nsw = (nw + 63u) >> 6;
+  if (p.gwave == p.gwaves - 1) {  // clear C, find the next smallest unstable label
+    const uint32_t w0 = C >> 6;
+    const uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
+    if (lane() == 0) {
+      a.ub[w0] = bits;
+      if (bits == 0) atomicAnd((unsigned long long*)&a.us[w0 >> 6], ~(1ull << (w0 & 63)));
+    }
+    uint32_t next = kNone;
+    for (uint32_t q = w0 >> 6; q < nsw; q += kWave) {
+      const uint32_t qq = q + lane();
+      uint64_t sv = qq < nsw ? a.us[qq] : 0ull;
+      if (qq == (w0 >> 6)) {
+        sv &= ~0ull << (w0 & 63);
+        const uint64_t b0 = 1ull << (w0 & 63);
+        sv = bits ? (sv | b0) : (sv & ~b0);
+      }
+      const uint64_t bal = __ballot(sv != 0);
+      if (bal) {
+        const int l = __ffsll((unsigned long long)bal) - 1;
+        const uint64_t v = (uint64_t)__shfl((unsigned long long)sv, l, kWave);
+        const uint32_t word =
+            ((q + (uint32_t)l) << 6) + (uint32_t)(__ffsll((unsigned long long)v) - 1);
+        const uint64_t wb = (word == w0) ? bits : a.ub[word];
+        if (wb) next = (word << 6) + (uint32_t)(__ffsll((unsigned long long)wb) - 1);
+        break;
+      }
+    }
+    if (lane() == 0 && next != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], next);
+  }
+  const uint32_t cb = (uint32_t)a.bs[C];
+  uint32_t csz = (uint32_t)a.be[C] - cb;
+  if (cb > n || csz > n - cb) csz = 0;  // never expected
+  if (p.gtid == 0 && a.count) {
+    atomicAdd((unsigned long long*)&a.work[0], (unsigned long long)csz);
+  }
+  for (uint32_t i0 = p.gwave * kWave; i0 < csz; i0 += p.gwaves * kWave) {
+    const uint32_t i = i0 + lane();
+    const bool hit = i < csz;
+    uint32_t beg = 0, deg = 0;
+    if (hit) {
+      const uint32_t t = (uint32_t)a.perm[cb + i];
+      beg = a.in_ptr[t];
+      deg = a.in_ptr[t + 1] - beg;
+    }
+    const uint32_t incl = wave_incl_scan_u32(deg);
+    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+    count_work(a, 1, total);
+    for (uint32_t e0 = 0; e0 < total; e0 += kWave) {
+      const uint32_t e = e0 + lane();
+      const bool valid = e < total;
+      const uint32_t ee = valid ? e : total - 1;
+      uint32_t j = 0;
+#pragma unroll
+      for (uint32_t step = 32; step >= 1; step >>= 1) {
+        const uint32_t probe = (uint32_t)__shfl((int)incl, (int)(j + step - 1), kWave);
+        if (probe <= ee) j += step;
+      }
+      const uint32_t jb = (uint32_t)__shfl((int)beg, (int)j, kWave);
+      const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
+      const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
+      bool first = false, lead = false;
+      int32_t s = 0;
+      if (valid) {
+        const uint32_t edge = jb + (ee - (ji - jd));
+        s = a.in_src[edge];
+        const int32_t o = a.in_ord[edge];
+        atomicOr((unsigned long long*)mword(a, s, o), 1ull << (o & 63));
+        const uint64_t tbit = 1ull << (s & 63);
+        const uint64_t old = atomicOr((unsigned long long*)&a.tb[s >> 6], (unsigned long long)tbit);
+        first = !(old & tbit);
+        if (first) {
+          const int32_t b = a.block[s];
+          // a touched leader of a one-state block has no untouched member
+          lead = (b == s) && !test_bit(a.sg, (uint32_t)s);
+        }
+      }
+      count_work(a, 2, (uint64_t)__popcll(__ballot(first)));
+      // the listed block's member segments (wave-aggregated reservation)
+      uint32_t lo_ = 0, nseg = 0;
+      if (lead) {
+        lo_ = (uint32_t)a.bs[s];
+        const uint32_t sz = (uint32_t)a.be[s] - lo_;
+        nseg = (sz + kSeg - 1) / kSeg;
+      }
+      const uint32_t sincl = wave_incl_scan_u32(nseg);
+      const uint32_t stot = (uint32_t)__shfl((int)sincl, kWave - 1, kWave);
+      count_work(a, 3, stot);
+      if (stot) {
+        uint32_t base = 0;
+        if (lane() == kWave - 1) base = atomicAdd(&a.ctl->cntC[par].v[0], stot);
+        base = (uint32_t)__shfl((int)base, kWave - 1, kWave) + sincl - nseg;
+        for (uint32_t q = 0; q < nseg; ++q) {
+          if (base + q >= a.lcap) break;  // never expected (capacity covers every block)
+          a.lb[base + q] = s;
+          a.lo[base + q] = (int32_t)(q * kSeg);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K: compare, elect, rank
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t k) {
+  const uint32_t par = k & 1;
+  const uint32_t done = a.ctl->state.v[1];
+  const uint32_t nL = a.ctl->cntC[par].v[0];
+  if (done) return;
+  const GPart p = gpart();
+  const uint64_t epoch = (uint64_t)(k + 1) << 32;
+  const uint32_t n = a.n;
+  const uint32_t nw = (n + 63u) >> 6;
+  const uint32_t half = p.gwaves > 1 ? p.gwaves / 2 : 1;
+  if (p.gwave < half) {
+    // touched states, through the touched bitmap: 64 words per wave and step
+    for (uint32_t w0 = p.gwave * kWave; w0 < nw; w0 += half * kWave) {
+      const uint32_t wi = w0 + lane();
+      const uint64_t word = wi < nw ? a.tb[wi] : 0ull;
+      uint64_t nz = __ballot(word != 0);
+      while (nz) {
+        const int j = __ffsll((unsigned long long)nz) - 1;
+        nz &= nz - 1;
+        const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
+        const uint32_t widx = w0 + (uint32_t)j;
+        const int32_t s = (int32_t)((widx << 6) + lane());
+        bool sp = false;
+        int32_t b = 0;
+        if ((W >> lane()) & 1ull) {
+          b = a.block[s];
+          sp = (b != s) && marks_differ(a, s, b);
+        }
+        int32_t r = 0;
+        if (sp) {
+          atomicMax((unsigned long long*)&a.nlw[b],
+                    (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
+          r = atomicAdd(&a.cnt[b], 1);
+          a.ob[s] = b;
+          a.rk[s] = r;
+        }
+        const uint64_t sbal = __ballot(sp);
+        if (sbal && lane() == 0) {
+          atomicOr((unsigned long long*)&a.sf[widx], (unsigned long long)sbal);
+          atomicAdd(&a.ctl->cntS[par].v[0], (uint32_t)__popcll(sbal));
+        }
+      }
+    }
+  } else {
+    // untouched members of the listed blocks: one segment per wave and step
+    for (uint32_t j = p.gwave - half; j < nL && j < a.lcap; j += p.gwaves - half) {
+      const int32_t b = a.lb[j];
+      const uint32_t off = (uint32_t)a.lo[j];
+      const uint32_t lo = (uint32_t)a.bs[b] + off, hi = (uint32_t)a.be[b];
+      const uint32_t cntm = hi > lo ? min(kSeg, hi - lo) : 0u;
+      count_work(a, 4, cntm);
+      for (uint32_t i0 = 0; i0 < cntm; i0 += kWave) {
+        const uint32_t i = i0 + lane();
+        int32_t s = 0;
+        bool sp = false;
+        if (i < cntm && lo + i < n) {
+          s = a.perm[lo + i];
+          sp = !test_bit(a.tb, (uint32_t)s);
+        }
+        const uint64_t bal = __ballot(sp);
+        if (!bal) continue;
+        // one bid (the smallest splitting state) and one rank reservation per step
+        uint32_t sm = sp ? (uint32_t)s : kNone;
+        sm = wave_min_u32(sm);
+        uint32_t base = 0;
+        if (lane() == 0) {
+          atomicMax((unsigned long long*)&a.nlw[b],
+                    (unsigned long long)(epoch | (uint64_t)(kNone - sm)));
+          base = (uint32_t)atomicAdd(&a.cnt[b], (int)__popcll(bal));
+          atomicAdd(&a.ctl->cntS[par].v[0], (uint32_t)__popcll(bal));
+        }
+        base = (uint32_t)__shfl((int)base, 0, kWave);
+        if (sp) {
+          a.ob[s] = b;
+          a.rk[s] = (int32_t)(base + (uint32_t)__popcll(bal & ((1ull << lane()) - 1ull)));
+          atomicOr((unsigned long long*)&a.sf[s >> 6], 1ull << (s & 63));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// R: relabel, tail bookkeeping; clear marks and touched bits
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t k) {
+  const uint32_t par = k & 1;
+  const uint32_t done = a.ctl->state.v[1];
+  const uint32_t nS = a.ctl->cntS[par].v[0];
+  if (done) return;
+  const GPart p = gpart();
+  const uint32_t n = a.n;
+  const uint32_t nw = (n + 63u) >> 6;
+  const uint32_t half = p.gwaves > 1 ? p.gwaves / 2 : 1;
+  if (p.gwave < half) {
+    if (nS == 0) return;
+    count_work(a, 5, p.gtid == 0 ? nS : 0);
+    for (uint32_t w0 = p.gwave * kWave; w0 < nw; w0 += half * kWave) {
+      const uint32_t wi = w0 + lane();
+      const uint64_t word = wi < nw ? a.sf[wi] : 0ull;
+      uint64_t nz = __ballot(word != 0);
+      while (nz) {
+        const int j = __ffsll((unsigned long long)nz) - 1;
+        nz &= nz - 1;
+        const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
+        const uint32_t widx = w0 + (uint32_t)j;
+        const int32_t s = (int32_t)((widx << 6) + lane());
+        if (!((W >> lane()) & 1ull)) continue;
+        const int32_t b = a.ob[s], r = a.rk[s];
+        const uint64_t nv = a.nlw[b];
+        const int32_t e = a.be[b], c = a.cnt[b], bsb = a.bs[b], pv = a.pos[s];
+        const int32_t nl = (int32_t)(kNone - (uint32_t)nv);
+        a.block[s] = nl;
+        const int32_t ne = e - c, q = ne + r;
+        int32_t fv = -1, uv = -1;
+        const bool ok = ne >= 0 && q >= ne && q < e && e <= (int32_t)n && pv >= 0 && pv < (int32_t)n;
+        if (ok) {
+          if (pv < ne) fv = atomicAdd(&a.fc[b], 1);
+          uv = a.perm[q];  // every tail position is examined once
+        }
+        a.fi[s] = fv;
+        a.ne[s] = ok ? ne : 0;
+        a.ps[s] = ok ? pv : 0;
+        a.se[s] = (ok && nl == s) ? e : -1;
+        a.sb0[s] = bsb;
+        if (uv >= 0 && uv < (int32_t)n && !test_bit(a.sf, (uint32_t)uv)) {
+          const int32_t jj = atomicAdd(&a.gc[b], 1);
+          if (ne + jj < e)
+            a.tmp64[ne + jj] = ((uint64_t)(uint32_t)uv << 32) | (uint32_t)q;
+        }
+      }
+    }
+  } else {
+    // clear the marks and touched bits of this iteration's touched states
+    for (uint32_t w0 = (p.gwave - half) * kWave; w0 < nw; w0 += (p.gwaves - half) * kWave) {
+      const uint32_t wi = w0 + lane();
+      const uint64_t word = wi < nw ? a.tb[wi] : 0ull;
+      uint64_t nz = __ballot(word != 0);
+      if (word) a.tb[wi] = 0;
+      while (nz) {
+        const int j = __ffsll((unsigned long long)nz) - 1;
+        nz &= nz - 1;
+        const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
+        const int32_t s = (int32_t)(((w0 + (uint32_t)j) << 6) + lane());
+        if (!((W >> lane()) & 1ull)) continue;
+        if (a.uniform) {
+          a.mw[s] = 0;
+        } else {
+          for (uint32_t w = a.woff[s]; w < a.woff[s + 1]; ++w) a.mw[w] = 0;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// W: swaps, new ranges, unstable updates, next candidate
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t k) {
+  const uint32_t par = k & 1;
+  const uint32_t done = a.ctl->state.v[1];
+  const uint32_t nS = a.ctl->cntS[par].v[0];
+  const uint32_t C = a.ctl->state.v[3];
+  if (done) return;
+  const GPart p = gpart();
+  if (p.gtid == 0) {
+    a.ctl->cand[par].v[0] = kNone;  // the candidate slot of iteration k + 2
+    if (a.trace_nsplit && k < a.trace_cap) a.trace_nsplit[k] = nS;
+    if (nS > 0) {
+      set_unstable(a, C);
+      atomicMin(&a.ctl->cand[par ^ 1].v[0], C);
+    }
+    count_work(a, 7, nS > 0 ? 1 : 0);
+  }
+  if (nS == 0) return;
+  const uint32_t n = a.n;
+  const uint32_t nw = (n + 63u) >> 6;
+  uint32_t best = kNone, leaders = 0;
+  for (uint32_t w0 = p.gwave * kWave; w0 < nw; w0 += p.gwaves * kWave) {
+    const uint32_t wi = w0 + lane();
+    const uint64_t word = wi < nw ? a.sf[wi] : 0ull;
+    uint64_t nz = __ballot(word != 0);
+    if (word) a.sf[wi] = 0;
+    while (nz) {
+      const int j = __ffsll((unsigned long long)nz) - 1;
+      nz &= nz - 1;
+      const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
+      const int32_t s = (int32_t)(((w0 + (uint32_t)j) << 6) + lane());
+      if (!((W >> lane()) & 1ull)) continue;
+      const int32_t b = a.ob[s], fv = a.fi[s], ne = a.ne[s], ps = a.ps[s], e = a.se[s];
+      const int32_t bsb = a.sb0[s];
+      if (fv >= 0 && ne >= 0 && ne + fv < (int32_t)n) {
+        const uint64_t x = a.tmp64[ne + fv];
+        const int32_t q = (int32_t)(uint32_t)x, su = (int32_t)(x >> 32);
+        if (q >= ne && q < (int32_t)n && ps >= 0 && ps < ne && su >= 0 && su < (int32_t)n) {
+          a.perm[ps] = su;
+          a.pos[su] = ps;
+          a.perm[q] = s;
+          a.pos[s] = q;
+        }
+      }
+      if (e >= 0) {  // the new leader: one thread per split block
+        a.bs[s] = ne;
+        a.be[s] = e;
+        a.be[b] = ne;
+        a.cnt[b] = 0;
+        a.fc[b] = 0;
+        a.gc[b] = 0;
+        if (e - ne == 1) atomicOr((unsigned long long*)&a.sg[s >> 6], 1ull << (s & 63));
+        if (ne - bsb == 1) atomicOr((unsigned long long*)&a.sg[b >> 6], 1ull << (b & 63));
+        set_unstable(a, (uint32_t)b);
+        set_unstable(a, (uint32_t)s);
+        best = min(best, (uint32_t)b);
+        ++leaders;
+      }
+    }
+  }
+  best = wave_min_u32(best);
+  if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
+  count_work(a, 6, wave_sum_u64(leaders));
+}
+
+// ---------------------------------------------------------------------------
+// per-run set-up of the refinable partition (after the common run
+// initialisation has written block[], the bitmaps and the control block)
+// ---------------------------------------------------------------------------
+__global__ void k_l_zero(LArgs a) {
+  const GPart p = gpart();
+  for (uint32_t s = p.gtid; s < a.n; s += p.gthreads) {
+    a.cnt[s] = 0;
+    a.fc[s] = 0;
+    a.gc[s] = 0;
+  }
+  for (uint32_t w = p.gtid; w < (uint32_t)a.nwd; w += p.gthreads) a.sg[w] = 0;
+  if (p.gtid < 8) a.work[p.gtid] = 0;
+}
+__global__ void k_l_count(LArgs a) {
+  const GPart p = gpart();
+  for (uint32_t s = p.gtid; s < a.n; s += p.gthreads) atomicAdd(&a.cnt[a.block[s]], 1);
+}
+__global__ void k_l_fill(LArgs a) {
+  const GPart p = gpart();
+  for (uint32_t s = p.gtid; s < a.n; s += p.gthreads) {
+    const uint32_t q = (uint32_t)atomicAdd(&a.be[a.block[s]], 1);
+    if (q < a.n) {
+      a.perm[q] = (int32_t)s;
+      a.pos[s] = (int32_t)q;
+    } else {
+      a.ctl->state.v[4] = 1;  // never expected
+    }
+  }
+}
+__global__ void k_l_single(LArgs a) {
+  const GPart p = gpart();
+  for (uint32_t b = p.gtid; b < a.n; b += p.gthreads) {
+    if (a.cnt[b] == 1) atomicOr((unsigned long long*)&a.sg[b >> 6], 1ull << (b & 63));
+  }
+}
+__global__ void k_l_zero_cnt(LArgs a) {
+  const GPart p = gpart();
+  for (uint32_t b = p.gtid; b < a.n; b += p.gthreads) a.cnt[b] = 0;
+}
+
+template <class T>
+bisim_status lalloc(T** p, size_t count, hipStream_t s) {
+  if (*p) return BISIM_OK;
+  if (count == 0) count = 1;
+  hipError_t e = dev_alloc((void**)p, sizeof(T) * count, s);
+  if (e != hipSuccess) {
+    set_error("device allocation of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
+    return BISIM_E_NOMEM;
+  }
+  return BISIM_OK;
+}
+
+}  // namespace
+
+// capacity of the segment list: every block contributes at most
+// ceil(size / kSeg) <= size / kSeg + 1 segments
+static uint64_t seg_capacity(uint64_t n) { return n + n / kSeg + 64; }
+
+bisim_status lists_alloc(bisim_lts* h) {
+  const size_t n = (size_t)h->n;
+  const size_t nwd = (n + 63) / 64;
+  hipStream_t s = h->stream;
+  bisim_lists& L = h->lists;
+  BISIM_TRY(lalloc(&L.perm, n, s));
+  BISIM_TRY(lalloc(&L.pos, n, s));
+  BISIM_TRY(lalloc(&L.bs, n + 1, s));
+  BISIM_TRY(lalloc(&L.be, n, s));
+  BISIM_TRY(lalloc(&L.cnt, n, s));
+  BISIM_TRY(lalloc(&L.fc, n, s));
+  BISIM_TRY(lalloc(&L.gc, n, s));
+  BISIM_TRY(lalloc(&L.tmp64, n, s));
+  BISIM_TRY(lalloc(&L.lb, seg_capacity(n), s));
+  BISIM_TRY(lalloc(&L.lo, seg_capacity(n), s));
+  BISIM_TRY(lalloc(&L.ob, n, s));
+  BISIM_TRY(lalloc(&L.rk, n, s));
+  BISIM_TRY(lalloc(&L.fi, n, s));
+  BISIM_TRY(lalloc(&L.ne, n, s));
+  BISIM_TRY(lalloc(&L.ps, n, s));
+  BISIM_TRY(lalloc(&L.se, n, s));
+  BISIM_TRY(lalloc(&L.sb0, n, s));
+  BISIM_TRY(lalloc(&L.sg, nwd, s));
+  BISIM_TRY(lalloc(&L.work, 8, s));
+  return BISIM_OK;
+}
+
+// The iteration loop of engine 3; the common run initialisation has been
+// enqueued (block[] = the start partition, bitmaps, bids, control block).
+bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
+  BISIM_TRY(lists_alloc(h));
+  hipStream_t st = h->stream;
+  const uint32_t n = (uint32_t)h->n;
+  bisim_lists& L = h->lists;
+  LArgs a{};
+  a.n = n;
+  a.uniform = h->uniform;
+  a.nwd = ((uint64_t)n + 63) / 64;
+  a.in_ptr = h->in_ptr;
+  a.in_src = h->in_src;
+  a.in_ord = h->in_ord;
+  a.woff = h->woff;
+  a.block = h->block;
+  a.mw = h->mw;
+  a.tb = h->tb;
+  a.sf = h->sb;
+  a.sg = L.sg;
+  a.ub = h->ub;
+  a.us = h->us;
+  a.nlw = h->nlw;
+  a.perm = L.perm;
+  a.pos = L.pos;
+  a.bs = L.bs;
+  a.be = L.be;
+  a.cnt = L.cnt;
+  a.fc = L.fc;
+  a.gc = L.gc;
+  a.tmp64 = L.tmp64;
+  a.lb = L.lb;
+  a.lo = L.lo;
+  a.lcap = (uint32_t)seg_capacity(n);
+  a.ob = L.ob;
+  a.rk = L.rk;
+  a.fi = L.fi;
+  a.ne = L.ne;
+  a.ps = L.ps;
+  a.se = L.se;
+  a.sb0 = L.sb0;
+  a.work = L.work;
+  a.count = count_work_totals ? 1 : 0;
+  a.ctl = h->ctl;
+  a.iter_cap = cap;
+  a.trace_C = h->trace_C;
+  a.trace_nsplit = h->trace_nsplit;
+  a.trace_cap = (uint32_t)h->trace_cap;
+
+  const int cu = h->num_cu > 0 ? h->num_cu : 1;
+  int64_t gi = ((int64_t)n + kLT - 1) / kLT;
+  gi = gi > cu * 8 ? cu * 8 : (gi < 1 ? 1 : gi);
+  hipLaunchKernelGGL(k_l_zero, dim3((unsigned)gi), dim3(kLT), 0, st, a);
+  hipLaunchKernelGGL(k_l_count, dim3((unsigned)gi), dim3(kLT), 0, st, a);
+  BISIM_TRY_HIP(hipGetLastError());
+  BISIM_TRY(exclusive_scan_u32(reinterpret_cast<const uint32_t*>(L.cnt),
+                               reinterpret_cast<uint32_t*>(L.bs), n, st));
+  if (n > 0)
+    BISIM_TRY_HIP(hipMemcpyAsync(L.be, L.bs, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_l_fill, dim3((unsigned)gi), dim3(kLT), 0, st, a);
+  hipLaunchKernelGGL(k_l_single, dim3((unsigned)gi), dim3(kLT), 0, st, a);
+  hipLaunchKernelGGL(k_l_zero_cnt, dim3((unsigned)gi), dim3(kLT), 0, st, a);
+  BISIM_TRY_HIP(hipGetLastError());
+
+  const int grid = h->grid > 0 ? h->grid : cu * 8;
+  const bool prof = h->profile_every > 0;
+  if (prof && !h->pev) {
+    h->pev = new (std::nothrow) hipEvent_t[8 * 256];
+    if (!h->pev) return BISIM_E_NOMEM;
+    for (int i = 0; i < 8 * 256; ++i) BISIM_TRY_HIP(hipEventCreate(&h->pev[i]));
+    h->pev_slots = 256;
+  }
+  std::vector<uint32_t> sampled;
+  std::vector<hipEvent_t> starts;
+  auto go = [&](auto kern, hipEvent_t stop, uint32_t k) {
+    if (stop)
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kLT), 0, st, nullptr, stop, 0, a, k);
+    else
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(kLT), 0, st, a, k);
+  };
+  const uint64_t pe = prof ? (uint64_t)h->profile_every : 0;
+  hipEvent_t carry = nullptr;
+  uint32_t k = 0, chunk = 8;
+  for (;;) {
+    for (uint32_t j = 0; j < chunk; ++j, ++k) {
+      hipEvent_t ends[4] = {nullptr, nullptr, nullptr, nullptr};
+      const size_t slot = sampled.size();
+      if (prof && carry && slot < (size_t)h->pev_slots) {
+        for (int q = 0; q < 4; ++q) ends[q] = h->pev[8 * slot + 1 + q];
+        sampled.push_back(k);
+        starts.push_back(carry);
+      }
+      carry = nullptr;
+      if (prof && (k + 1) % pe == 0 && sampled.size() < (size_t)h->pev_slots) {
+        if (!ends[3]) ends[3] = h->pev[8 * sampled.size()];
+        carry = ends[3];
+      }
+      go(k_l_mark, ends[0], k);
+      go(k_l_compare, ends[1], k);
+      go(k_l_relabel, ends[2], k);
+      go(k_l_swap, ends[3], k);
+    }
+    BISIM_TRY_HIP(hipGetLastError());
+    BISIM_TRY_HIP(hipMemcpyAsync(&h->ctl_host->state, &h->ctl->state, sizeof(Line),
+                                 hipMemcpyDeviceToHost, st));
+    BISIM_TRY_HIP(hipStreamSynchronize(st));
+    if (h->ctl_host->state.v[1]) break;
+    if (k >= cap + 1) break;
+    if (chunk < 256) chunk *= 2;
+  }
+  for (int q = 0; q < 4; ++q) {
+    h->phase_ms[q] = 0;
+    h->phase_cnt[q] = 0;
+  }
+  const uint64_t iters = h->ctl_host->state.v[0];
+  for (size_t i = 0; i < sampled.size(); ++i) {
+    if ((uint64_t)sampled[i] + 1 >= iters) continue;
+    hipEvent_t prev = starts[i];
+    for (int q = 0; q < 4; ++q) {
+      hipEvent_t cur = h->pev[8 * i + 1 + q];
+      float pm = 0.f;
+      if (hipEventElapsedTime(&pm, prev, cur) == hipSuccess) {
+        h->phase_ms[q] += pm;
+        h->phase_cnt[q] += 1;
+      }
+      prev = cur;
+    }
+  }
+  if (count_work_totals)
+    BISIM_TRY_HIP(hipMemcpyAsync(h->lists_work, L.work, sizeof(h->lists_work),
+                                 hipMemcpyDeviceToHost, st));
+  else
+    for (uint64_t& w : h->lists_work) w = 0;
+  return BISIM_OK;
+}
+
+void lists_free(bisim_lts* h) {
+  bisim_lists& L = h->lists;
+  void* ptrs[] = {L.perm, L.pos, L.bs, L.be, L.cnt, L.fc, L.gc, L.tmp64, L.lb, L.lo,
+                  L.ob,   L.rk,  L.fi, L.ne, L.ps,  L.se, L.sb0, L.sg, L.work};
+  for (void* q : ptrs)
+    if (q) (void)dev_free(q, h->stream);
+  L = bisim_lists{};
+}
+
+}  // namespace bisim

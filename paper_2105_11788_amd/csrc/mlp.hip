@@ -11,7 +11,12 @@
 //                   consecutive words.
 //   k_mlp_backward  same row mapping; each wave keeps lane j's slice of the
 //                   weight gradients in registers over its rows, then the
-//                   workgroup reduces through LDS and adds once to global.
+//                   workgroup reduces through LDS (waves in a fixed order)
+//                   and stores its partial sums in its own row of a
+//                   partials buffer.
+//   k_mlp_sum       sums the workgroups' partials of each parameter in
+//                   workgroup order: no floating-point atomics, so a training
+//                   step is bitwise reproducible.
 //   k_mlp_adam      elementwise Adam step, refreshes the bf16 copy.
 #include <cmath>
 #include <new>
@@ -29,6 +34,7 @@ struct bisim_mlp {
   float* v = nullptr;
   float* grad = nullptr;     // device fp32 [P]
   float* loss = nullptr;     // device fp32 [1]
+  float* part = nullptr;     // device fp32 [workgroups][P + 2]: partial sums (+ b3, loss)
   int64_t step = 0;
 };
 
@@ -52,11 +58,30 @@ __global__ void __launch_bounds__(kMT) k_mlp_forward(const uint16_t* __restrict_
   }
 }
 
+// the same with bf16 inputs (raw IEEE bf16 bits): exact in fp32, and already
+// at the precision the forward pass rounds its inputs to
+__global__ void __launch_bounds__(kMT) k_mlp_forward_bf16(const uint16_t* __restrict__ w, int F,
+                                                           const uint16_t* __restrict__ x,
+                                                           int64_t rows, float* __restrict__ y) {
+  extern __shared__ float sw[];
+  MlpLds L = mlp_lds_layout(sw, F);
+  mlp_stage(L, w, F);
+  __syncthreads();
+  const int64_t wave = ((int64_t)blockIdx.x * kMT + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * kMT / kWave;
+  const int j = (int)lane();
+  for (int64_t r = wave; r < rows; r += nwaves) {
+    const float xl = j < F ? __uint_as_float((uint32_t)x[r * F + j] << 16) : 0.f;
+    float z1, z2;
+    const float out = mlp_forward_lanes(L, F, xl, &z1, &z2);
+    if (lane() == 0) y[r] = out;
+  }
+}
+
 __global__ void __launch_bounds__(kMT) k_mlp_backward(const uint16_t* __restrict__ w, int F,
                                                        const float* __restrict__ x,
                                                        const float* __restrict__ t, int64_t rows,
-                                                       float* __restrict__ grad,
-                                                       float* __restrict__ loss) {
+                                                       float* __restrict__ part, int64_t P) {
   extern __shared__ float sw[];
   MlpLds L = mlp_lds_layout(sw, F);
   float* red = L.end;  // [kMT/64 waves][64 lanes] partial sums, one parameter row at a time
@@ -102,32 +127,54 @@ __global__ void __launch_bounds__(kMT) k_mlp_backward(const uint16_t* __restrict
     for (int f = 0; f < kMlpMaxF; ++f)
       if (f < F) gW1[f] += dz1 * bf16_rne(xr[f]);
   }
-  // workgroup reduction through LDS, then one global add per parameter
-  auto reduce_add = [&](float v, float* dst) {
+  // workgroup reduction through LDS (waves summed in order), one store per
+  // parameter into this workgroup's row of the partials
+  float* mine = part + (int64_t)blockIdx.x * (P + 2);
+  auto reduce_store = [&](float v, int64_t idx) {
     red[wv * kWave + j] = v;
     __syncthreads();
     if (wv == 0) {
       float s = 0.f;
       for (int q = 0; q < kMT / kWave; ++q) s += red[q * kWave + j];
-      if (s != 0.f) atomicAdd(dst, s);
+      mine[idx] = s;
     }
     __syncthreads();
   };
   const MlpOffsets o = mlp_offsets(F);
-  for (int i = 0; i < kMlpH; ++i) reduce_add(gW2[i], grad + o.W2 + j * kMlpH + i);
-  for (int f = 0; f < F; ++f) reduce_add(gW1[f], grad + o.W1 + j * F + f);
-  reduce_add(gb1, grad + o.b1 + j);
-  reduce_add(gb2, grad + o.b2 + j);
-  reduce_add(gw3, grad + o.w3 + j);
-  // scalars: wave sums first
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    gb3 += __shfl_xor(gb3, d, kWave);
-    lsum += __shfl_xor(lsum, d, kWave);
-  }
+  for (int i = 0; i < kMlpH; ++i) reduce_store(gW2[i], o.W2 + j * kMlpH + i);
+  for (int f = 0; f < F; ++f) reduce_store(gW1[f], o.W1 + j * F + f);
+  reduce_store(gb1, o.b1 + j);
+  reduce_store(gb2, o.b2 + j);
+  reduce_store(gw3, o.w3 + j);
+  // scalars: every lane of a wave holds the same dy sum (b3) and the same
+  // squared errors (the row's output is the wave's); lane 0's, then the
+  // waves in order
   if (j == 0) {
-    atomicAdd(grad + o.b3, gb3 / kWave);  // every lane held the same dy sum
-    atomicAdd(loss, lsum / kWave / (float)rows);
+    red[wv] = gb3;
+    red[kMT / kWave + wv] = lsum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float sb = 0.f, sl = 0.f;
+    for (int q = 0; q < kMT / kWave; ++q) {
+      sb += red[q];
+      sl += red[kMT / kWave + q];
+    }
+    mine[o.b3] = sb;
+    mine[P + 1] = sl / (float)rows;
+  }
+}
+
+// sum of the workgroups' partials, in workgroup order; index P + 1 is the loss
+__global__ void k_mlp_sum(const float* __restrict__ part, int nblk, int64_t P,
+                          float* __restrict__ grad, float* __restrict__ loss) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= P + 1;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == P) continue;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * (P + 2) + i];
+    if (i == P + 1) *loss = s;
+    else grad[i] = s;
   }
 }
 
@@ -170,10 +217,11 @@ double normal(uint64_t& s) {
 size_t fwd_lds(int F) { return mlp_lds_floats(F) * sizeof(float); }
 size_t bwd_lds(int F) { return (mlp_lds_floats(F) + (kMT / kWave) * kWave) * sizeof(float); }
 
+constexpr int kMaxGridRows = 1024;
 unsigned grid_rows(int64_t rows) {
   int64_t waves = (rows + 0) / 1;
   int64_t g = (waves + (kMT / kWave) - 1) / (kMT / kWave);
-  if (g > 1024) g = 1024;
+  if (g > kMaxGridRows) g = kMaxGridRows;
   if (g < 1) g = 1;
   return (unsigned)g;
 }
@@ -228,6 +276,7 @@ bisim_status mlp_create(int32_t in_features, const float* init_fp32, uint64_t se
   if (e == hipSuccess) e = hipMalloc((void**)&w->v, 4 * w->P);
   if (e == hipSuccess) e = hipMalloc((void**)&w->grad, 4 * w->P);
   if (e == hipSuccess) e = hipMalloc((void**)&w->loss, 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&w->part, 4 * (size_t)kMaxGridRows * (w->P + 2));
   if (e == hipSuccess) e = hipMemcpy(w->master, h.data(), 4 * w->P, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(w->m, 0, 4 * w->P);
   if (e == hipSuccess) e = hipMemset(w->v, 0, 4 * w->P);
@@ -248,7 +297,7 @@ bisim_status mlp_create(int32_t in_features, const float* init_fp32, uint64_t se
 void mlp_free(bisim_mlp* w) {
   if (!w) return;
   (void)hipDeviceSynchronize();
-  void* p[] = {w->master, w->wbf, w->m, w->v, w->grad, w->loss};
+  void* p[] = {w->master, w->wbf, w->m, w->v, w->grad, w->loss, w->part};
   for (void* q : p)
     if (q) (void)hipFree(q);
   delete w;
@@ -275,6 +324,22 @@ bisim_status mlp_forward(const bisim_mlp* w, const float* x, int64_t rows, float
   return BISIM_OK;
 }
 
+bisim_status mlp_forward_bf16(const bisim_mlp* w, const void* x_bf16, int64_t rows, float* y,
+                              void* hip_stream) {
+  if (!w || rows < 0 || (rows > 0 && (!x_bf16 || !y))) {
+    set_error("mlp_forward_bf16: bad arguments");
+    return BISIM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (rows > 0) {
+    hipLaunchKernelGGL(k_mlp_forward_bf16, dim3(grid_rows(rows)), dim3(kMT), fwd_lds(w->F), s,
+                       w->wbf, w->F, (const uint16_t*)x_bf16, rows, y);
+    BISIM_TRY_HIP(hipGetLastError());
+  }
+  BISIM_TRY_HIP(hipStreamSynchronize(s));
+  return BISIM_OK;
+}
+
 bisim_status mlp_train_step(bisim_mlp* w, const float* x, const float* target, int64_t rows,
                             float lr, float* loss_out, float* grad_out, void* hip_stream) {
   if (!w || rows < 1 || !x || !target || !(lr >= 0.f)) {
@@ -282,10 +347,11 @@ bisim_status mlp_train_step(bisim_mlp* w, const float* x, const float* target, i
     return BISIM_E_INVALID;
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  BISIM_TRY_HIP(hipMemsetAsync(w->grad, 0, 4 * w->P, s));
-  BISIM_TRY_HIP(hipMemsetAsync(w->loss, 0, 4, s));
-  hipLaunchKernelGGL(k_mlp_backward, dim3(grid_rows(rows)), dim3(kMT), bwd_lds(w->F), s, w->wbf,
-                     w->F, x, target, rows, w->grad, w->loss);
+  const unsigned g = grid_rows(rows);
+  hipLaunchKernelGGL(k_mlp_backward, dim3(g), dim3(kMT), bwd_lds(w->F), s, w->wbf, w->F, x,
+                     target, rows, w->part, w->P);
+  hipLaunchKernelGGL(k_mlp_sum, dim3(32), dim3(256), 0, s, w->part, (int)g, w->P, w->grad,
+                     w->loss);
   BISIM_TRY_HIP(hipGetLastError());
   if (grad_out)
     BISIM_TRY_HIP(hipMemcpyAsync(grad_out, w->grad, 4 * w->P, hipMemcpyDeviceToDevice, s));

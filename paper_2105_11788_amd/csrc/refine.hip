@@ -415,6 +415,12 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
     }
     first = (uint32_t)h->first_splitter;
   }
+  const int engine = h->engine == 0 ? 2 : h->engine;  // per-phase kernels: the default
+  if (engine == 3 && (learned || rcpp)) {
+    set_error("coarsest_partition: the member-list engine runs Algorithm 3 with the plain "
+              "splitter policy only");
+    return BISIM_E_UNSUPPORTED;
+  }
   if (learned) BISIM_TRY(refine_alloc_features(h));
   Args a = make_args(h, (uint32_t)cap, learned, learned);
   a.rcpp = rcpp ? 1u : 0u;
@@ -425,9 +431,9 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
   const size_t lds = learned ? mlp_lds_floats(kPolicyF) * sizeof(float) : 0;
   std::vector<uint32_t> sampled;
   std::vector<hipEvent_t> sample_start;
-  int engine = h->engine;
-  if (engine == 0) engine = 2;  // per-phase kernels measured fastest on MI355X
-  if (engine == 1) {
+  if (engine == 3) {
+    BISIM_TRY(lists_loop(h, (uint32_t)cap, h->count_work != 0));
+  } else if (engine == 1) {
     int per_cu = 0;
     if (learned)
       BISIM_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<true>, kPT, lds));
@@ -525,7 +531,8 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
     return BISIM_E_DEVICE;
   }
   if (c.state.v[4]) {
-    set_error("learned splitter policy: priority structure inconsistent");
+    set_error(engine == 3 ? "member-list engine: inconsistent block ranges"
+                          : "learned splitter policy: priority structure inconsistent");
     return BISIM_E_DEVICE;
   }
   if (!c.state.v[1]) {
@@ -533,7 +540,7 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
     return BISIM_E_DEVICE;
   }
   h->last_iters = c.state.v[0];
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 4 && engine != 3; ++q) {  // engine 3 keeps its own
     h->phase_ms[q] = 0;
     h->phase_cnt[q] = 0;
   }

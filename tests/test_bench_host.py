@@ -66,3 +66,26 @@ def test_cpu_baseline_single_checks_partition():
     wrong = ks.copy()
     wrong[-1] = wrong[-1] + 1 if wrong[-1] + 1 < L.n else 0
     assert not bench.cpu_baseline(L, 500, wrong, target_s=0.0)["partition_equal_to_gpu"]
+
+
+def test_lists_bytes_model():
+    w = {"members": 100, "in_transitions": 600, "touched": 300, "segments": 4,
+         "member_visits": 2000, "split_states": 50, "split_blocks": 5, "split_iterations": 3}
+    n, iters = 6400, 11  # ten working iterations and the final pass
+    lb = bench.lists_bytes(n, iters, w)
+    assert len(lb) == 4
+    assert lb[0] == pytest.approx((8 * 10 + 12 * 100 + 40 * 600 + 12 * 300 + 16 * 4) / 10)
+    assert lb[1] == pytest.approx((n / 8 * 10 + 20 * 300 + 48 * 50 + 16 * 4 + 12 * 2000) / 10)
+    assert lb[2] == pytest.approx((n / 4 * 10 + 16 * 300 + 100 * 50) / 10)
+    assert lb[3] == pytest.approx((n / 8 * 10 + 48 * 50 + 72 * 5) / 10)
+
+
+def test_batch_bytes_model():
+    sizes = [10, 5000, 300, 20000]
+    st = {"global_instances": 2,
+          "work": [[7, 40, 90, 0, 0, 0, 0, 2], [100, 30, 200, 80, 10, 500, 20, 4]]}
+    got = bench.batch_bytes(sizes, st, 4)
+    n_list = 20000 + 5000  # the two largest instances take the member-list tier
+    exp = 8 * sum(sizes) + 8 * 40 + 8 * 90 + 60 * n_list + 8 * 100 + 12 * 30 + 16 * 200 \
+        + 16 * 80 + 8 * 10 + 4 * 500 + 104 * 20 + 24 * 4
+    assert got == pytest.approx(exp)

@@ -41,7 +41,16 @@ def check(B, insts, blocks, its, trace_every=1):
             assert its[k] == r["iters"], (k, L.name, its[k], r["iters"])
 
 
-@pytest.mark.parametrize("wg,lds", [(1024, 0), (256, 0), (512, 1024), (1024, 1 << 14)])
+SPILL_SKIP = pytest.mark.skip(
+    reason="512- and 1024-thread builds of the batched kernel are switched off: builds that "
+           "spilled 212-332 bytes per lane made illegal memory accesses and the cause is "
+           "not found; the kernel is built for 256 threads only")
+
+
+@pytest.mark.parametrize("wg,lds", [
+    (256, 0), (256, 1024), (256, 1 << 14), (256, 40000),
+    pytest.param(1024, 0, marks=SPILL_SKIP), pytest.param(1024, 1 << 14, marks=SPILL_SKIP),
+    pytest.param(512, 1024, marks=SPILL_SKIP)])
 def test_mixed_batch_tiers(B, wg, lds):
     insts = mixed_instances()
     with B.Batch(insts) as b:
@@ -118,9 +127,9 @@ def test_batch_4096_up_to_200k_full(B):
     """The full batch shape (4096 instances, log-uniform 100..200k states,
     ~0.65G transitions): every instance's partition against the oracle
     (computed over a pool of host processes), in two launch configurations
-    at the ends of the autotuner's range (the largest workgroups with the
-    whole LDS, so most instances are LDS-resident; the smallest workgroups
-    with a 16 KiB LDS budget, so most take the global-memory tier), with
+    at the ends of the autotuner's range (the whole LDS, so most instances
+    are LDS-resident and the large ones keep their bitmaps and lists in LDS;
+    a 16 KiB LDS budget, so most take the global-memory tier), with
     identical per-instance iteration counts; #It vs the lock-step oracle on
     a sample of small instances."""
     import ks_workers
@@ -129,7 +138,7 @@ def test_batch_4096_up_to_200k_full(B):
     print(f"[batch-200k] generated {len(insts)} instances", flush=True)
     runs = []
     with B.Batch(insts) as b:
-        for wg, lds in [(1024, 0), (256, 16384)]:
+        for wg, lds in [(256, 0), (256, 16384)]:
             b.set_option(B.BOPT_WG_SIZE, wg)
             b.set_option(B.BOPT_LDS_LIMIT, lds)
             out, its, st = b.run()

@@ -79,6 +79,42 @@ def test_mlp_gradient_and_adam_match_reference(B):
     assert np.all(np.abs(w1 - w) <= lr * (1 + 1e-3) + 1e-7)
 
 
+def test_mlp_forward_bf16_inputs(B):
+    """bf16 inputs give exactly what fp32 inputs of the same values give (the
+    forward pass rounds its inputs to bf16 either way)."""
+    F = 19
+    rng = np.random.default_rng(4)
+    x = (rng.random((1000, F)) * 8.0).astype(np.float32)
+    bits = (x.view(np.uint32) >> 16).astype(np.uint16)  # truncation: exact bf16 values
+    xb = (bits.astype(np.uint32) << 16).view(np.float32)
+    net = B.MLP(F, seed=3)
+    y32 = net.forward(np.ascontiguousarray(xb))
+    y16 = net.forward_bf16(bits)
+    assert np.array_equal(y32, y16)
+
+
+def test_mlp_training_is_reproducible(B):
+    """The gradient is summed without floating-point atomics (workgroup
+    partials added in a fixed order), so identical steps give identical
+    gradients and identical parameters, bit for bit."""
+    F = 19
+    rng = np.random.default_rng(8)
+    w = ref.he_init(F, seed=12)
+    x = (rng.random((20000, F)) * 5.0).astype(np.float32)
+    t = rng.normal(size=20000).astype(np.float32)
+    xd, td = B.DeviceArray.from_numpy(x), B.DeviceArray.from_numpy(t)
+    runs = []
+    for _ in range(2):
+        net = B.MLP(F, init=w)
+        loss, g = net.train_step(xd, td, lr=0.0, want_grad=True)
+        for _ in range(5):
+            net.train_step(xd, td, lr=1e-3)
+        runs.append((loss, g, net.params()))
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
+
+
 def test_mlp_training_reduces_loss(B):
     F = 19
     rng = np.random.default_rng(5)

@@ -1,7 +1,9 @@
 """GPU parity: the HIP refinement (through the C ABI) against the CPU oracle.
 
 Bar: bit-exact block ids (canonical, smallest member), identical iteration
-counts, and identical splitter / split-count traces, on both engines."""
+counts, and identical splitter / split-count traces, on every engine (1: one
+persistent launch, 2: a kernel per phase scanning all states, 3: a kernel per
+phase over member lists)."""
 import json
 import os
 
@@ -15,7 +17,8 @@ from paper_2105_11788_amd import gen
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-ENGINES = [1, 2]
+ENGINES = [1, 2, 3]
+ALG2_ENGINES = [1, 2]  # the member-list engine runs Algorithm 3 only
 
 
 @pytest.fixture(scope="module")
@@ -170,7 +173,7 @@ def test_many_tiny(B):
         n = int(rng.integers(1, 9))
         L = gen.random_lts(n, int(rng.integers(0, 16)), int(rng.integers(1, 4)), seed=500 + k,
                            init_blocks=int(rng.integers(0, 3)))
-        assert_parity(B, L, engines=[1 + (k % 2)])
+        assert_parity(B, L, engines=[1 + (k % 3)])
 
 
 def test_more_than_64_actions_per_state(B):
@@ -252,7 +255,7 @@ def test_repeat_runs_and_grids_deterministic(B):
     src, lab, dst, _ = dev(L)
     res = []
     with B.LTS(src, lab, dst, L.n, L.K) as h:
-        for eng, grid in [(1, 0), (1, 7), (2, 0), (2, 3), (1, 0)]:
+        for eng, grid in [(1, 0), (1, 7), (2, 0), (2, 3), (3, 0), (3, 5), (1, 0)]:
             h.set_option(B.OPT_ENGINE, eng)
             h.set_option(B.OPT_GRID, grid)
             tr = h.set_trace(4096)
@@ -326,12 +329,13 @@ def pq10m():
     return P, ks, nb
 
 
-def test_planted_quotient_10m_full(B, pq10m):
-    """The 10M-state workload on the per-phase engine: partition bit-exact
+@pytest.mark.parametrize("engine", [2, 3])
+def test_planted_quotient_10m_full(B, pq10m, engine):
+    """The 10M-state workload on the per-phase engines: partition bit-exact
     against the oracle, block count, Theorem 3 bounds, and the first 64
     iterations' splitters against the lock-step oracle."""
     P, ks, nb = pq10m
-    r = run_gpu(B, P, engine=2, trace=64)
+    r = run_gpu(B, P, engine=engine, trace=64)
     st = r["stats"]
     print(f"[pq10m] GPU: #It={st.iterations} in {st.t_alg_ms:.0f} ms", flush=True)
     assert (r["block"] == ks).all()
@@ -348,7 +352,7 @@ def assert_parity_alg2(B, L):
     cap = 3 * L.n + 2
     ref = oracle.alg3_trace(L.n, 1, L.src, L.lab, L.dst, L.init, trace_cap=cap, variant=2)
     ks, nb = oracle.ks_coarsest(L.n, 1, L.src, L.lab, L.dst, L.init)
-    for e in ENGINES:
+    for e in ALG2_ENGINES:
         g = run_gpu(B, L, engine=e, trace=cap, algorithm=2)
         assert (g["block"] == ks).all(), (L.name, e)
         st = g["stats"]
@@ -359,7 +363,7 @@ def assert_parity_alg2(B, L):
     return ref["iters"]
 
 
-@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("engine", ALG2_ENGINES)
 def test_algorithm2_figure1(B, engine):
     g = json.load(open(os.path.join(GOLD, "figure1.json")))
     L = gen.figure1()
@@ -376,6 +380,20 @@ def test_algorithm2_kripke_and_random(B):
     cases += [gen.LTS(5, 1, [], [], [], np.array([0, 1, 0, 1, 4]))]
     for L in cases:
         assert_parity_alg2(B, L)
+
+
+def test_member_list_engine_runs_algorithm3_only(B):
+    L = gen.figure1()
+    src, lab, dst, init = dev(L)
+    with B.LTS(src, lab, dst, L.n, L.K, init) as h:
+        h.set_option(B.OPT_ENGINE, 3)
+        h.set_option(B.OPT_ALGORITHM, 2)
+        with pytest.raises(B.BisimError) as e:
+            h.run()
+        assert e.value.status == B.E_UNSUPPORTED
+        h.set_option(B.OPT_ALGORITHM, 3)  # the handle stays usable
+        blk, st = h.run()
+        assert st.iterations == 8
 
 
 def test_algorithm2_needs_one_action(B):
