@@ -117,30 +117,28 @@ def lists_bytes(n: int, iters: int, w: dict):
     (int32 ids, 64-bit mark words, bids and bitmap words; an atomic counts
     its read and its write) times the run's work totals:
       mark     8 (range of C) + 12 per member (perm, in_ptr pair)
-               + 40 per in-transition (source, rank, mark-word and
-                 touched-word atomics) + 12 per touched state (block,
-                 one-state flag) + 16 per listed segment (range, entry)
-      compare  n/8 (touched bitmap scan) + 20 per touched state (block,
-               own and leader mark words) + 48 per split state (bid,
-               rank, split-flag atomics, old block and rank stores)
-               + 16 per segment + 12 per member visited (perm, touched word)
-      relabel  n/4 (split and touched bitmap scans) + 16 per touched state
-               (mark word and touched word cleared) + 100 per split state
-               (its block's bid, range and count, position, label store,
-               front/tail counters, tail state and its flag, pair store,
-               five per-state stores)
-      swap     n/8 (split bitmap scan, words cleared) + 48 per split state
-               (six per-state loads, pair load, four perm/pos stores)
-               + 72 per split block (range, counters, flags, unstable bits)
+               + 52 per in-transition (source, rank, the source's block and
+                 range, mark-word and touched-word atomics) + 8 per touched
+                 state (list entry) + 12 per listed segment (entry)
+      compare  24 per touched state (list entry, own and leader mark
+               words) + 56 per split state (bid, rank and split-flag
+               atomics, list entry) + 12 per segment + 12 per member visited
+               (perm, touched word)
+      relabel  24 per touched state (list entry; mark word and touched word
+               cleared) + 96 per split state (list entry, its block's bid,
+               range and count, position, label store, front/tail counters,
+               tail state and its flag, pair store, four list stores)
+      swap     44 per split state (seven list loads, pair load, four
+               perm/pos stores, split flag) + 64 per split block (ranges,
+               counters, unstable bits)
     Returns a list of four floats (bytes per launch)."""
     it = max(1, iters - 1)  # the final pass does no work
-    nb = n / 8.0
-    mark = 8 * it + 12 * w["members"] + 40 * w["in_transitions"] + 12 * w["touched"] \
-        + 16 * w["segments"]
-    comp = nb * it + 20 * w["touched"] + 48 * w["split_states"] + 16 * w["segments"] \
+    mark = 8 * it + 12 * w["members"] + 52 * w["in_transitions"] + 8 * w["touched"] \
+        + 12 * w["segments"]
+    comp = 24 * w["touched"] + 56 * w["split_states"] + 12 * w["segments"] \
         + 12 * w["member_visits"]
-    rel = 2 * nb * it + 16 * w["touched"] + 100 * w["split_states"]
-    swp = nb * it + 48 * w["split_states"] + 72 * w["split_blocks"]
+    rel = 24 * w["touched"] + 96 * w["split_states"]
+    swp = 44 * w["split_states"] + 64 * w["split_blocks"]
     return [mark / it, comp / it, rel / it, swp / it]
 
 
@@ -376,10 +374,15 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
         bisim.set_splitter_policy(h, bisim.POLICY_LEARNED, mlp, args.rescore)
     out = bisim.DeviceArray(L.n, np.int32)
     st = None
-    for w in range(args.warmup):
+    for w in range(max(1, args.warmup) if engine == 0 else args.warmup):
         _, st = h.run(out)
         log(f"warmup {w}: #It={st.iterations} blocks={st.blocks} t_alg={st.t_alg_ms:.1f} ms")
-    if engine != 1:  # sample ~200 iterations' phase kernels per step
+    if engine == 0:  # what the automatic choice (cached tuner) resolved to, kept fixed
+        engine, grid = h.run_config()
+        h.set_option(bisim.OPT_ENGINE, engine)
+        h.set_option(bisim.OPT_GRID, grid)
+        log(f"automatic engine choice: engine {engine}, {grid} workgroups")
+    if engine == 2:  # sample ~200 iterations' phase kernels per step
         h.set_option(bisim.OPT_PROFILE_EVERY,
                      max(1, st.iterations // 200) if st is not None else 256)
     bisim.synchronize()
@@ -393,11 +396,23 @@ def run_single(bisim, L, args, engine, mlp=None, trace=True):
     bisim.synchronize()
     t1 = time.perf_counter()
     res = {"ms_per_step": (t1 - t0) * 1000.0 / args.steps, "stats": st,
+           "run_config": h.run_config(),
            "kern_ms": float(np.mean(alg_ms)), "block": out.numpy(),
            "ms_per_step_sem": sem(step_ms), "t_alg_ms_sem": sem(alg_ms)}
-    if engine != 1:
+    if engine == 2:
         res["phase_ms"], res["phase_samples"] = h.phase_times()
         h.set_option(bisim.OPT_PROFILE_EVERY, 0)
+    elif engine == 3:
+        # the timed runs replay captured graphs; kernel durations come from one
+        # more run launched kernel by kernel with end events (~200 sampled
+        # iterations); that run's fixpoint time is reported beside them
+        h.set_option(bisim.OPT_PROFILE_EVERY, max(1, st.iterations // 200))
+        t1 = time.perf_counter()
+        _, st_p = h.run(out)
+        res["eager_ms_per_step"] = (time.perf_counter() - t1) * 1000.0
+        res["phase_ms"], res["phase_samples"] = h.phase_times()
+        h.set_option(bisim.OPT_PROFILE_EVERY, 0)
+        assert st_p.iterations == st.iterations
     if trace and engine == 3:
         h.set_option(bisim.OPT_COUNT_WORK, 1)
         _, st_w = h.run(out)
@@ -428,9 +443,10 @@ def form_plain(bisim, gen, args):
     r = run_single(bisim, L, args, args.engine)
     st = r["stats"]
     iters = st.iterations
+    eng, grid = r["run_config"]
     copy_gbs = bisim.copy_bandwidth(1 << 30)
     names = ["k_fused_x (relabel+select+mark)", "k_fused_y (compare+elect)"]
-    if args.engine == 3:
+    if eng == 3:
         lb = lists_bytes(L.n, iters, r["work_totals"])
         ms = r["phase_ms"][:4]
         q = int(np.argmax(ms))
@@ -450,7 +466,10 @@ def form_plain(bisim, gen, args):
                                         "samples": int(r["phase_samples"][i])}
                      for i in range(4)}
         per_phase["work_totals"] = r["work_totals"]
-    elif args.engine == 1:
+        per_phase["timing"] = ("kernel durations from a run launched kernel by kernel "
+                               f"({r['eager_ms_per_step']:.1f} ms to the fixpoint); the timed "
+                               "runs replay captured graphs of 32 iterations")
+    elif eng == 1:
         pb = phase_bytes(L.n, r["work"], r["nsplit"])
         mb = method_bytes(L.n, L.m, st.mark_length, r["work"], r["nsplit"])
         kernel, kern_ms = "k_persistent", r["kern_ms"]
@@ -483,7 +502,8 @@ def form_plain(bisim, gen, args):
     cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
            "iterations": iters, "blocks": st.blocks, "pre_blocks": st.pre_blocks,
            "mark_length": st.mark_length, "form": "plain", "algorithm": args.algorithm,
-           "engine": ENGINE_NAMES.get(args.engine, str(args.engine))}
+           "engine": ENGINE_NAMES.get(eng, str(eng)), "workgroups": grid,
+           "engine_choice": "automatic (cached tuner)" if args.engine == 0 else "fixed"}
     res = base_record(args, "transitions*iterations/sec (plain refinement to fixpoint)",
                       L.m * iters / (r["ms_per_step"] * 1e-3), r["ms_per_step"], cfg)
     res.update({

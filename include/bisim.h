@@ -144,7 +144,13 @@ const char* bisim_last_error(void);
 
 /*
  * bisim_set_option — per-handle settings.
- *   BISIM_OPT_ENGINE        0 = automatic, 1 = one cooperative persistent
+ *   BISIM_OPT_ENGINE        0 = automatic (default: engine 2 for LTSs under
+ *                           200,000 states, the learned policy, Algorithm 2,
+ *                           traced or limited runs; otherwise the fastest of
+ *                           engines 2 and 3 at a few grid sizes, timed on the
+ *                           LTS's first 96 iterations once per device and size
+ *                           class and cached in the file BISIM_TUNE_CACHE, else
+ *                           $HOME/.cache/bisim_tune.txt), 1 = one cooperative persistent
  *                           launch per fixpoint (grid barriers between
  *                           phases), 2 = one kernel per phase, launched in
  *                           batches with a device-side done flag, each
@@ -154,7 +160,7 @@ const char* bisim_last_error(void);
  *                           splitter's members and in-transitions and the
  *                           states they touch, not n; Algorithm 3 with the
  *                           plain policy only (else BISIM_E_UNSUPPORTED at
- *                           coarsest_partition); about 68 more bytes of
+ *                           coarsest_partition); about 84 more bytes of
  *                           device memory per state, allocated on first use.
  *   BISIM_OPT_COUNT_WORK    0 (default) or 1: engine 3 accumulates work totals
  *                           over the run (bisim_get_work).
@@ -235,6 +241,13 @@ bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* sample
  * Errors: BISIM_E_INVALID.
  */
 bisim_status bisim_get_work(bisim_lts* h, int64_t* out);
+
+/*
+ * bisim_get_run_config — engine (1, 2 or 3) and workgroup count of the last
+ * coarsest_partition on h (what BISIM_OPT_ENGINE = 0 resolved to); 0s before
+ * the first run.  Errors: BISIM_E_INVALID.
+ */
+bisim_status bisim_get_run_config(bisim_lts* h, int32_t* engine, int32_t* grid);
 
 /*
  * bisim_set_trace — record, for each iteration k < cap of subsequent

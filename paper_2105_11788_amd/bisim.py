@@ -51,7 +51,8 @@ EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
            "bisim_batch_set_option", "mlp_num_params", "mlp_create", "mlp_free",
            "mlp_get_params", "mlp_forward", "mlp_train_step", "bisim_set_splitter_policy",
            "bisim_collect_training", "bisim_get_phase_times", "bisim_device_copy",
-           "coarsest_partition_noalloc", "bisim_get_work", "mlp_forward_bf16"]
+           "coarsest_partition_noalloc", "bisim_get_work", "mlp_forward_bf16",
+           "bisim_get_run_config"]
 
 # size of the static device region of coarsest_partition_noalloc (bisim.h)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -280,6 +281,15 @@ class LTS:
         _check(L.bisim_get_phase_times(self._h, ms.ctypes.data_as(ctypes.c_void_p),
                                        cnt.ctypes.data_as(ctypes.c_void_p)))
         return ms, cnt
+
+    def run_config(self):
+        """(engine, grid) of the last run: what ENGINE_AUTO resolved to."""
+        L = self._L
+        e, g = ctypes.c_int32(0), ctypes.c_int32(0)
+        L.bisim_get_run_config.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.bisim_get_run_config.restype = ctypes.c_int32
+        _check(L.bisim_get_run_config(self._h, ctypes.byref(e), ctypes.byref(g)))
+        return e.value, g.value
 
     def work(self):
         """Work totals of the last run with OPT_COUNT_WORK (engine 3): dict of

@@ -227,6 +227,16 @@ bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* sample
   return BISIM_OK;
 }
 
+bisim_status bisim_get_run_config(bisim_lts* h, int32_t* engine, int32_t* grid) {
+  if (!h || !engine || !grid) {
+    set_error("bisim_get_run_config: NULL argument");
+    return BISIM_E_INVALID;
+  }
+  *engine = h->run_engine;
+  *grid = h->run_grid;
+  return BISIM_OK;
+}
+
 bisim_status bisim_get_work(bisim_lts* h, int64_t* out) {
   if (!h || !out) {
     set_error("bisim_get_work: NULL handle or output");

@@ -154,11 +154,16 @@ struct bisim_lists {
   int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr;
   int32_t *cnt = nullptr, *fc = nullptr, *gc = nullptr;
   uint64_t* tmp64 = nullptr;
-  int32_t *lb = nullptr, *lo = nullptr;
-  int32_t *ob = nullptr, *rk = nullptr, *fi = nullptr, *ne = nullptr, *ps = nullptr,
-          *se = nullptr, *sb0 = nullptr;
-  uint64_t* sg = nullptr;
+  int32_t *lb = nullptr, *lo = nullptr, *lh = nullptr;
+  int32_t *ts = nullptr, *tbk = nullptr;
+  int32_t *ss = nullptr, *sbk = nullptr, *sr = nullptr, *sfi = nullptr, *sne = nullptr,
+          *sps = nullptr, *sse = nullptr;
   uint64_t* work = nullptr;
+  // the captured graph of a chunk of iterations and the arguments it holds
+  hipGraphExec_t gexec = nullptr;
+  unsigned char gargs[512] = {};
+  int ggrid = 0;
+  hipStream_t own = nullptr;  // capture stream when the handle's stream is the null stream
 };
 
 struct bisim_lts {
@@ -236,6 +241,10 @@ struct bisim_lts {
   int pev_slots = 0;
   double phase_ms[4] = {0, 0, 0, 0};
   int64_t phase_cnt[4] = {0, 0, 0, 0};
+
+  // engine and grid of the last run (engine 0 resolves to the tuner's choice)
+  int run_engine = 0;
+  int run_grid = 0;
 
   // member-list engine
   bisim_lists lists;

@@ -11,15 +11,15 @@
 //                unstable bit and search the next set bit (one wave); visit
 //                the in-transitions of C's members (perm[bs[C] .. be[C]))
 //                and set their mark bits; the first touch of a state sets
-//                its touched bit, and a touched leader of a block with more
-//                than one state appends the block's member segments to a
-//                list.
-//   K  compare   touched states (found through the touched bitmap) whose
-//                marks differ from their leader's split; so do the untouched
-//                members of the listed blocks.  A split state bids for its
-//                block's new leader (64-bit max of (epoch, ~state): the
-//                smallest state wins), takes its rank within the block's
-//                split part and sets its split bit.
+//                its touched bit and lists it with its block, and a touched
+//                leader of a block with more than one state appends the
+//                block's member segments to a list.
+//   K  compare   listed touched states whose marks differ from their
+//                leader's split; so do the untouched members of the listed
+//                blocks.  A split state bids for its block's new leader
+//                (64-bit max of (epoch, ~state): the smallest state wins),
+//                takes its rank within the block's split part, sets its split
+//                bit and is listed.
 //   R  relabel   every split state takes its block's winning bid as label;
 //                the split part will be the tail [ne, be) of the block's
 //                range: split states in front of ne take an index, and the
@@ -27,15 +27,21 @@
 //                of its own; marks and touched bits are cleared.
 //   W  swap      the i-th front split state and the i-th staying tail state
 //                swap places; the new leader of each split block sets both
-//                ranges, the one-state flags and the unstable bits, and the
+//                ranges and the unstable bits, and the
 //                old label joins the next candidate (with C if anything
 //                split, the lock-step reading of Algorithm 3).
 //
+// Every per-iteration set (touched states, listed segments, split states) is
+// a list built with wave-aggregated atomics, so no kernel scans anything of
+// size n.  Iterations are captured in a hipGraph of kGraphIters iterations
+// (4 kernels each, plus one that advances the iteration base the kernels add
+// their position in the graph to) and replayed until the done flag is set.
 // The splitter sequence, the split counts and the partitions are those of
 // the other engines.  States with more than 64 actions use the mark-word
 // offsets of the preprocessing.
 #include <hip/hip_ext.h>
 
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -45,7 +51,8 @@ namespace bisim {
 namespace {
 
 constexpr int kLT = 256;
-constexpr uint32_t kSeg = 1024;  // members of a listed block per segment
+constexpr uint32_t kSeg = 1024;       // members of a listed block per segment
+constexpr uint32_t kGraphIters = 32;  // iterations per captured graph
 
 struct LArgs {
   uint32_t n;
@@ -59,15 +66,16 @@ struct LArgs {
   uint64_t* mw;
   uint64_t* tb;   // touched states
   uint64_t* sf;   // split states
-  uint64_t* sg;   // labels of one-state blocks
   uint64_t* ub;   // unstable labels
   uint64_t* us;   // summary of ub
   uint64_t* nlw;  // bids
   int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc;
   uint64_t* tmp64;
-  int32_t *lb, *lo;  // listed segments: block, offset
+  int32_t *lb, *lo, *lh;  // listed segments: block, first and end position
   uint32_t lcap;
-  int32_t *ob, *rk, *fi, *ne, *ps, *se, *sb0;  // per split state
+  uint32_t mpw;  // splitter members per wave and step of the mark kernel
+  int32_t *ts, *tbk;  // touched states and their blocks
+  int32_t *ss, *sbk, *sr, *sfi, *sne, *sps, *sse;  // split states (by list index)
   uint64_t* work;  // [8] totals when counting
   int count;
   Ctl* ctl;
@@ -84,6 +92,24 @@ __device__ __forceinline__ GPart gpart() {
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t gthreads = gridDim.x * blockDim.x;
   return {gtid, gthreads, gtid / kWave, gthreads / kWave};
+}
+
+// iteration of a launch: the base advanced after every graph replay (0 for
+// eager launches) plus the launch's position
+__device__ __forceinline__ uint32_t iter_of(const LArgs& a, uint32_t kofs) {
+  return a.ctl->state.v[6] + kofs;
+}
+
+// wave-aggregated reservation of one list entry per lane with pred; returns
+// the entry index (kNone without pred).  Wave-uniform call.
+__device__ __forceinline__ uint32_t reserve(uint32_t* counter, bool pred) {
+  const uint64_t bal = __ballot(pred);
+  if (!bal) return kNone;
+  const int leader = __ffsll((unsigned long long)bal) - 1;
+  uint32_t base = 0;
+  if ((int)lane() == leader) base = atomicAdd(counter, (uint32_t)__popcll(bal));
+  base = (uint32_t)__shfl((int)base, leader, kWave);
+  return pred ? base + (uint32_t)__popcll(bal & ((1ull << lane()) - 1ull)) : kNone;
 }
 
 __device__ __forceinline__ void set_unstable(const LArgs& a, uint32_t b) {
@@ -119,9 +145,10 @@ __device__ __forceinline__ bool marks_differ(const LArgs& a, int32_t s, int32_t 
 // ---------------------------------------------------------------------------
 // M: select, mark
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t k) {
-  const uint32_t par = k & 1;
+__global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
+  const uint32_t k = iter_of(a, kofs);
+  const uint32_t par = k & 1;
   const uint32_t C0 = a.ctl->cand[par].v[0];
   if (done) return;
   const GPart p = gpart();
@@ -141,13 +168,17 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t k) {
   const uint32_t C = C0;
   if (p.gtid == 0) {
     a.ctl->state.v[3] = C;
-    a.ctl->cntS[par ^ 1].v[0] = 0;  // counters of the next iteration
+    a.ctl->cntT[par ^ 1].v[0] = 0;  // counters of the next iteration
+    a.ctl->cntS[par ^ 1].v[0] = 0;
     a.ctl->cntC[par ^ 1].v[0] = 0;
     if (a.trace_C && k < a.trace_cap) a.trace_C[k] = (int32_t)C;
   }
   const uint32_t n = a.n;
   const uint32_t nw = (n + 63u) >> 6, nsw = (nw + 63u) >> 6;
-  if (p.gwave == p.gwaves - 1) {  // clear C, find the next smallest unstable label
+  // clear C, find the next smallest unstable label: the last wave of the
+  // first workgroup (dispatched first; members go to waves in order, so a
+  // small splitter's marking falls to other waves)
+  if (p.gwave == min(p.gwaves, (uint32_t)(kLT / kWave)) - 1) {
     const uint32_t w0 = C >> 6;
     const uint64_t bits = a.ub[w0] & ~(1ull << (C & 63));
     if (lane() == 0) {
@@ -182,9 +213,11 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t k) {
   if (p.gtid == 0 && a.count) {
     atomicAdd((unsigned long long*)&a.work[0], (unsigned long long)csz);
   }
-  for (uint32_t i0 = p.gwave * kWave; i0 < csz; i0 += p.gwaves * kWave) {
+  // a.mpw members per wave and step (about 64 / the mean in-degree), so that
+  // a wave's in-transitions mostly fit one round of its 64 lanes
+  for (uint32_t i0 = p.gwave * a.mpw; i0 < csz; i0 += p.gwaves * a.mpw) {
     const uint32_t i = i0 + lane();
-    const bool hit = i < csz;
+    const bool hit = lane() < a.mpw && i < csz;
     uint32_t beg = 0, deg = 0;
     if (hit) {
       const uint32_t t = (uint32_t)a.perm[cb + i];
@@ -208,29 +241,33 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t k) {
       const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
       const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
       bool first = false, lead = false;
-      int32_t s = 0;
+      int32_t s = 0, b = 0;
+      uint32_t lo_ = 0, hi_ = 0;
       if (valid) {
         const uint32_t edge = jb + (ee - (ji - jd));
         s = a.in_src[edge];
         const int32_t o = a.in_ord[edge];
+        // the source's block and, in case it leads that block, the block's
+        // range are loaded beside the atomics (one round trip, not three)
+        b = a.block[s];
+        lo_ = (uint32_t)a.bs[s];
+        hi_ = (uint32_t)a.be[s];
         atomicOr((unsigned long long*)mword(a, s, o), 1ull << (o & 63));
         const uint64_t tbit = 1ull << (s & 63);
         const uint64_t old = atomicOr((unsigned long long*)&a.tb[s >> 6], (unsigned long long)tbit);
         first = !(old & tbit);
-        if (first) {
-          const int32_t b = a.block[s];
-          // a touched leader of a one-state block has no untouched member
-          lead = (b == s) && !test_bit(a.sg, (uint32_t)s);
-        }
+        // a touched leader of a one-state block has no untouched member
+        lead = first && b == s && hi_ > lo_ + 1 && hi_ <= a.n;
       }
       count_work(a, 2, (uint64_t)__popcll(__ballot(first)));
-      // the listed block's member segments (wave-aggregated reservation)
-      uint32_t lo_ = 0, nseg = 0;
-      if (lead) {
-        lo_ = (uint32_t)a.bs[s];
-        const uint32_t sz = (uint32_t)a.be[s] - lo_;
-        nseg = (sz + kSeg - 1) / kSeg;
+      const uint32_t ti = reserve(&a.ctl->cntT[par].v[0], first);
+      if (first && ti < a.n) {
+        a.ts[ti] = s;
+        a.tbk[ti] = b;
       }
+      // the listed block's member segments (wave-aggregated reservation),
+      // each recorded with its absolute position range
+      const uint32_t nseg = lead ? (hi_ - lo_ + kSeg - 1) / kSeg : 0u;
       const uint32_t sincl = wave_incl_scan_u32(nseg);
       const uint32_t stot = (uint32_t)__shfl((int)sincl, kWave - 1, kWave);
       count_work(a, 3, stot);
@@ -241,7 +278,8 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t k) {
         for (uint32_t q = 0; q < nseg; ++q) {
           if (base + q >= a.lcap) break;  // never expected (capacity covers every block)
           a.lb[base + q] = s;
-          a.lo[base + q] = (int32_t)(q * kSeg);
+          a.lo[base + q] = (int32_t)(lo_ + q * kSeg);
+          a.lh[base + q] = (int32_t)min(hi_, lo_ + (q + 1) * kSeg);
         }
       }
     }
@@ -251,55 +289,48 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t k) {
 // ---------------------------------------------------------------------------
 // K: compare, elect, rank
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t k) {
-  const uint32_t par = k & 1;
+__global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
+  const uint32_t k = iter_of(a, kofs);
+  const uint32_t par = k & 1;
+  const uint32_t nT = min(a.ctl->cntT[par].v[0], a.n);
   const uint32_t nL = a.ctl->cntC[par].v[0];
   if (done) return;
   const GPart p = gpart();
   const uint64_t epoch = (uint64_t)(k + 1) << 32;
   const uint32_t n = a.n;
-  const uint32_t nw = (n + 63u) >> 6;
+  uint32_t* nS = &a.ctl->cntS[par].v[0];
   const uint32_t half = p.gwaves > 1 ? p.gwaves / 2 : 1;
   if (p.gwave < half) {
-    // touched states, through the touched bitmap: 64 words per wave and step
-    for (uint32_t w0 = p.gwave * kWave; w0 < nw; w0 += half * kWave) {
-      const uint32_t wi = w0 + lane();
-      const uint64_t word = wi < nw ? a.tb[wi] : 0ull;
-      uint64_t nz = __ballot(word != 0);
-      while (nz) {
-        const int j = __ffsll((unsigned long long)nz) - 1;
-        nz &= nz - 1;
-        const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
-        const uint32_t widx = w0 + (uint32_t)j;
-        const int32_t s = (int32_t)((widx << 6) + lane());
-        bool sp = false;
-        int32_t b = 0;
-        if ((W >> lane()) & 1ull) {
-          b = a.block[s];
-          sp = (b != s) && marks_differ(a, s, b);
-        }
-        int32_t r = 0;
-        if (sp) {
-          atomicMax((unsigned long long*)&a.nlw[b],
-                    (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
-          r = atomicAdd(&a.cnt[b], 1);
-          a.ob[s] = b;
-          a.rk[s] = r;
-        }
-        const uint64_t sbal = __ballot(sp);
-        if (sbal && lane() == 0) {
-          atomicOr((unsigned long long*)&a.sf[widx], (unsigned long long)sbal);
-          atomicAdd(&a.ctl->cntS[par].v[0], (uint32_t)__popcll(sbal));
-        }
+    // listed touched states, one per thread of the first half of the grid
+    for (uint32_t i0 = p.gwave * kWave; i0 < nT; i0 += half * kWave) {
+      const uint32_t i = i0 + lane();
+      int32_t s = 0, b = 0;
+      bool sp = false;
+      if (i < nT) {
+        s = a.ts[i];
+        b = a.tbk[i];
+        sp = (b != s) && marks_differ(a, s, b);
+      }
+      int32_t r = 0;
+      if (sp) {
+        atomicMax((unsigned long long*)&a.nlw[b],
+                  (unsigned long long)(epoch | (uint64_t)(kNone - (uint32_t)s)));
+        r = atomicAdd(&a.cnt[b], 1);
+        atomicOr((unsigned long long*)&a.sf[s >> 6], 1ull << (s & 63));
+      }
+      const uint32_t si = reserve(nS, sp);
+      if (sp && si < n) {
+        a.ss[si] = s;
+        a.sbk[si] = b;
+        a.sr[si] = r;
       }
     }
   } else {
     // untouched members of the listed blocks: one segment per wave and step
     for (uint32_t j = p.gwave - half; j < nL && j < a.lcap; j += p.gwaves - half) {
       const int32_t b = a.lb[j];
-      const uint32_t off = (uint32_t)a.lo[j];
-      const uint32_t lo = (uint32_t)a.bs[b] + off, hi = (uint32_t)a.be[b];
+      const uint32_t lo = (uint32_t)a.lo[j], hi = (uint32_t)a.lh[j];
       const uint32_t cntm = hi > lo ? min(kSeg, hi - lo) : 0u;
       count_work(a, 4, cntm);
       for (uint32_t i0 = 0; i0 < cntm; i0 += kWave) {
@@ -320,13 +351,15 @@ __global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t k) {
           atomicMax((unsigned long long*)&a.nlw[b],
                     (unsigned long long)(epoch | (uint64_t)(kNone - sm)));
           base = (uint32_t)atomicAdd(&a.cnt[b], (int)__popcll(bal));
-          atomicAdd(&a.ctl->cntS[par].v[0], (uint32_t)__popcll(bal));
         }
         base = (uint32_t)__shfl((int)base, 0, kWave);
-        if (sp) {
-          a.ob[s] = b;
-          a.rk[s] = (int32_t)(base + (uint32_t)__popcll(bal & ((1ull << lane()) - 1ull)));
-          atomicOr((unsigned long long*)&a.sf[s >> 6], 1ull << (s & 63));
+        const int32_t r = (int32_t)(base + (uint32_t)__popcll(bal & ((1ull << lane()) - 1ull)));
+        if (sp) atomicOr((unsigned long long*)&a.sf[s >> 6], 1ull << (s & 63));
+        const uint32_t si = reserve(nS, sp);
+        if (sp && si < n) {
+          a.ss[si] = s;
+          a.sbk[si] = b;
+          a.sr[si] = r;
         }
       }
     }
@@ -336,72 +369,55 @@ __global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t k) {
 // ---------------------------------------------------------------------------
 // R: relabel, tail bookkeeping; clear marks and touched bits
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t k) {
-  const uint32_t par = k & 1;
+__global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
-  const uint32_t nS = a.ctl->cntS[par].v[0];
+  const uint32_t k = iter_of(a, kofs);
+  const uint32_t par = k & 1;
+  const uint32_t nS = min(a.ctl->cntS[par].v[0], a.n);
+  const uint32_t nT = min(a.ctl->cntT[par].v[0], a.n);
   if (done) return;
   const GPart p = gpart();
   const uint32_t n = a.n;
-  const uint32_t nw = (n + 63u) >> 6;
   const uint32_t half = p.gwaves > 1 ? p.gwaves / 2 : 1;
   if (p.gwave < half) {
-    if (nS == 0) return;
     count_work(a, 5, p.gtid == 0 ? nS : 0);
-    for (uint32_t w0 = p.gwave * kWave; w0 < nw; w0 += half * kWave) {
-      const uint32_t wi = w0 + lane();
-      const uint64_t word = wi < nw ? a.sf[wi] : 0ull;
-      uint64_t nz = __ballot(word != 0);
-      while (nz) {
-        const int j = __ffsll((unsigned long long)nz) - 1;
-        nz &= nz - 1;
-        const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
-        const uint32_t widx = w0 + (uint32_t)j;
-        const int32_t s = (int32_t)((widx << 6) + lane());
-        if (!((W >> lane()) & 1ull)) continue;
-        const int32_t b = a.ob[s], r = a.rk[s];
-        const uint64_t nv = a.nlw[b];
-        const int32_t e = a.be[b], c = a.cnt[b], bsb = a.bs[b], pv = a.pos[s];
-        const int32_t nl = (int32_t)(kNone - (uint32_t)nv);
-        a.block[s] = nl;
-        const int32_t ne = e - c, q = ne + r;
-        int32_t fv = -1, uv = -1;
-        const bool ok = ne >= 0 && q >= ne && q < e && e <= (int32_t)n && pv >= 0 && pv < (int32_t)n;
-        if (ok) {
-          if (pv < ne) fv = atomicAdd(&a.fc[b], 1);
-          uv = a.perm[q];  // every tail position is examined once
-        }
-        a.fi[s] = fv;
-        a.ne[s] = ok ? ne : 0;
-        a.ps[s] = ok ? pv : 0;
-        a.se[s] = (ok && nl == s) ? e : -1;
-        a.sb0[s] = bsb;
-        if (uv >= 0 && uv < (int32_t)n && !test_bit(a.sf, (uint32_t)uv)) {
-          const int32_t jj = atomicAdd(&a.gc[b], 1);
-          if (ne + jj < e)
-            a.tmp64[ne + jj] = ((uint64_t)(uint32_t)uv << 32) | (uint32_t)q;
-        }
+    for (uint32_t i = p.gwave * kWave + lane(); i < nS; i += half * kWave) {
+      const int32_t s = a.ss[i], b = a.sbk[i], r = a.sr[i];
+      const uint64_t nv = a.nlw[b];
+      const int32_t e = a.be[b], c = a.cnt[b], pv = a.pos[s];
+      const int32_t nl = (int32_t)(kNone - (uint32_t)nv);
+      a.block[s] = nl;
+      const int32_t ne = e - c, q = ne + r;
+      int32_t fv = -1, uv = -1;
+      const bool ok = ne >= 0 && q >= ne && q < e && e <= (int32_t)n && pv >= 0 && pv < (int32_t)n;
+      if (ok) {
+        if (pv < ne) fv = atomicAdd(&a.fc[b], 1);
+        uv = a.perm[q];  // every tail position is examined once
+      } else {
+        a.ctl->state.v[4] = 1;  // never expected
+      }
+      a.sfi[i] = fv;
+      a.sne[i] = ok ? ne : 0;
+      a.sps[i] = ok ? pv : 0;
+      a.sse[i] = (ok && nl == s) ? e : -1;
+      if (uv >= 0 && uv < (int32_t)n && !test_bit(a.sf, (uint32_t)uv)) {
+        const int32_t jj = atomicAdd(&a.gc[b], 1);
+        if (ne + jj < e)
+          a.tmp64[ne + jj] = ((uint64_t)(uint32_t)uv << 32) | (uint32_t)q;
+        else
+          a.ctl->state.v[4] = 1;
       }
     }
   } else {
     // clear the marks and touched bits of this iteration's touched states
-    for (uint32_t w0 = (p.gwave - half) * kWave; w0 < nw; w0 += (p.gwaves - half) * kWave) {
-      const uint32_t wi = w0 + lane();
-      const uint64_t word = wi < nw ? a.tb[wi] : 0ull;
-      uint64_t nz = __ballot(word != 0);
-      if (word) a.tb[wi] = 0;
-      while (nz) {
-        const int j = __ffsll((unsigned long long)nz) - 1;
-        nz &= nz - 1;
-        const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
-        const int32_t s = (int32_t)(((w0 + (uint32_t)j) << 6) + lane());
-        if (!((W >> lane()) & 1ull)) continue;
-        if (a.uniform) {
-          a.mw[s] = 0;
-        } else {
-          for (uint32_t w = a.woff[s]; w < a.woff[s + 1]; ++w) a.mw[w] = 0;
-        }
+    for (uint32_t i = (p.gwave - half) * kWave + lane(); i < nT; i += (p.gwaves - half) * kWave) {
+      const int32_t s = a.ts[i];
+      if (a.uniform) {
+        a.mw[s] = 0;
+      } else {
+        for (uint32_t w = a.woff[s]; w < a.woff[s + 1]; ++w) a.mw[w] = 0;
       }
+      a.tb[s >> 6] = 0;  // every touched state of the word clears it
     }
   }
 }
@@ -409,10 +425,11 @@ __global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t k) {
 // ---------------------------------------------------------------------------
 // W: swaps, new ranges, unstable updates, next candidate
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t k) {
-  const uint32_t par = k & 1;
+__global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
-  const uint32_t nS = a.ctl->cntS[par].v[0];
+  const uint32_t k = iter_of(a, kofs);
+  const uint32_t par = k & 1;
+  const uint32_t nS = min(a.ctl->cntS[par].v[0], a.n);
   const uint32_t C = a.ctl->state.v[3];
   if (done) return;
   const GPart p = gpart();
@@ -427,21 +444,12 @@ __global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t k) {
   }
   if (nS == 0) return;
   const uint32_t n = a.n;
-  const uint32_t nw = (n + 63u) >> 6;
   uint32_t best = kNone, leaders = 0;
-  for (uint32_t w0 = p.gwave * kWave; w0 < nw; w0 += p.gwaves * kWave) {
-    const uint32_t wi = w0 + lane();
-    const uint64_t word = wi < nw ? a.sf[wi] : 0ull;
-    uint64_t nz = __ballot(word != 0);
-    if (word) a.sf[wi] = 0;
-    while (nz) {
-      const int j = __ffsll((unsigned long long)nz) - 1;
-      nz &= nz - 1;
-      const uint64_t W = (uint64_t)__shfl((unsigned long long)word, j, kWave);
-      const int32_t s = (int32_t)(((w0 + (uint32_t)j) << 6) + lane());
-      if (!((W >> lane()) & 1ull)) continue;
-      const int32_t b = a.ob[s], fv = a.fi[s], ne = a.ne[s], ps = a.ps[s], e = a.se[s];
-      const int32_t bsb = a.sb0[s];
+  for (uint32_t i0 = p.gwave * kWave; i0 < nS; i0 += p.gwaves * kWave) {
+    const uint32_t i = i0 + lane();
+    if (i < nS) {
+      const int32_t s = a.ss[i], b = a.sbk[i], fv = a.sfi[i], ne = a.sne[i], ps = a.sps[i];
+      const int32_t e = a.sse[i];
       if (fv >= 0 && ne >= 0 && ne + fv < (int32_t)n) {
         const uint64_t x = a.tmp64[ne + fv];
         const int32_t q = (int32_t)(uint32_t)x, su = (int32_t)(x >> 32);
@@ -450,6 +458,8 @@ __global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t k) {
           a.pos[su] = ps;
           a.perm[q] = s;
           a.pos[s] = q;
+        } else {
+          a.ctl->state.v[4] = 1;  // never expected
         }
       }
       if (e >= 0) {  // the new leader: one thread per split block
@@ -459,18 +469,22 @@ __global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t k) {
         a.cnt[b] = 0;
         a.fc[b] = 0;
         a.gc[b] = 0;
-        if (e - ne == 1) atomicOr((unsigned long long*)&a.sg[s >> 6], 1ull << (s & 63));
-        if (ne - bsb == 1) atomicOr((unsigned long long*)&a.sg[b >> 6], 1ull << (b & 63));
         set_unstable(a, (uint32_t)b);
         set_unstable(a, (uint32_t)s);
         best = min(best, (uint32_t)b);
         ++leaders;
       }
+      atomicAnd((unsigned long long*)&a.sf[s >> 6], ~(1ull << (s & 63)));
     }
   }
   best = wave_min_u32(best);
   if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
   count_work(a, 6, wave_sum_u64(leaders));
+}
+
+// after a graph replay of `by` iterations: advance the iteration base
+__global__ void k_l_advance(LArgs a, uint32_t by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctl->state.v[6] += by;
 }
 
 // ---------------------------------------------------------------------------
@@ -484,7 +498,6 @@ __global__ void k_l_zero(LArgs a) {
     a.fc[s] = 0;
     a.gc[s] = 0;
   }
-  for (uint32_t w = p.gtid; w < (uint32_t)a.nwd; w += p.gthreads) a.sg[w] = 0;
   if (p.gtid < 8) a.work[p.gtid] = 0;
 }
 __global__ void k_l_count(LArgs a) {
@@ -501,12 +514,6 @@ __global__ void k_l_fill(LArgs a) {
     } else {
       a.ctl->state.v[4] = 1;  // never expected
     }
-  }
-}
-__global__ void k_l_single(LArgs a) {
-  const GPart p = gpart();
-  for (uint32_t b = p.gtid; b < a.n; b += p.gthreads) {
-    if (a.cnt[b] == 1) atomicOr((unsigned long long*)&a.sg[b >> 6], 1ull << (b & 63));
   }
 }
 __global__ void k_l_zero_cnt(LArgs a) {
@@ -534,7 +541,6 @@ static uint64_t seg_capacity(uint64_t n) { return n + n / kSeg + 64; }
 
 bisim_status lists_alloc(bisim_lts* h) {
   const size_t n = (size_t)h->n;
-  const size_t nwd = (n + 63) / 64;
   hipStream_t s = h->stream;
   bisim_lists& L = h->lists;
   BISIM_TRY(lalloc(&L.perm, n, s));
@@ -547,14 +553,9 @@ bisim_status lists_alloc(bisim_lts* h) {
   BISIM_TRY(lalloc(&L.tmp64, n, s));
   BISIM_TRY(lalloc(&L.lb, seg_capacity(n), s));
   BISIM_TRY(lalloc(&L.lo, seg_capacity(n), s));
-  BISIM_TRY(lalloc(&L.ob, n, s));
-  BISIM_TRY(lalloc(&L.rk, n, s));
-  BISIM_TRY(lalloc(&L.fi, n, s));
-  BISIM_TRY(lalloc(&L.ne, n, s));
-  BISIM_TRY(lalloc(&L.ps, n, s));
-  BISIM_TRY(lalloc(&L.se, n, s));
-  BISIM_TRY(lalloc(&L.sb0, n, s));
-  BISIM_TRY(lalloc(&L.sg, nwd, s));
+  BISIM_TRY(lalloc(&L.lh, seg_capacity(n), s));
+  int32_t** lists[] = {&L.ts, &L.tbk, &L.ss, &L.sbk, &L.sr, &L.sfi, &L.sne, &L.sps, &L.sse};
+  for (int32_t** q : lists) BISIM_TRY(lalloc(q, n, s));
   BISIM_TRY(lalloc(&L.work, 8, s));
   return BISIM_OK;
 }
@@ -578,7 +579,6 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
   a.mw = h->mw;
   a.tb = h->tb;
   a.sf = h->sb;
-  a.sg = L.sg;
   a.ub = h->ub;
   a.us = h->us;
   a.nlw = h->nlw;
@@ -592,14 +592,23 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
   a.tmp64 = L.tmp64;
   a.lb = L.lb;
   a.lo = L.lo;
+  a.lh = L.lh;
   a.lcap = (uint32_t)seg_capacity(n);
-  a.ob = L.ob;
-  a.rk = L.rk;
-  a.fi = L.fi;
-  a.ne = L.ne;
-  a.ps = L.ps;
-  a.se = L.se;
-  a.sb0 = L.sb0;
+  {
+    const uint64_t deg = n > 0 ? ((uint64_t)h->m + n - 1) / n : 1;  // mean in-degree, rounded up
+    uint32_t mpw = 64;
+    while (mpw > 1 && (uint64_t)mpw * (deg ? deg : 1) > 64) mpw >>= 1;
+    a.mpw = mpw;
+  }
+  a.ts = L.ts;
+  a.tbk = L.tbk;
+  a.ss = L.ss;
+  a.sbk = L.sbk;
+  a.sr = L.sr;
+  a.sfi = L.sfi;
+  a.sne = L.sne;
+  a.sps = L.sps;
+  a.sse = L.sse;
   a.work = L.work;
   a.count = count_work_totals ? 1 : 0;
   a.ctl = h->ctl;
@@ -619,55 +628,103 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
   if (n > 0)
     BISIM_TRY_HIP(hipMemcpyAsync(L.be, L.bs, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_l_fill, dim3((unsigned)gi), dim3(kLT), 0, st, a);
-  hipLaunchKernelGGL(k_l_single, dim3((unsigned)gi), dim3(kLT), 0, st, a);
   hipLaunchKernelGGL(k_l_zero_cnt, dim3((unsigned)gi), dim3(kLT), 0, st, a);
   BISIM_TRY_HIP(hipGetLastError());
 
   const int grid = h->grid > 0 ? h->grid : cu * 8;
+  h->run_grid = grid;
   const bool prof = h->profile_every > 0;
-  if (prof && !h->pev) {
-    h->pev = new (std::nothrow) hipEvent_t[8 * 256];
-    if (!h->pev) return BISIM_E_NOMEM;
-    for (int i = 0; i < 8 * 256; ++i) BISIM_TRY_HIP(hipEventCreate(&h->pev[i]));
-    h->pev_slots = 256;
-  }
   std::vector<uint32_t> sampled;
   std::vector<hipEvent_t> starts;
-  auto go = [&](auto kern, hipEvent_t stop, uint32_t k) {
-    if (stop)
-      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kLT), 0, st, nullptr, stop, 0, a, k);
-    else
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(kLT), 0, st, a, k);
-  };
-  const uint64_t pe = prof ? (uint64_t)h->profile_every : 0;
-  hipEvent_t carry = nullptr;
-  uint32_t k = 0, chunk = 8;
-  for (;;) {
-    for (uint32_t j = 0; j < chunk; ++j, ++k) {
-      hipEvent_t ends[4] = {nullptr, nullptr, nullptr, nullptr};
-      const size_t slot = sampled.size();
-      if (prof && carry && slot < (size_t)h->pev_slots) {
-        for (int q = 0; q < 4; ++q) ends[q] = h->pev[8 * slot + 1 + q];
-        sampled.push_back(k);
-        starts.push_back(carry);
-      }
-      carry = nullptr;
-      if (prof && (k + 1) % pe == 0 && sampled.size() < (size_t)h->pev_slots) {
-        if (!ends[3]) ends[3] = h->pev[8 * sampled.size()];
-        carry = ends[3];
-      }
-      go(k_l_mark, ends[0], k);
-      go(k_l_compare, ends[1], k);
-      go(k_l_relabel, ends[2], k);
-      go(k_l_swap, ends[3], k);
+  if (prof) {
+    // eager launches (the iteration base stays 0), with events bound to the
+    // ends of the kernels of every P-th iteration
+    if (!h->pev) {
+      h->pev = new (std::nothrow) hipEvent_t[8 * 256];
+      if (!h->pev) return BISIM_E_NOMEM;
+      for (int i = 0; i < 8 * 256; ++i) BISIM_TRY_HIP(hipEventCreate(&h->pev[i]));
+      h->pev_slots = 256;
     }
-    BISIM_TRY_HIP(hipGetLastError());
-    BISIM_TRY_HIP(hipMemcpyAsync(&h->ctl_host->state, &h->ctl->state, sizeof(Line),
-                                 hipMemcpyDeviceToHost, st));
-    BISIM_TRY_HIP(hipStreamSynchronize(st));
-    if (h->ctl_host->state.v[1]) break;
-    if (k >= cap + 1) break;
-    if (chunk < 256) chunk *= 2;
+    auto go = [&](auto kern, hipEvent_t stop, uint32_t k) {
+      if (stop)
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kLT), 0, st, nullptr, stop, 0, a, k);
+      else
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kLT), 0, st, a, k);
+    };
+    const uint64_t pe = (uint64_t)h->profile_every;
+    hipEvent_t carry = nullptr;
+    uint32_t k = 0, chunk = 8;
+    for (;;) {
+      for (uint32_t j = 0; j < chunk; ++j, ++k) {
+        hipEvent_t ends[4] = {nullptr, nullptr, nullptr, nullptr};
+        const size_t slot = sampled.size();
+        if (carry && slot < (size_t)h->pev_slots) {
+          for (int q = 0; q < 4; ++q) ends[q] = h->pev[8 * slot + 1 + q];
+          sampled.push_back(k);
+          starts.push_back(carry);
+        }
+        carry = nullptr;
+        if ((k + 1) % pe == 0 && sampled.size() < (size_t)h->pev_slots) {
+          if (!ends[3]) ends[3] = h->pev[8 * sampled.size()];
+          carry = ends[3];
+        }
+        go(k_l_mark, ends[0], k);
+        go(k_l_compare, ends[1], k);
+        go(k_l_relabel, ends[2], k);
+        go(k_l_swap, ends[3], k);
+      }
+      BISIM_TRY_HIP(hipGetLastError());
+      BISIM_TRY_HIP(hipMemcpyAsync(&h->ctl_host->state, &h->ctl->state, sizeof(Line),
+                                   hipMemcpyDeviceToHost, st));
+      BISIM_TRY_HIP(hipStreamSynchronize(st));
+      if (h->ctl_host->state.v[1]) break;
+      if (k >= cap + 1) break;
+      if (chunk < 256) chunk *= 2;
+    }
+  } else {
+    // a graph of kGraphIters iterations, captured once per argument set and
+    // replayed until the done flag is set.  The null stream cannot be
+    // captured: the handle then uses a stream of its own, created blocking,
+    // so that it is ordered with the null stream's work before and after.
+    static_assert(sizeof(LArgs) <= sizeof(L.gargs), "graph argument record");
+    if (!st && !L.own) BISIM_TRY_HIP(hipStreamCreate(&L.own));
+    hipStream_t gs = st ? st : L.own;
+    if (!L.gexec || L.ggrid != grid || memcmp(L.gargs, &a, sizeof(LArgs)) != 0) {
+      if (L.gexec) {
+        (void)hipGraphExecDestroy(L.gexec);
+        L.gexec = nullptr;
+      }
+      hipGraph_t graph = nullptr;
+      BISIM_TRY_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      for (uint32_t j = 0; j < kGraphIters; ++j) {
+        hipLaunchKernelGGL(k_l_mark, dim3(grid), dim3(kLT), 0, gs, a, j);
+        hipLaunchKernelGGL(k_l_compare, dim3(grid), dim3(kLT), 0, gs, a, j);
+        hipLaunchKernelGGL(k_l_relabel, dim3(grid), dim3(kLT), 0, gs, a, j);
+        hipLaunchKernelGGL(k_l_swap, dim3(grid), dim3(kLT), 0, gs, a, j);
+      }
+      hipLaunchKernelGGL(k_l_advance, dim3(1), dim3(64), 0, gs, a, kGraphIters);
+      const hipError_t le = hipGetLastError();
+      const hipError_t ce = hipStreamEndCapture(gs, &graph);
+      BISIM_TRY_HIP(le);
+      BISIM_TRY_HIP(ce);
+      const hipError_t ie = hipGraphInstantiate(&L.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      BISIM_TRY_HIP(ie);
+      memcpy(L.gargs, &a, sizeof(LArgs));
+      L.ggrid = grid;
+    }
+    uint64_t launched = 0;
+    uint32_t reps = 1;
+    for (;;) {
+      for (uint32_t r = 0; r < reps; ++r) BISIM_TRY_HIP(hipGraphLaunch(L.gexec, gs));
+      launched += (uint64_t)reps * kGraphIters;
+      BISIM_TRY_HIP(hipMemcpyAsync(&h->ctl_host->state, &h->ctl->state, sizeof(Line),
+                                   hipMemcpyDeviceToHost, gs));
+      BISIM_TRY_HIP(hipStreamSynchronize(gs));
+      if (h->ctl_host->state.v[1]) break;
+      if (launched >= (uint64_t)cap + 1) break;
+      if (reps < 8) reps *= 2;
+    }
   }
   for (int q = 0; q < 4; ++q) {
     h->phase_ms[q] = 0;
@@ -697,8 +754,13 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
 
 void lists_free(bisim_lts* h) {
   bisim_lists& L = h->lists;
-  void* ptrs[] = {L.perm, L.pos, L.bs, L.be, L.cnt, L.fc, L.gc, L.tmp64, L.lb, L.lo,
-                  L.ob,   L.rk,  L.fi, L.ne, L.ps,  L.se, L.sb0, L.sg, L.work};
+  if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
+  if (L.own) {
+    (void)hipStreamSynchronize(L.own);
+    (void)hipStreamDestroy(L.own);
+  }
+  void* ptrs[] = {L.perm, L.pos, L.bs,  L.be,  L.cnt, L.fc,  L.gc,  L.tmp64, L.lb, L.lo, L.lh, L.ts,
+                  L.tbk,  L.ss,  L.sbk, L.sr,  L.sfi, L.sne, L.sps, L.sse,   L.work};
   for (void* q : ptrs)
     if (q) (void)dev_free(q, h->stream);
   L = bisim_lists{};

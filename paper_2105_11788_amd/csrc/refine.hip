@@ -44,8 +44,13 @@
 // barriers.
 #include <hip/hip_ext.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -376,7 +381,149 @@ bisim_status count_labels(bisim_lts* h, const int32_t* block, int64_t* out) {
   return BISIM_OK;
 }
 
+static bisim_status refine_run_impl(bisim_lts* h, int32_t* block_id);
+
+namespace {
+// ---------------------------------------------------------------------------
+// automatic engine choice: a cached tuner over (engine, grid)
+// ---------------------------------------------------------------------------
+constexpr int32_t kTuneMinStates = 200000;  // smaller LTSs: per-phase kernels, no trials
+constexpr int64_t kTuneIters = 96;          // iterations per trial
+
+std::string lts_tune_key(const bisim_lts* h) {
+  hipDeviceProp_t p;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&p, h->device) == hipSuccess) arch = p.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  int ln = 0, lm = 0;
+  for (int64_t v = h->n; v > 1; v >>= 1) ++ln;
+  for (int64_t v = h->m; v > 1; v >>= 1) ++lm;
+  char buf[256];
+  snprintf(buf, sizeof buf, "lts_%s_cu%d_n%d_m%d_u%d", arch.c_str(), h->num_cu, ln, lm,
+           h->uniform);
+  return buf;
+}
+
+std::string lts_tune_path() {
+  const char* e = getenv("BISIM_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* home = getenv("HOME");
+  return std::string(home && *home ? home : "/tmp") + "/.cache/bisim_tune.txt";
+}
+
+bool lts_tune_lookup(const std::string& key, int* engine, int* grid) {
+  FILE* f = fopen(lts_tune_path().c_str(), "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[256];
+    int e = 0, g = 0;
+    float us = 0.f;
+    if (sscanf(line, "%255s %d %d %f", k, &e, &g, &us) == 4 && key == k && (e == 2 || e == 3) &&
+        g > 0) {
+      *engine = e;
+      *grid = g;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void lts_tune_store(const std::string& key, int engine, int grid, float us) {
+  const std::string path = lts_tune_path();
+  const std::string dir = path.substr(0, path.find_last_of('/'));
+  for (size_t i = 1; i <= dir.size(); ++i)
+    if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %.4f\n", key.c_str(), engine, grid, us);
+  fclose(f);
+}
+}  // namespace
+
+// Engine and grid of an automatic run: the per-phase kernels for small LTSs
+// (and for the learned policy, Algorithm 2, traced runs and the
+// allocation-free entry point); otherwise the cached choice for this device
+// and size class, else the fastest of a few candidates timed on the first
+// kTuneIters iterations of this LTS (each timed twice, the second kept).
+static bisim_status choose_engine(bisim_lts* h, int* engine, int* grid) {
+  const int cu = h->num_cu > 0 ? h->num_cu : 1;
+  *engine = 2;
+  *grid = h->grid;
+  const bool learned = h->policy == 1 && h->policy_w;
+  if (h->n < kTuneMinStates || learned || h->algorithm == 2 || h->trace_cap > 0 ||
+      h->first_splitter >= 0 || h->iter_limit > 0 || h->profile_every > 0 || arena_active() ||
+      h->start_override)
+    return BISIM_OK;
+  const std::string key = lts_tune_key(h);
+  int e = 0, g = 0;
+  if (lts_tune_lookup(key, &e, &g)) {
+    *engine = e;
+    *grid = h->grid > 0 ? h->grid : g;
+    return BISIM_OK;
+  }
+  struct Cand {
+    int engine, grid;
+  };
+  const Cand cands[] = {{2, cu * 4}, {2, cu * 8}, {2, cu * 16}, {3, cu * 4}, {3, cu * 8}};
+  const int saved_engine = h->engine, saved_grid = h->grid;
+  const int64_t saved_limit = h->iter_limit;
+  float best = 1e30f;
+  int be = 2, bg = cu * 8;
+  bisim_status rc = BISIM_OK;
+  for (const Cand& c : cands) {
+    h->engine = c.engine;
+    h->grid = c.grid;
+    h->iter_limit = kTuneIters;
+    float us = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      const bisim_status r = refine_run_impl(h, nullptr);
+      if (r != BISIM_OK && r != BISIM_E_ITERCAP) {
+        rc = r;
+        break;
+      }
+      const int64_t its = r == BISIM_OK ? h->last_iters : kTuneIters;
+      us = (float)(h->t_alg_ms * 1000.0 / (double)(its > 0 ? its : 1));
+    }
+    if (rc != BISIM_OK) break;
+    if (us < best) {
+      best = us;
+      be = c.engine;
+      bg = c.grid;
+    }
+  }
+  h->engine = saved_engine;
+  h->grid = saved_grid;
+  h->iter_limit = saved_limit;
+  if (rc != BISIM_OK) return rc;
+  clear_error();
+  lts_tune_store(key, be, bg, best);
+  *engine = be;
+  *grid = h->grid > 0 ? h->grid : bg;
+  return BISIM_OK;
+}
+
 bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
+  if (h->engine != 0) {
+    h->run_engine = h->engine;
+    return refine_run_impl(h, block_id);
+  }
+  int engine = 2, grid = 0;
+  BISIM_TRY(choose_engine(h, &engine, &grid));
+  const int saved_grid = h->grid;
+  h->engine = engine;
+  h->grid = grid;
+  h->run_engine = engine;
+  const bisim_status rc = refine_run_impl(h, block_id);
+  h->engine = 0;
+  h->grid = saved_grid;
+  return rc;
+}
+
+static bisim_status refine_run_impl(bisim_lts* h, int32_t* block_id) {
   hipStream_t st = h->stream;
   const int32_t n = h->n;
   const bool learned = h->policy == 1 && h->policy_w;
@@ -444,12 +591,14 @@ bisim_status refine_run(bisim_lts* h, int32_t* block_id) {
       return BISIM_E_DEVICE;
     }
     int grid = h->grid > 0 ? h->grid : cu;
+    h->run_grid = grid;
     if (grid > per_cu * cu) grid = per_cu * cu;
     void* args[] = {&a};
     const void* fn = learned ? (const void*)k_persistent<true> : (const void*)k_persistent<false>;
     BISIM_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPT), args, lds, st));
   } else {
     int grid = h->grid > 0 ? h->grid : cu * 8;  // 2048 workgroups on MI355X: best of a 128..2048 sweep
+    h->run_grid = grid;
     const bool prof = h->profile_every > 0;
     if (prof && !h->pev) {
       h->pev = new (std::nothrow) hipEvent_t[8 * 256];

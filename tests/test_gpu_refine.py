@@ -396,6 +396,48 @@ def test_member_list_engine_runs_algorithm3_only(B):
         assert st.iterations == 8
 
 
+def test_automatic_engine_tunes_once_and_caches(B, tmp_path, monkeypatch):
+    """Engine 0 on an LTS of >= 200k states times engines 2 and 3 at a few
+    grid sizes on its first iterations, caches the winner, and reuses it;
+    the result is the oracle's either way."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("BISIM_TUNE_CACHE", str(cache))
+    P = gen.planted_quotient(q=12000, deg_mean=8.0, K=16, seed=4)
+    assert P.n >= 200_000
+    ks, nb = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)
+    src, lab, dst, _ = dev(P)
+    for rep in range(2):
+        with B.LTS(src, lab, dst, P.n, P.K) as h:
+            blk, st = h.run()
+            eng, grid = h.run_config()
+        assert (blk.numpy() == ks).all() and st.blocks == nb
+        assert eng in (2, 3) and grid > 0
+        lines = [l for l in cache.read_text().splitlines() if l.startswith("lts_")]
+        assert len(lines) == 1  # tuned on the first handle, cached for the second
+        assert lines[0].split()[1] == str(eng)
+
+
+def test_member_list_engine_graph_replays_match_eager_launches(B):
+    """Engine 3 replays captured graphs of 32 iterations unless kernel timing
+    is on, which launches kernel by kernel: both give the same partition,
+    iteration count and splitter trace, over repeated runs on one handle
+    (each graph replayed many times, with eager runs in between)."""
+    L = gen.planted_quotient(q=3000, deg_mean=6.0, K=8, seed=21)
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst)
+    src, lab, dst, _ = dev(L)
+    res = []
+    with B.LTS(src, lab, dst, L.n, L.K) as h:
+        h.set_option(B.OPT_ENGINE, 3)
+        tr = h.set_trace(1 << 16)
+        for prof in (0, 1, 0, 7, 0):
+            h.set_option(B.OPT_PROFILE_EVERY, prof)
+            blk, st = h.run()
+            res.append((blk.numpy(), st.iterations, tr[0].numpy()[:st.iterations].copy()))
+    assert st.iterations > 64  # more than one replay of the graph
+    for b, it, c in res:
+        assert (b == ks).all() and it == res[0][1] and (c == res[0][2]).all()
+
+
 def test_algorithm2_needs_one_action(B):
     L = gen.figure2()  # two actions
     src, lab, dst, _ = dev(L)
