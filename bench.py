@@ -212,7 +212,8 @@ def stored_traffic(kernel: str, workload: str):
                 key, val = line.split(":", 1)
                 kv[key.strip()] = val.strip()
     src = os.path.join(ROOT, "paper_2105_11788_amd", "csrc")
-    if kv.get("source_sha1") != profsum.source_digest(src):
+    files = [f for f in kv.get("source_files", "").split(",") if f] or None
+    if kv.get("source_sha1") != profsum.source_digest(src, files):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])

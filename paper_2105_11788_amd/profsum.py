@@ -6,7 +6,7 @@ traffic).
     python -m paper_2105_11788_amd.profsum pmc    COUNTER_COLLECTION.csv
     python -m paper_2105_11788_amd.profsum traffic --kernel REGEX \\
         --fetch A.csv --write B.csv --copy-fetch C.csv --copy-write D.csv \\
-        --copy-bytes N --sources DIR
+        --copy-bytes N --sources DIR [--source-files a.hip,b.h]
 
 `traffic` scales each counter by what it reads for a plain copy of N bytes
 (each byte read once and written once), and prints `key: value` lines that
@@ -29,14 +29,15 @@ def short(name: str, width: int = 60) -> str:
     return name if len(name) <= width else name[: width - 3] + "..."
 
 
-def source_digest(root: str) -> str:
-    """sha1 over the kernel sources (names and contents, sorted)."""
+def source_digest(root: str, files: list[str] | None = None) -> str:
+    """sha1 over kernel sources (names and contents, sorted): the listed files
+    of `root`, else every .hip and .h file there."""
     h = hashlib.sha1()
-    for f in sorted(os.listdir(root)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(root, f), "rb") as fh:
-                h.update(fh.read())
+    names = files if files else [f for f in os.listdir(root) if f.endswith((".hip", ".h"))]
+    for f in sorted(names):
+        h.update(f.encode())
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -95,8 +96,11 @@ def cmd_traffic(a) -> None:
     kib = a.copy_bytes / 1024.0
     ff, fw = kib / cf, kib / cw
     traffic = (fetch * ff + write * fw) * 1024.0
+    files = [f for f in a.source_files.split(",") if f] if a.source_files else None
     print(f"kernel_regex: {a.kernel}")
-    print(f"source_sha1: {source_digest(a.sources)}")
+    if files:
+        print(f"source_files: {','.join(sorted(files))}")
+    print(f"source_sha1: {source_digest(a.sources, files)}")
     print(f"fetch_dispatches: {nf}")
     print(f"fetch_kib_per_dispatch: {fetch:.3f}")
     print(f"write_dispatches: {nw}")
@@ -126,6 +130,9 @@ def main(argv=None) -> None:
     s.add_argument("--kernel", required=True)
     s.add_argument("--copy-bytes", type=int, default=1 << 30)
     s.add_argument("--sources", default=os.path.join(os.path.dirname(__file__), "csrc"))
+    s.add_argument("--source-files", default="",
+                   help="comma-separated files of --sources that the kernel is built from "
+                        "(default: all of them)")
     s.set_defaults(fn=cmd_traffic)
     a = p.parse_args(argv)
     a.fn(a)

@@ -48,3 +48,13 @@ def test_source_digest_tracks_changes(tmp_path):
     d1 = profsum.source_digest(str(tmp_path))
     (tmp_path / "k.hip").write_text("b")
     assert profsum.source_digest(str(tmp_path)) != d1
+
+
+def test_source_digest_of_listed_files_ignores_the_others(tmp_path):
+    (tmp_path / "k.hip").write_text("a")
+    (tmp_path / "other.hip").write_text("x")
+    d1 = profsum.source_digest(str(tmp_path), ["k.hip"])
+    (tmp_path / "other.hip").write_text("y")
+    assert profsum.source_digest(str(tmp_path), ["k.hip"]) == d1
+    (tmp_path / "k.hip").write_text("b")
+    assert profsum.source_digest(str(tmp_path), ["k.hip"]) != d1
