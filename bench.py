@@ -118,14 +118,16 @@ def lists_bytes(n: int, iters: int, w: dict):
     its read and its write) times the run's work totals:
       mark     8 (range of C) + 12 per member (perm, in_ptr pair)
                + 52 per in-transition (source, rank, the source's block and
-                 range, mark-word and touched-word atomics) + 8 per touched
-                 state (list entry) + 12 per listed segment (entry)
+                 range, mark-word and touched-word atomics) + 16 per touched
+                 state (list entry, its block's touched-count atomic)
+                 + 12 per listed segment (entry)
       compare  24 per touched state (list entry, own and leader mark
                words) + 56 per split state (bid, rank and split-flag
-               atomics, list entry) + 12 per segment + 12 per member visited
-               (perm, touched word)
-      relabel  24 per touched state (list entry; mark word and touched word
-               cleared) + 96 per split state (list entry, its block's bid,
+               atomics, list entry) + 24 per segment (entry, its block's
+               touched count and range) + 12 per member visited (perm,
+               touched word; only blocks with an untouched member)
+      relabel  32 per touched state (list entry and its block; mark word,
+               touched word and touched count cleared) + 96 per split state (list entry, its block's bid,
                range and count, position, label store, front/tail counters,
                tail state and its flag, pair store, four list stores)
       swap     44 per split state (seven list loads, pair load, four
@@ -133,11 +135,11 @@ def lists_bytes(n: int, iters: int, w: dict):
                counters, unstable bits)
     Returns a list of four floats (bytes per launch)."""
     it = max(1, iters - 1)  # the final pass does no work
-    mark = 8 * it + 12 * w["members"] + 52 * w["in_transitions"] + 8 * w["touched"] \
+    mark = 8 * it + 12 * w["members"] + 52 * w["in_transitions"] + 16 * w["touched"] \
         + 12 * w["segments"]
-    comp = 24 * w["touched"] + 56 * w["split_states"] + 12 * w["segments"] \
+    comp = 24 * w["touched"] + 56 * w["split_states"] + 24 * w["segments"] \
         + 12 * w["member_visits"]
-    rel = 24 * w["touched"] + 96 * w["split_states"]
+    rel = 32 * w["touched"] + 96 * w["split_states"]
     swp = 44 * w["split_states"] + 64 * w["split_blocks"]
     return [mark / it, comp / it, rel / it, swp / it]
 

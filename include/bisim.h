@@ -160,7 +160,7 @@ const char* bisim_last_error(void);
  *                           splitter's members and in-transitions and the
  *                           states they touch, not n; Algorithm 3 with the
  *                           plain policy only (else BISIM_E_UNSUPPORTED at
- *                           coarsest_partition); about 84 more bytes of
+ *                           coarsest_partition); about 88 more bytes of
  *                           device memory per state, allocated on first use.
  *   BISIM_OPT_COUNT_WORK    0 (default) or 1: engine 3 accumulates work totals
  *                           over the run (bisim_get_work).
@@ -235,9 +235,10 @@ bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* sample
 /*
  * bisim_get_work — work totals of the last run with BISIM_OPT_COUNT_WORK set
  * (engine 3): out (host, 8 entries) = members of the splitters, their
- * in-transitions, touched states, listed member segments, members of
- * leader-touched blocks visited, split states, split blocks, iterations in
- * which something split.  Zeros for other engines.
+ * in-transitions, touched states, listed member segments, members visited
+ * of leader-touched blocks that have an untouched member, split states,
+ * split blocks, iterations in which something split.  Zeros for other
+ * engines.
  * Errors: BISIM_E_INVALID.
  */
 bisim_status bisim_get_work(bisim_lts* h, int64_t* out);

@@ -152,7 +152,7 @@ __device__ __forceinline__ uint32_t hit_mask(const int32_t* blk, uint32_t base0,
 // device arrays of the member-list engine (engine 3), allocated on first use
 struct bisim_lists {
   int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr;
-  int32_t *cnt = nullptr, *fc = nullptr, *gc = nullptr;
+  int32_t *cnt = nullptr, *fc = nullptr, *gc = nullptr, *tcn = nullptr;
   uint64_t* tmp64 = nullptr;
   int32_t *lb = nullptr, *lo = nullptr, *lh = nullptr;
   int32_t *ts = nullptr, *tbk = nullptr;

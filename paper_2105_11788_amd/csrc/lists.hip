@@ -11,15 +11,16 @@
 //                unstable bit and search the next set bit (one wave); visit
 //                the in-transitions of C's members (perm[bs[C] .. be[C]))
 //                and set their mark bits; the first touch of a state sets
-//                its touched bit and lists it with its block, and a touched
-//                leader of a block with more than one state appends the
-//                block's member segments to a list.
+//                its touched bit, counts it for its block and lists it with
+//                its block, and a touched leader of a block with more than
+//                one state appends the block's member segments to a list.
 //   K  compare   listed touched states whose marks differ from their
 //                leader's split; so do the untouched members of the listed
-//                blocks.  A split state bids for its block's new leader
-//                (64-bit max of (epoch, ~state): the smallest state wins),
-//                takes its rank within the block's split part, sets its split
-//                bit and is listed.
+//                blocks (none when the block's count equals its size).  A
+//                split state bids for its block's new leader (64-bit max of
+//                (epoch, ~state): the smallest state wins), takes its rank
+//                within the block's split part, sets its split bit and is
+//                listed.
 //   R  relabel   every split state takes its block's winning bid as label;
 //                the split part will be the tail [ne, be) of the block's
 //                range: split states in front of ne take an index, and the
@@ -70,6 +71,7 @@ struct LArgs {
   uint64_t* us;   // summary of ub
   uint64_t* nlw;  // bids
   int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc;
+  int32_t* tcn;  // per label: members first touched this iteration (0 between iterations)
   uint64_t* tmp64;
   int32_t *lb, *lo, *lh;  // listed segments: block, first and end position
   uint32_t lcap;
@@ -256,6 +258,7 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t kofs) {
         const uint64_t tbit = 1ull << (s & 63);
         const uint64_t old = atomicOr((unsigned long long*)&a.tb[s >> 6], (unsigned long long)tbit);
         first = !(old & tbit);
+        if (first) atomicAdd(&a.tcn[b], 1);
         // a touched leader of a one-state block has no untouched member
         lead = first && b == s && hi_ > lo_ + 1 && hi_ <= a.n;
       }
@@ -327,10 +330,13 @@ __global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t kofs) {
       }
     }
   } else {
-    // untouched members of the listed blocks: one segment per wave and step
+    // untouched members of the listed blocks: one segment per wave and step;
+    // a block all of whose members were touched has none (its count of first
+    // touches equals its size) and is skipped
     for (uint32_t j = p.gwave - half; j < nL && j < a.lcap; j += p.gwaves - half) {
       const int32_t b = a.lb[j];
       const uint32_t lo = (uint32_t)a.lo[j], hi = (uint32_t)a.lh[j];
+      if ((uint32_t)a.tcn[b] == (uint32_t)(a.be[b] - a.bs[b])) continue;
       const uint32_t cntm = hi > lo ? min(kSeg, hi - lo) : 0u;
       count_work(a, 4, cntm);
       for (uint32_t i0 = 0; i0 < cntm; i0 += kWave) {
@@ -409,9 +415,11 @@ __global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t kofs) {
       }
     }
   } else {
-    // clear the marks and touched bits of this iteration's touched states
+    // clear the marks, touched bits and touched counts of this iteration's
+    // touched states
     for (uint32_t i = (p.gwave - half) * kWave + lane(); i < nT; i += (p.gwaves - half) * kWave) {
       const int32_t s = a.ts[i];
+      a.tcn[a.tbk[i]] = 0;  // every touched state of the block clears it
       if (a.uniform) {
         a.mw[s] = 0;
       } else {
@@ -497,6 +505,7 @@ __global__ void k_l_zero(LArgs a) {
     a.cnt[s] = 0;
     a.fc[s] = 0;
     a.gc[s] = 0;
+    a.tcn[s] = 0;
   }
   if (p.gtid < 8) a.work[p.gtid] = 0;
 }
@@ -550,6 +559,7 @@ bisim_status lists_alloc(bisim_lts* h) {
   BISIM_TRY(lalloc(&L.cnt, n, s));
   BISIM_TRY(lalloc(&L.fc, n, s));
   BISIM_TRY(lalloc(&L.gc, n, s));
+  BISIM_TRY(lalloc(&L.tcn, n, s));
   BISIM_TRY(lalloc(&L.tmp64, n, s));
   BISIM_TRY(lalloc(&L.lb, seg_capacity(n), s));
   BISIM_TRY(lalloc(&L.lo, seg_capacity(n), s));
@@ -589,6 +599,7 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
   a.cnt = L.cnt;
   a.fc = L.fc;
   a.gc = L.gc;
+  a.tcn = L.tcn;
   a.tmp64 = L.tmp64;
   a.lb = L.lb;
   a.lo = L.lo;
@@ -760,7 +771,7 @@ void lists_free(bisim_lts* h) {
     (void)hipStreamDestroy(L.own);
   }
   void* ptrs[] = {L.perm, L.pos, L.bs,  L.be,  L.cnt, L.fc,  L.gc,  L.tmp64, L.lb, L.lo, L.lh, L.ts,
-                  L.tbk,  L.ss,  L.sbk, L.sr,  L.sfi, L.sne, L.sps, L.sse,   L.work};
+                  L.tbk,  L.ss,  L.sbk, L.sr,  L.sfi, L.sne, L.sps, L.sse,   L.work, L.tcn};
   for (void* q : ptrs)
     if (q) (void)dev_free(q, h->stream);
   L = bisim_lists{};
