@@ -155,13 +155,16 @@ def batch_bytes(sizes, st, mask_bytes: int):
       member lists 56 + mask per state at set-up (labels, marks, bids,
                    counters, ranges, member list and positions)
                    + per iteration 8 (splitter range) + 12 per member (perm,
-                   in_ptr pair) + (8 + 2 mask) per in-transition (source,
-                   rank, mark atomic) + (4 + 3 mask) per touched state (block;
-                   own and leader marks; marks cleared) + 8 per touched
-                   leader listed (range) + 4 per member visited (perm)
-                   + 104 per split state (bid and rank atomics; bid, range,
-                   count, position, tail state, counters, pair, label; swap)
-                   + 24 per split block (ranges and counters)
+                   in_ptr pair; those of the next splitter's first 64
+                   members are prefetched and not loaded again unless the
+                   iteration split something, which is not counted)
+                   + (8 + 2 mask) per in-transition (source, rank, mark
+                   atomic) + (12 + 3 mask) per touched state (block and the
+                   range it would lead; own and leader marks; marks cleared)
+                   + 4 per member visited (perm) + 100 per split state (bid
+                   and rank atomics; bid, range end, count, position, tail
+                   state, counters, pair, label; swap) + 24 per split block
+                   (ranges and counters)
     Bitmaps and per-iteration lists live in LDS for the member-list tier too
     (when they fit) and count nothing.  sizes: instance sizes; the member-list
     tier holds the st["global_instances"] largest."""
@@ -173,7 +176,7 @@ def batch_bytes(sizes, st, mask_bytes: int):
     lds = 8.0 * w0[1] + 8.0 * w0[2]
     mk = float(mask_bytes)
     lists = (56 + mk) * n_list + 8.0 * w1[0] + 12.0 * w1[1] + (8 + 2 * mk) * w1[2] \
-        + (4 + 3 * mk) * w1[3] + 8.0 * w1[4] + 4.0 * w1[5] + 104.0 * w1[6] + 24.0 * w1[7]
+        + (12 + 3 * mk) * w1[3] + 4.0 * w1[5] + 100.0 * w1[6] + 24.0 * w1[7]
     return 8.0 * n_all + lds + lists
 
 

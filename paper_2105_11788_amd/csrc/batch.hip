@@ -56,7 +56,7 @@ struct bisim_batch {
   int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr, *cnt = nullptr,
           *fc = nullptr, *gc = nullptr, *tmp = nullptr, *rk = nullptr, *fi = nullptr,
           *ob = nullptr, *nev = nullptr, *ltl = nullptr, *tlb = nullptr, *se = nullptr,
-          *sgs = nullptr;
+          *sgs = nullptr, *llo = nullptr, *lsz = nullptr;
   uint64_t *sf = nullptr, *us = nullptr, *tmp64 = nullptr;
   uint32_t* iters_d = nullptr;  // [count]
   uint32_t* ctl_d = nullptr;    // [0] queue head, [1] error
@@ -99,7 +99,8 @@ struct BArgs {
   uint64_t* lt;
   int32_t* tl;
   int32_t* sl;
-  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ob, *nev, *ltl, *tlb, *se, *sgs;
+  int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ob, *nev, *ltl, *tlb, *se, *sgs,
+      *llo, *lsz;
   uint64_t *sf, *us, *tmp64;
   int32_t* out;
   uint32_t* iters;
@@ -386,12 +387,17 @@ __device__ __forceinline__ uint32_t wg_refine(const BArgs& a, Shared& sh, WArr<M
 // global-memory round trips, so the layout keeps that chain short: the
 // unstable, touched and split bitmaps (and the unstable summary) sit in LDS
 // when they fit beside a minimum of list space, and so do the per-iteration
-// lists (touched states with their block, touched leaders, split states with
-// everything the later phases need); list entries beyond the LDS capacity
-// spill to per-instance global arrays.  Ranks within a block's split part are
-// taken when the split is found, so the relabel and the search for staying
-// states in the tail run in one phase, and the staying state found for a
-// tail position is stored with it, so the swap is one more round trip.
+// lists (touched states with their block, touched leaders with their block's
+// range, split states with everything the later phases need); list entries
+// beyond the LDS capacity spill to per-instance global arrays.  A state's
+// block and, should it lead that block, the block's range are loaded together
+// at its first touch.  The wave that finds the next splitter also loads its
+// range and its first members' in-transition ranges into LDS; when nothing
+// splits in the iteration (most iterations) the next one starts marking from
+// there.  Ranks within a block's split part are taken when the split is found,
+// so the relabel and the search for staying states in the tail run in one
+// phase, and the staying state found for a tail position is stored with it,
+// so the swap is one more round trip.
 struct GList {
   int32_t* perm;    // [n] states ordered by block
   int32_t* pos;     // [n] position of each state in perm
@@ -402,9 +408,9 @@ struct GList {
   int32_t* gc;      // [n] per label: staying states found in the tail
   uint64_t* tmp64;  // [n] per tail position: (staying state << 32) | its position, by index
   // global spill of the lists (entry i >= the LDS capacity)
-  int32_t *ts, *tb_, *lb, *ss, *sb_, *sr, *sf_, *sn, *sp, *se, *sgs;
+  int32_t *ts, *tb_, *lb, *llo, *lsz, *ss, *sb_, *sr, *sf_, *sn, *sp, *se, *sgs;
   uint64_t* sf;     // [ceil(n/64)] split flags (global fallback)
-  uint64_t* sg;     // [ceil(n/64)] labels of one-state blocks (global fallback)
+  uint64_t* ml;     // [ceil(n/64)] labels of blocks with more than one state (global fallback)
   uint64_t* us;     // [ceil(n/4096)] summary of the unstable bitmap (global fallback)
 };
 
@@ -438,10 +444,15 @@ __device__ __forceinline__ void wg_unstable_set(uint64_t* ub, uint64_t* us, uint
 }
 
 // bytes of LDS per unit of list capacity: touched (state, block), touched
-// leader, split (state, block, rank, front index, tail start, position, end,
-// start of the block's range)
-constexpr uint32_t kListBytes = 4u * (2 + 1 + 8);
+// leader (state, first position, size), split (state, block, rank, front
+// index, tail start, position, end, start of the block's range)
+constexpr uint32_t kListBytes = 4u * (2 + 3 + 8);
 constexpr uint32_t kMinListCap = 256;
+// the next splitter, prefetched: two slots by iteration parity, each a header
+// (label, first position, size, valid) and the in-transition ranges (first
+// edge, count) of its first kWave members
+constexpr uint32_t kPfWords = 4u + 2u * kWave;
+constexpr uint32_t kPfBytes = 4u * 2u * kPfWords;
 
 // The refinement loop of one instance by one workgroup, member-list tier.
 // Same phases and the same splitter sequence as wg_refine.
@@ -452,17 +463,18 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t wid = tid / kWave, nwav = nthr / kWave;
   const uint32_t nw = (n + 63u) >> 6, nsw = (nw + 63u) >> 6;
-  // LDS: bitmaps first (when they fit beside kMinListCap list entries), then lists
+  // LDS: bitmaps first (when they fit beside the prefetch slots and
+  // kMinListCap list entries), the prefetch slots, then lists
   const uint32_t bm_bytes = 8u * (4u * nw + nsw);
-  const bool bm_lds = bm_bytes + kMinListCap * kListBytes <= lds_bytes;
-  uint64_t *ub, *tb, *sf, *sg, *us;
+  const bool bm_lds = bm_bytes + kPfBytes + kMinListCap * kListBytes <= lds_bytes;
+  uint64_t *ub, *tb, *sf, *ml, *us;
   char* lp = reinterpret_cast<char*>(lds);
   uint32_t lbytes = lds_bytes;
   if (bm_lds) {
     ub = lds;
     tb = lds + nw;
     sf = lds + 2 * nw;
-    sg = lds + 3 * nw;
+    ml = lds + 3 * nw;
     us = lds + 4 * nw;
     lp += bm_bytes;
     lbytes -= bm_bytes;
@@ -470,15 +482,23 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
     ub = gub;
     tb = gtb;
     sf = g.sf;
-    sg = g.sg;
+    ml = g.ml;
     us = g.us;
+  }
+  // the prefetch slots, when the LDS left holds them ([2][kPfWords])
+  const bool pf_on = lbytes >= kPfBytes;
+  uint32_t* pf = reinterpret_cast<uint32_t*>(lp);
+  if (pf_on) {
+    lp += kPfBytes;
+    lbytes -= kPfBytes;
   }
   const uint32_t cap = lbytes / kListBytes;
   int32_t* li = reinterpret_cast<int32_t*>(lp);
-  const LField Ts{li, g.ts}, Tb{li + cap, g.tb_}, Lb{li + 2 * cap, g.lb};
-  const LField Ss{li + 3 * cap, g.ss}, Sb{li + 4 * cap, g.sb_}, Sr{li + 5 * cap, g.sr},
-      Sf{li + 6 * cap, g.sf_}, Sn{li + 7 * cap, g.sn}, Sp{li + 8 * cap, g.sp},
-      Se{li + 9 * cap, g.se}, Sg{li + 10 * cap, g.sgs};
+  const LField Ts{li, g.ts}, Tb{li + cap, g.tb_}, Lb{li + 2 * cap, g.lb},
+      Llo{li + 3 * cap, g.llo}, Lsz{li + 4 * cap, g.lsz};
+  const LField Ss{li + 5 * cap, g.ss}, Sb{li + 6 * cap, g.sb_}, Sr{li + 7 * cap, g.sr},
+      Sf{li + 8 * cap, g.sf_}, Sn{li + 9 * cap, g.sn}, Sp{li + 10 * cap, g.sp},
+      Se{li + 11 * cap, g.se}, Sg{li + 12 * cap, g.sgs};
 
   // ---- initial state: blocks of the preprocessed partition, all unstable
   for (uint32_t s = tid; s < n; s += nthr) {
@@ -497,9 +517,10 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
     ub[q] = bits;
     tb[q] = 0;
     sf[q] = 0;
-    sg[q] = 0;
+    ml[q] = 0;
   }
   for (uint32_t q = tid; q < nsw; q += nthr) us[q] = 0;
+  if (pf_on && tid < 2) pf[tid * kPfWords + 3] = 0;
   if (tid == 0) {
     sh.cand[0] = n ? 0u : kNone;
     sh.cand[1] = kNone;
@@ -529,7 +550,7 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
       const uint32_t c = (uint32_t)g.cnt[b];
       g.bs[b] = (int32_t)run;
       g.be[b] = (int32_t)run;  // fill cursor, ends at the block's end
-      if (c == 1) atomicOr((unsigned long long*)&sg[b >> 6], 1ull << (b & 63));
+      if (c > 1) atomicOr((unsigned long long*)&ml[b >> 6], 1ull << (b & 63));
       run += c;
     }
   }
@@ -567,7 +588,11 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
     // The search runs on the last wave: marking a small splitter's
     // in-transitions falls to the first waves.  A state's first touch (its
     // touched bit set by this lane) lists it with its block, and a touched
-    // block leader is listed apart.
+    // leader of a block with more than one state is listed with the block's
+    // range.  The range of C and its first members' in-transition ranges come
+    // from the prefetch slot when the previous iteration filled it for C and
+    // split nothing.
+    uint32_t next = kNone;
     if (wid == nwav - 1) {
       const uint32_t w0 = C >> 6;
       const uint64_t bits = ub[w0] & ~(1ull << (C & 63));
@@ -576,7 +601,6 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
         if (bits == 0) atomicAnd((unsigned long long*)&us[w0 >> 6], ~(1ull << (w0 & 63)));
       }
       // C is the smallest unstable label: the next one is the next set bit
-      uint32_t next = kNone;
       for (uint32_t q = w0 >> 6; q < nsw; q += kWave) {
         const uint32_t qq = q + lane();
         uint64_t sv = qq < nsw ? us[qq] : 0ull;
@@ -603,11 +627,19 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
       sh.nL[par ^ 1] = 0;
     }
     {
-      const uint32_t cb = (uint32_t)g.bs[C];
-      uint32_t csz = (uint32_t)g.be[C] - cb;
-      if (cb > n || csz > n - cb) {  // never expected: report, visit nothing
-        sh.bad = 1;
-        csz = 0;
+      const uint32_t* pc = pf + par * kPfWords;  // filled in the previous iteration
+      const bool pre = pf_on && pc[3] != 0 && pc[0] == C;
+      uint32_t cb, csz;
+      if (pre) {
+        cb = pc[1];
+        csz = pc[2];
+      } else {
+        cb = (uint32_t)g.bs[C];
+        csz = (uint32_t)g.be[C] - cb;
+        if (cb > n || csz > n - cb) {  // never expected: report, visit nothing
+          sh.bad = 1;
+          csz = 0;
+        }
       }
       if (tid == 0) sM += csz;
       for (uint32_t i0 = wid * kWave; i0 < csz; i0 += nwav * kWave) {
@@ -615,9 +647,14 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
         const bool hit = i < csz;
         uint32_t beg = 0, deg = 0;
         if (hit) {
-          const uint32_t t = (uint32_t)g.perm[cb + i];
-          beg = a.in_ptr[s0 + t];
-          deg = a.in_ptr[s0 + t + 1] - beg;
+          if (pre && i0 == 0) {
+            beg = pc[4 + lane()];
+            deg = pc[4 + kWave + lane()];
+          } else {
+            const uint32_t t = (uint32_t)g.perm[cb + i];
+            beg = a.in_ptr[s0 + t];
+            deg = a.in_ptr[s0 + t + 1] - beg;
+          }
         }
         const uint32_t incl = wave_incl_scan_u32(deg);
         const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
@@ -636,7 +673,7 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
           const uint32_t ji = (uint32_t)__shfl((int)incl, (int)j, kWave);
           const uint32_t jd = (uint32_t)__shfl((int)deg, (int)j, kWave);
           bool first = false, lead = false;
-          int32_t s = 0, b = 0;
+          int32_t s = 0, b = 0, lo = 0, hi = 0;
           if (valid) {
             const uint32_t edge = jb + (ee - (ji - jd));
             s = a.in_src[edge] - (int32_t)s0;
@@ -647,10 +684,14 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
             const uint64_t old =
                 atomicOr((unsigned long long*)&tb[s >> 6], (unsigned long long)tbit);
             first = !(old & tbit);
-            if (first) {
-              b = blk[s];
-              // a touched leader of a one-state block has no untouched member
-              lead = (b == s) && !test_bit(sg, (uint32_t)s);
+            // a touched leader of a one-state block has no untouched member;
+            // a leader of a larger one is listed with its block's range,
+            // loaded beside its block id
+            lead = first && test_bit(ml, (uint32_t)s);
+            if (first) b = blk[s];
+            if (lead) {
+              lo = g.bs[s];
+              hi = g.be[s];
             }
           }
           const uint32_t ti = push_idx(&sh.nT[par], first);
@@ -659,8 +700,41 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
             *ent(Tb, cap, ti) = b;
           }
           const uint32_t li_ = push_idx(&sh.nL[par], lead);
-          if (lead) *ent(Lb, cap, li_) = s;
+          if (lead) {
+            *ent(Lb, cap, li_) = s;
+            *ent(Llo, cap, li_) = lo;
+            *ent(Lsz, cap, li_) = hi - lo;
+          }
         }
+      }
+    }
+    // prefetch for the next iteration (slot par ^ 1): the candidate found
+    // above, its range and its first kWave members' in-transition ranges.
+    // Valid only if the candidate stands and nothing splits in this iteration
+    // (then no range, member list or candidate changes); the split phase
+    // clears it otherwise.
+    if (pf_on && wid == nwav - 1) {
+      uint32_t* pn = pf + (par ^ 1) * kPfWords;
+      uint32_t ncb = 0, nsz = 0;
+      bool ok = false;
+      if (next != kNone) {
+        ncb = (uint32_t)g.bs[next];
+        nsz = (uint32_t)g.be[next] - ncb;
+        ok = ncb <= n && nsz <= n - ncb;
+      }
+      uint32_t beg = 0, deg = 0;
+      if (ok && lane() < nsz) {
+        const uint32_t t = (uint32_t)g.perm[ncb + lane()];
+        beg = a.in_ptr[s0 + t];
+        deg = a.in_ptr[s0 + t + 1] - beg;
+      }
+      pn[4 + lane()] = beg;
+      pn[4 + kWave + lane()] = deg;
+      if (lane() == 0) {
+        pn[0] = next;
+        pn[1] = ncb;
+        pn[2] = nsz;
+        pn[3] = ok ? 1u : 0u;
       }
     }
     __syncthreads();
@@ -704,7 +778,8 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
       }
       // members of the blocks whose leader was touched, 64 blocks at a time:
       // their member slots are spread over all waves by a prefix sum of the
-      // block sizes (a block can hold most of the instance)
+      // block sizes (a block can hold most of the instance); each listed
+      // leader carries its block's range
       const uint32_t nL = sh.nL[par];
       for (uint32_t j0 = 0; j0 < nL; j0 += kWave) {
         const uint32_t j = j0 + lane();
@@ -712,8 +787,8 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
         uint32_t lo = 0, sz = 0;
         if (j < nL) {
           b = *ent(Lb, cap, j);
-          lo = (uint32_t)g.bs[b];
-          sz = (uint32_t)g.be[b] - lo;
+          lo = (uint32_t)*ent(Llo, cap, j);
+          sz = (uint32_t)*ent(Lsz, cap, j);
         }
         const uint32_t incl = wave_incl_scan_u32(sz);
         const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
@@ -888,8 +963,8 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
             g.cnt[b] = 0;
             g.fc[b] = 0;
             g.gc[b] = 0;
-            if (ev[u] - ne == 1) atomicOr((unsigned long long*)&sg[s >> 6], 1ull << (s & 63));
-            if (ne - gv[u] == 1) atomicOr((unsigned long long*)&sg[b >> 6], 1ull << (b & 63));
+            if (ev[u] - ne > 1) atomicOr((unsigned long long*)&ml[s >> 6], 1ull << (s & 63));
+            if (ne - gv[u] == 1) atomicAnd((unsigned long long*)&ml[b >> 6], ~(1ull << (b & 63)));
             wg_unstable_set(ub, us, (uint32_t)b);
             wg_unstable_set(ub, us, (uint32_t)s);
             best = min(best, (uint32_t)b);
@@ -903,6 +978,7 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
         if (nS > 0) {
           wg_unstable_set(ub, us, C);
           atomicMin(&sh.cand[par ^ 1], C);
+          if (pf_on) pf[(par ^ 1) * kPfWords + 3] = 0;  // ranges changed: the prefetch is stale
         }
         sh.cand[par] = kNone;
       }
@@ -972,6 +1048,9 @@ __global__ void __launch_bounds__(WG) k_batch(BArgs a) {
       g.ts = T;
       g.tb_ = a.tlb + s0;
       g.lb = a.ltl + s0;
+      g.llo = a.llo + s0;
+      g.lsz = a.lsz + s0;
+      g.sgs = a.sgs + s0;
       g.ss = S;
       g.sb_ = a.ob + s0;
       g.sr = a.rk + s0;
@@ -979,9 +1058,8 @@ __global__ void __launch_bounds__(WG) k_batch(BArgs a) {
       g.sn = a.nev + s0;
       g.sp = a.tmp + s0;
       g.se = a.se + s0;
-      g.sgs = a.sgs + s0;
       g.sf = a.sf + b0;
-      g.sg = a.lt + b0;
+      g.ml = a.lt + b0;
       g.us = a.us + b0;
       its = wg_refine_lists<MaskT>(a, sh, a.blk + s0, reinterpret_cast<MaskT*>(a.mw) + s0,
                                    a.nlb + s0, g, lds, a.lds_bytes, a.ub + b0, a.tb + b0, s0, n);
@@ -1060,7 +1138,7 @@ void free_batch(bisim_batch* b) {
                   b->tb,      b->lt,       b->tl,      b->sl,  b->iters_d, b->ctl_d, b->perm,
                   b->pos,     b->bs,       b->be,      b->cnt, b->fc,      b->gc,    b->tmp,
                   b->rk,      b->fi,       b->ltl,     b->sf,  b->us,      b->ob,    b->nev,
-                  b->tlb,     b->se,       b->tmp64,   b->sgs,    b->work_d};
+                  b->tlb,     b->se,       b->tmp64,   b->sgs,    b->work_d, b->llo, b->lsz};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->u) lts_destroy(b->u);
@@ -1104,6 +1182,8 @@ BArgs make_args(bisim_batch* b, int32_t* out) {
   a.tlb = b->tlb;
   a.se = b->se;
   a.sgs = b->sgs;
+  a.llo = b->llo;
+  a.lsz = b->lsz;
   a.tmp64 = b->tmp64;
   a.sf = b->sf;
   a.us = b->us;
@@ -1381,7 +1461,8 @@ bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* 
         (st = dmalloc(&b->ob, (size_t)N)) || (st = dmalloc(&b->nev, (size_t)N)) ||
         (st = dmalloc(&b->us, BW)) || (st = dmalloc(&b->tlb, (size_t)N)) ||
         (st = dmalloc(&b->se, (size_t)N)) || (st = dmalloc(&b->tmp64, (size_t)N)) ||
-        (st = dmalloc(&b->sgs, (size_t)N)) ||
+        (st = dmalloc(&b->sgs, (size_t)N)) || (st = dmalloc(&b->llo, (size_t)N)) ||
+        (st = dmalloc(&b->lsz, (size_t)N)) ||
         (st = dmalloc(&b->iters_d, count)) || (st = dmalloc(&b->ctl_d, 2)) ||
         (st = dmalloc(&b->work_d, 16)))
       break;

@@ -87,5 +87,5 @@ def test_batch_bytes_model():
     got = bench.batch_bytes(sizes, st, 4)
     n_list = 20000 + 5000  # the two largest instances take the member-list tier
     exp = 8 * sum(sizes) + 8 * 40 + 8 * 90 + 60 * n_list + 8 * 100 + 12 * 30 + 16 * 200 \
-        + 16 * 80 + 8 * 10 + 4 * 500 + 104 * 20 + 24 * 4
+        + 24 * 80 + 4 * 500 + 100 * 20 + 24 * 4
     assert got == pytest.approx(exp)
