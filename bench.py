@@ -152,19 +152,22 @@ def batch_bytes(sizes, st, mask_bytes: int):
       LDS tier     per iteration only the in-transitions of the splitter
                    leave LDS: 8 per splitter member (in_ptr pair) + 8 per
                    in-transition (source, action rank)
-      member lists 56 + mask per state at set-up (labels, marks, bids,
-                   counters, ranges, member list and positions)
-                   + per iteration 8 (splitter range) + 12 per member (perm,
-                   in_ptr pair; those of the next splitter's first 64
+      member lists 72 + mask per state at set-up (labels, marks, bids,
+                   counters, ranges, member list, positions, in-transition
+                   ranges by position)
+                   + per iteration 8 (splitter range) + 8 per member (its
+                   in-transition range; those of the next splitter's first 64
                    members are prefetched and not loaded again unless the
                    iteration split something, which is not counted)
                    + (8 + 2 mask) per in-transition (source, rank, mark
                    atomic) + (12 + 3 mask) per touched state (block and the
                    range it would lead; own and leader marks; marks cleared)
-                   + 4 per member visited (perm) + 100 per split state (bid
+                   + 4 per member visited (perm) + 132 per split state (bid
                    and rank atomics; bid, range end, count, position, tail
-                   state, counters, pair, label; swap) + 24 per split block
-                   (ranges and counters)
+                   state, counters, pair, label; swap of the states and of
+                   their two in-transition ranges, counted for every split
+                   state though only those in front of the tail swap)
+                   + 24 per split block (ranges and counters)
     Bitmaps and per-iteration lists live in LDS for the member-list tier too
     (when they fit) and count nothing.  sizes: instance sizes; the member-list
     tier holds the st["global_instances"] largest."""
@@ -175,8 +178,8 @@ def batch_bytes(sizes, st, mask_bytes: int):
     w0, w1 = st["work"][0], st["work"][1]
     lds = 8.0 * w0[1] + 8.0 * w0[2]
     mk = float(mask_bytes)
-    lists = (56 + mk) * n_list + 8.0 * w1[0] + 12.0 * w1[1] + (8 + 2 * mk) * w1[2] \
-        + (12 + 3 * mk) * w1[3] + 4.0 * w1[5] + 100.0 * w1[6] + 24.0 * w1[7]
+    lists = (72 + mk) * n_list + 8.0 * w1[0] + 8.0 * w1[1] + (8 + 2 * mk) * w1[2] \
+        + (12 + 3 * mk) * w1[3] + 4.0 * w1[5] + 132.0 * w1[6] + 24.0 * w1[7]
     return 8.0 * n_all + lds + lists
 
 

@@ -57,7 +57,7 @@ struct bisim_batch {
           *fc = nullptr, *gc = nullptr, *tmp = nullptr, *rk = nullptr, *fi = nullptr,
           *ob = nullptr, *nev = nullptr, *ltl = nullptr, *tlb = nullptr, *se = nullptr,
           *sgs = nullptr, *llo = nullptr, *lsz = nullptr;
-  uint64_t *sf = nullptr, *us = nullptr, *tmp64 = nullptr;
+  uint64_t *sf = nullptr, *us = nullptr, *tmp64 = nullptr, *pin = nullptr;
   uint32_t* iters_d = nullptr;  // [count]
   uint32_t* ctl_d = nullptr;    // [0] queue head, [1] error
   unsigned long long* work_d = nullptr;  // [16] work totals per tier
@@ -101,7 +101,7 @@ struct BArgs {
   int32_t* sl;
   int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc, *tmp, *rk, *fi, *ob, *nev, *ltl, *tlb, *se, *sgs,
       *llo, *lsz;
-  uint64_t *sf, *us, *tmp64;
+  uint64_t *sf, *us, *tmp64, *pin;
   int32_t* out;
   uint32_t* iters;
   uint32_t* ctl;
@@ -407,6 +407,7 @@ struct GList {
   int32_t* fc;      // [n] per label: split states found in the front part
   int32_t* gc;      // [n] per label: staying states found in the tail
   uint64_t* tmp64;  // [n] per tail position: (staying state << 32) | its position, by index
+  uint64_t* pin;    // [n] per position p: in-transition range of perm[p] (first edge << 32 | count)
   // global spill of the lists (entry i >= the LDS capacity)
   int32_t *ts, *tb_, *lb, *llo, *lsz, *ss, *sb_, *sr, *sf_, *sn, *sp, *se, *sgs;
   uint64_t* sf;     // [ceil(n/64)] split flags (global fallback)
@@ -563,6 +564,8 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
     }
     g.perm[p] = (int32_t)s;
     g.pos[s] = (int32_t)p;
+    const uint32_t e0 = a.in_ptr[s0 + s];
+    g.pin[p] = ((uint64_t)e0 << 32) | (a.in_ptr[s0 + s + 1] - e0);
   }
   __syncthreads();
   if (sh.bad) {  // workgroup-uniform
@@ -651,9 +654,9 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
             beg = pc[4 + lane()];
             deg = pc[4 + kWave + lane()];
           } else {
-            const uint32_t t = (uint32_t)g.perm[cb + i];
-            beg = a.in_ptr[s0 + t];
-            deg = a.in_ptr[s0 + t + 1] - beg;
+            const uint64_t x = g.pin[cb + i];
+            beg = (uint32_t)(x >> 32);
+            deg = (uint32_t)x;
           }
         }
         const uint32_t incl = wave_incl_scan_u32(deg);
@@ -724,9 +727,9 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
       }
       uint32_t beg = 0, deg = 0;
       if (ok && lane() < nsz) {
-        const uint32_t t = (uint32_t)g.perm[ncb + lane()];
-        beg = a.in_ptr[s0 + t];
-        deg = a.in_ptr[s0 + t + 1] - beg;
+        const uint64_t x = g.pin[ncb + lane()];
+        beg = (uint32_t)(x >> 32);
+        deg = (uint32_t)x;
       }
       pn[4 + lane()] = beg;
       pn[4 + kWave + lane()] = deg;
@@ -836,6 +839,23 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
       sS += nS;
       sL += sh.nL[par];
     }
+    if (nS == 0) {  // workgroup-uniform
+      // nothing split (most iterations): clear the touched states' marks and
+      // flags and the candidate slot of iteration it + 2, behind one barrier
+      // instead of the two of the split phases
+      for (uint32_t i = tid; i < nT; i += nthr) {
+        const int32_t s = *ent(Ts, cap, i);
+        mw[s] = 0;
+        tb[s >> 6] = 0;
+      }
+      if (tid == 0) sh.cand[par] = kNone;
+      __syncthreads();
+      if (sh.bad) {  // workgroup-uniform
+        if (tid == 0) atomicOr(&a.ctl[1], 2u);
+        break;
+      }
+      continue;
+    }
     // The split phases take kCU entries per thread and step; each stage issues
     // the loads (or atomics) of all of them before using any, so a step waits
     // for one memory latency per stage, not kCU.
@@ -940,6 +960,16 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
           }
           xv[u] = (sv[u] >= 0 && fv[u] >= 0) ? g.tmp64[nev[u] + fv[u]] : 0ull;
         }
+        // the in-transition ranges by position travel with the swapped states
+        uint64_t pq[kCU], pp[kCU];
+#pragma unroll
+        for (uint32_t u = 0; u < kCU; ++u) {
+          const int32_t q = (int32_t)(uint32_t)xv[u];
+          const bool sw = sv[u] >= 0 && fv[u] >= 0 && q >= nev[u] && q < (int32_t)n &&
+                          psv[u] >= 0 && psv[u] < nev[u];
+          pq[u] = sw ? g.pin[q] : 0ull;
+          pp[u] = sw ? g.pin[psv[u]] : 0ull;
+        }
 #pragma unroll
         for (uint32_t u = 0; u < kCU; ++u) {
           if (sv[u] < 0) continue;
@@ -952,8 +982,10 @@ __device__ uint32_t wg_refine_lists(const BArgs& a, Shared& sh, int32_t* blk, Ma
             } else {
               g.perm[ps] = su;
               g.pos[su] = ps;
+              g.pin[ps] = pq[u];
               g.perm[q] = s;
               g.pos[s] = q;
+              g.pin[q] = pp[u];
             }
           }
           if (ev[u] >= 0) {  // the new leader: one thread per split block
@@ -1045,6 +1077,7 @@ __global__ void __launch_bounds__(WG) k_batch(BArgs a) {
       g.fc = a.fc + s0;
       g.gc = a.gc + s0;
       g.tmp64 = a.tmp64 + s0;
+      g.pin = a.pin + s0;
       g.ts = T;
       g.tb_ = a.tlb + s0;
       g.lb = a.ltl + s0;
@@ -1138,7 +1171,8 @@ void free_batch(bisim_batch* b) {
                   b->tb,      b->lt,       b->tl,      b->sl,  b->iters_d, b->ctl_d, b->perm,
                   b->pos,     b->bs,       b->be,      b->cnt, b->fc,      b->gc,    b->tmp,
                   b->rk,      b->fi,       b->ltl,     b->sf,  b->us,      b->ob,    b->nev,
-                  b->tlb,     b->se,       b->tmp64,   b->sgs,    b->work_d, b->llo, b->lsz};
+                  b->tlb,     b->se,       b->tmp64,   b->sgs,    b->work_d, b->llo, b->lsz,
+                  b->pin};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->u) lts_destroy(b->u);
@@ -1185,6 +1219,7 @@ BArgs make_args(bisim_batch* b, int32_t* out) {
   a.llo = b->llo;
   a.lsz = b->lsz;
   a.tmp64 = b->tmp64;
+  a.pin = b->pin;
   a.sf = b->sf;
   a.us = b->us;
   a.out = out;
@@ -1461,6 +1496,7 @@ bisim_status lts_batch_load(int32_t count, const int64_t* n_off, const int64_t* 
         (st = dmalloc(&b->ob, (size_t)N)) || (st = dmalloc(&b->nev, (size_t)N)) ||
         (st = dmalloc(&b->us, BW)) || (st = dmalloc(&b->tlb, (size_t)N)) ||
         (st = dmalloc(&b->se, (size_t)N)) || (st = dmalloc(&b->tmp64, (size_t)N)) ||
+        (st = dmalloc(&b->pin, (size_t)N)) ||
         (st = dmalloc(&b->sgs, (size_t)N)) || (st = dmalloc(&b->llo, (size_t)N)) ||
         (st = dmalloc(&b->lsz, (size_t)N)) ||
         (st = dmalloc(&b->iters_d, count)) || (st = dmalloc(&b->ctl_d, 2)) ||

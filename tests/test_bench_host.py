@@ -86,6 +86,6 @@ def test_batch_bytes_model():
           "work": [[7, 40, 90, 0, 0, 0, 0, 2], [100, 30, 200, 80, 10, 500, 20, 4]]}
     got = bench.batch_bytes(sizes, st, 4)
     n_list = 20000 + 5000  # the two largest instances take the member-list tier
-    exp = 8 * sum(sizes) + 8 * 40 + 8 * 90 + 60 * n_list + 8 * 100 + 12 * 30 + 16 * 200 \
-        + 24 * 80 + 4 * 500 + 100 * 20 + 24 * 4
+    exp = 8 * sum(sizes) + 8 * 40 + 8 * 90 + 76 * n_list + 8 * 100 + 8 * 30 + 16 * 200 \
+        + 24 * 80 + 4 * 500 + 132 * 20 + 24 * 4
     assert got == pytest.approx(exp)
