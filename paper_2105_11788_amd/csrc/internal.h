@@ -154,6 +154,8 @@ struct bisim_lists {
   int32_t *perm = nullptr, *pos = nullptr, *bs = nullptr, *be = nullptr;
   int32_t *cnt = nullptr, *fc = nullptr, *gc = nullptr, *tcn = nullptr;
   uint64_t* tmp64 = nullptr;
+  uint64_t* pin = nullptr;  // in-transition range by member-list position
+  uint32_t* pf = nullptr;   // the next splitter, prefetched (two slots)
   int32_t *lb = nullptr, *lo = nullptr, *lh = nullptr;
   int32_t *ts = nullptr, *tbk = nullptr;
   int32_t *ss = nullptr, *sbk = nullptr, *sr = nullptr, *sfi = nullptr, *sne = nullptr,

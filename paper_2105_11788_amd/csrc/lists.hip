@@ -54,6 +54,11 @@ namespace {
 constexpr int kLT = 256;
 constexpr uint32_t kSeg = 1024;       // members of a listed block per segment
 constexpr uint32_t kGraphIters = 32;  // iterations per captured graph
+static_assert(kGraphIters % 2 == 0, "the iteration parity is the launch position's");
+// the next splitter, prefetched: two slots by iteration parity, each a header
+// (label, first position, size, valid) and the in-transition ranges (first
+// edge << 32 | count) of its first kWave members
+constexpr uint32_t kPfWords = 4u + 2u * kWave;
 
 struct LArgs {
   uint32_t n;
@@ -72,6 +77,8 @@ struct LArgs {
   uint64_t* nlw;  // bids
   int32_t *perm, *pos, *bs, *be, *cnt, *fc, *gc;
   int32_t* tcn;  // per label: members first touched this iteration (0 between iterations)
+  uint64_t* pin;  // per position p: in-transition range of perm[p] (first edge << 32 | count)
+  uint32_t* pf;   // [2][kPfWords] the next splitter, prefetched
   uint64_t* tmp64;
   int32_t *lb, *lo, *lh;  // listed segments: block, first and end position
   uint32_t lcap;
@@ -97,7 +104,8 @@ __device__ __forceinline__ GPart gpart() {
 }
 
 // iteration of a launch: the base advanced after every graph replay (0 for
-// eager launches) plus the launch's position
+// eager launches) plus the launch's position.  The base stays even, so the
+// iteration's parity is the position's, known without waiting for the load.
 __device__ __forceinline__ uint32_t iter_of(const LArgs& a, uint32_t kofs) {
   return a.ctl->state.v[6] + kofs;
 }
@@ -150,10 +158,18 @@ __device__ __forceinline__ bool marks_differ(const LArgs& a, int32_t s, int32_t 
 __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
   const uint32_t k = iter_of(a, kofs);
-  const uint32_t par = k & 1;
+  const uint32_t par = kofs & 1;
   const uint32_t C0 = a.ctl->cand[par].v[0];
-  if (done) return;
+  // the prefetch slot of this iteration, and the in-transition range this
+  // lane would take from it for the wave's first member chunk
+  const uint32_t* pc = a.pf + par * kPfWords;
+  const uint32_t pf_ok = pc[3], pf_C = pc[0], pf_cb = pc[1], pf_n = pc[2];
   const GPart p = gpart();
+  const uint32_t i_first = p.gwave * a.mpw + lane();
+  const bool lane_first = lane() < a.mpw && i_first < kWave;
+  const uint32_t pf_lo = lane_first ? pc[4 + 2 * i_first] : 0u;
+  const uint32_t pf_hi = lane_first ? pc[5 + 2 * i_first] : 0u;
+  if (done) return;
   const bool over = k + 1 > a.iter_cap;
   if (C0 == kNone || over) {  // the final pass, or the iteration cap
     if (p.gtid == 0) {
@@ -209,8 +225,9 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t kofs) {
     }
     if (lane() == 0 && next != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], next);
   }
-  const uint32_t cb = (uint32_t)a.bs[C];
-  uint32_t csz = (uint32_t)a.be[C] - cb;
+  const bool pre = pf_ok != 0 && pf_C == C;
+  const uint32_t cb = pre ? pf_cb : (uint32_t)a.bs[C];
+  uint32_t csz = pre ? pf_n : (uint32_t)a.be[C] - cb;
   if (cb > n || csz > n - cb) csz = 0;  // never expected
   if (p.gtid == 0 && a.count) {
     atomicAdd((unsigned long long*)&a.work[0], (unsigned long long)csz);
@@ -222,9 +239,14 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t kofs) {
     const bool hit = lane() < a.mpw && i < csz;
     uint32_t beg = 0, deg = 0;
     if (hit) {
-      const uint32_t t = (uint32_t)a.perm[cb + i];
-      beg = a.in_ptr[t];
-      deg = a.in_ptr[t + 1] - beg;
+      if (pre && lane_first && i0 == p.gwave * a.mpw) {  // the wave's first chunk
+        beg = pf_hi;
+        deg = pf_lo;
+      } else {
+        const uint64_t x = a.pin[cb + i];
+        beg = (uint32_t)(x >> 32);
+        deg = (uint32_t)x;
+      }
     }
     const uint32_t incl = wave_incl_scan_u32(deg);
     const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
@@ -295,7 +317,7 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t kofs) {
 __global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
   const uint32_t k = iter_of(a, kofs);
-  const uint32_t par = k & 1;
+  const uint32_t par = kofs & 1;
   const uint32_t nT = min(a.ctl->cntT[par].v[0], a.n);
   const uint32_t nL = a.ctl->cntC[par].v[0];
   if (done) return;
@@ -303,6 +325,29 @@ __global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t kofs) {
   const uint64_t epoch = (uint64_t)(k + 1) << 32;
   const uint32_t n = a.n;
   uint32_t* nS = &a.ctl->cntS[par].v[0];
+  if (p.gwave == p.gwaves - 1) {
+    // prefetch the next iteration's splitter: the candidate the mark kernel
+    // found, its range and its first kWave members' in-transition ranges.
+    // Should anything split in this iteration, the candidate may still
+    // change and ranges move; the swap kernel then marks the slot stale.
+    const uint32_t nx = a.ctl->cand[par ^ 1].v[0];
+    uint32_t* pn = a.pf + (par ^ 1) * kPfWords;
+    uint32_t ncb = 0, nsz = 0;
+    bool ok = false;
+    if (nx < n) {
+      ncb = (uint32_t)a.bs[nx];
+      nsz = (uint32_t)a.be[nx] - ncb;
+      ok = ncb <= n && nsz <= n - ncb;
+    }
+    const uint64_t x = (ok && lane() < nsz) ? a.pin[ncb + lane()] : 0ull;
+    reinterpret_cast<uint64_t*>(pn + 4)[lane()] = x;
+    if (lane() == 0) {
+      pn[0] = nx;
+      pn[1] = ncb;
+      pn[2] = nsz;
+      pn[3] = ok ? 1u : 0u;
+    }
+  }
   const uint32_t half = p.gwaves > 1 ? p.gwaves / 2 : 1;
   if (p.gwave < half) {
     // listed touched states, one per thread of the first half of the grid
@@ -377,8 +422,7 @@ __global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t kofs) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
-  const uint32_t k = iter_of(a, kofs);
-  const uint32_t par = k & 1;
+  const uint32_t par = kofs & 1;
   const uint32_t nS = min(a.ctl->cntS[par].v[0], a.n);
   const uint32_t nT = min(a.ctl->cntT[par].v[0], a.n);
   if (done) return;
@@ -436,7 +480,7 @@ __global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t kofs) {
 __global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t kofs) {
   const uint32_t done = a.ctl->state.v[1];
   const uint32_t k = iter_of(a, kofs);
-  const uint32_t par = k & 1;
+  const uint32_t par = kofs & 1;
   const uint32_t nS = min(a.ctl->cntS[par].v[0], a.n);
   const uint32_t C = a.ctl->state.v[3];
   if (done) return;
@@ -447,6 +491,7 @@ __global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t kofs) {
     if (nS > 0) {
       set_unstable(a, C);
       atomicMin(&a.ctl->cand[par ^ 1].v[0], C);
+      a.pf[(par ^ 1) * kPfWords + 3] = 0;  // ranges changed: the prefetch is stale
     }
     count_work(a, 7, nS > 0 ? 1 : 0);
   }
@@ -462,10 +507,13 @@ __global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t kofs) {
         const uint64_t x = a.tmp64[ne + fv];
         const int32_t q = (int32_t)(uint32_t)x, su = (int32_t)(x >> 32);
         if (q >= ne && q < (int32_t)n && ps >= 0 && ps < ne && su >= 0 && su < (int32_t)n) {
+          const uint64_t xq = a.pin[q], xp = a.pin[ps];
           a.perm[ps] = su;
           a.pos[su] = ps;
+          a.pin[ps] = xq;
           a.perm[q] = s;
           a.pos[s] = q;
+          a.pin[q] = xp;
         } else {
           a.ctl->state.v[4] = 1;  // never expected
         }
@@ -508,6 +556,7 @@ __global__ void k_l_zero(LArgs a) {
     a.tcn[s] = 0;
   }
   if (p.gtid < 8) a.work[p.gtid] = 0;
+  if (p.gtid < 2) a.pf[p.gtid * kPfWords + 3] = 0;
 }
 __global__ void k_l_count(LArgs a) {
   const GPart p = gpart();
@@ -520,6 +569,8 @@ __global__ void k_l_fill(LArgs a) {
     if (q < a.n) {
       a.perm[q] = (int32_t)s;
       a.pos[s] = (int32_t)q;
+      const uint32_t e0 = a.in_ptr[s];
+      a.pin[q] = ((uint64_t)e0 << 32) | (a.in_ptr[s + 1] - e0);
     } else {
       a.ctl->state.v[4] = 1;  // never expected
     }
@@ -560,6 +611,8 @@ bisim_status lists_alloc(bisim_lts* h) {
   BISIM_TRY(lalloc(&L.fc, n, s));
   BISIM_TRY(lalloc(&L.gc, n, s));
   BISIM_TRY(lalloc(&L.tcn, n, s));
+  BISIM_TRY(lalloc(&L.pin, n, s));
+  BISIM_TRY(lalloc(&L.pf, 2 * (size_t)kPfWords, s));
   BISIM_TRY(lalloc(&L.tmp64, n, s));
   BISIM_TRY(lalloc(&L.lb, seg_capacity(n), s));
   BISIM_TRY(lalloc(&L.lo, seg_capacity(n), s));
@@ -600,6 +653,8 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
   a.fc = L.fc;
   a.gc = L.gc;
   a.tcn = L.tcn;
+  a.pin = L.pin;
+  a.pf = L.pf;
   a.tmp64 = L.tmp64;
   a.lb = L.lb;
   a.lo = L.lo;
@@ -771,7 +826,8 @@ void lists_free(bisim_lts* h) {
     (void)hipStreamDestroy(L.own);
   }
   void* ptrs[] = {L.perm, L.pos, L.bs,  L.be,  L.cnt, L.fc,  L.gc,  L.tmp64, L.lb, L.lo, L.lh, L.ts,
-                  L.tbk,  L.ss,  L.sbk, L.sr,  L.sfi, L.sne, L.sps, L.sse,   L.work, L.tcn};
+                  L.tbk,  L.ss,  L.sbk, L.sr,  L.sfi, L.sne, L.sps, L.sse,   L.work, L.tcn,
+                  L.pin,  L.pf};
   for (void* q : ptrs)
     if (q) (void)dev_free(q, h->stream);
   L = bisim_lists{};
