@@ -116,7 +116,7 @@ def lists_bytes(n: int, iters: int, w: dict):
     over the iterations: the byte model of its loads, stores and atomics
     (int32 ids, 64-bit mark words, bids and bitmap words; an atomic counts
     its read and its write) times the run's work totals:
-      mark     8 (range of C) + 12 per member (perm, in_ptr pair)
+      mark     8 (range of C) + 8 per member (its in-transition range)
                + 52 per in-transition (source, rank, the source's block and
                  range, mark-word and touched-word atomics) + 16 per touched
                  state (list entry, its block's touched-count atomic)
@@ -126,21 +126,27 @@ def lists_bytes(n: int, iters: int, w: dict):
                atomics, list entry) + 24 per segment (entry, its block's
                touched count and range) + 12 per member visited (perm,
                touched word; only blocks with an untouched member)
+               + the prefetch of the next splitter: 28 (candidate, range,
+               slot header) + 16 per member prefetched (range loaded and
+               stored; min(64, the mean splitter size) per iteration)
       relabel  32 per touched state (list entry and its block; mark word,
                touched word and touched count cleared) + 96 per split state (list entry, its block's bid,
                range and count, position, label store, front/tail counters,
                tail state and its flag, pair store, four list stores)
-      swap     44 per split state (seven list loads, pair load, four
-               perm/pos stores, split flag) + 64 per split block (ranges,
+      swap     76 per split state (seven list loads, pair load, four
+               perm/pos stores, two in-transition ranges loaded and stored,
+               split flag; counted for every split state though only those
+               in front of the tail swap) + 64 per split block (ranges,
                counters, unstable bits)
     Returns a list of four floats (bytes per launch)."""
     it = max(1, iters - 1)  # the final pass does no work
-    mark = 8 * it + 12 * w["members"] + 52 * w["in_transitions"] + 16 * w["touched"] \
+    mark = 8 * it + 8 * w["members"] + 52 * w["in_transitions"] + 16 * w["touched"] \
         + 12 * w["segments"]
+    pref = it * (28 + 16 * min(64.0, w["members"] / it))
     comp = 24 * w["touched"] + 56 * w["split_states"] + 24 * w["segments"] \
-        + 12 * w["member_visits"]
+        + 12 * w["member_visits"] + pref
     rel = 32 * w["touched"] + 96 * w["split_states"]
-    swp = 44 * w["split_states"] + 64 * w["split_blocks"]
+    swp = 76 * w["split_states"] + 64 * w["split_blocks"]
     return [mark / it, comp / it, rel / it, swp / it]
 
 
