@@ -107,8 +107,8 @@ def phase_bytes(n: int, work: np.ndarray, nsplit: np.ndarray):
     return out
 
 
-LISTS_KERNELS = ["k_l_mark (select+mark)", "k_l_compare (compare+elect+rank)",
-                 "k_l_relabel (relabel+tail, clear marks)", "k_l_swap (swaps+ranges+unstable)"]
+LISTS_KERNELS = ["k_l_mark (select+mark)", "k_l_compare (compare+elect+rank, prefetch)",
+                 "k_l_split (relabel+tail+swaps+ranges, clear marks)"]
 
 
 def lists_bytes(n: int, iters: int, w: dict):
@@ -129,25 +129,27 @@ def lists_bytes(n: int, iters: int, w: dict):
                + the prefetch of the next splitter: 28 (candidate, range,
                slot header) + 16 per member prefetched (range loaded and
                stored; min(64, the mean splitter size) per iteration)
-      relabel  32 per touched state (list entry and its block; mark word,
-               touched word and touched count cleared) + 96 per split state (list entry, its block's bid,
-               range and count, position, label store, front/tail counters,
-               tail state and its flag, pair store, four list stores)
-      swap     76 per split state (seven list loads, pair load, four
-               perm/pos stores, two in-transition ranges loaded and stored,
-               split flag; counted for every split state though only those
-               in front of the tail swap) + 64 per split block (ranges,
-               counters, unstable bits)
-    Returns a list of four floats (bytes per launch)."""
+      split    32 per touched state (list entry and its block; mark word,
+               touched word and touched count cleared) + 96 per split state
+               (list entry, its block's bid, range and count, position, label
+               store, front/tail counters, tail state and its flag, pair
+               store, four list stores) + 8 per iteration that splits
+               (the arrival counter; one relabelling workgroup per 256 split
+               states, one in most such iterations) + 76 per split state
+               (seven list loads, pair load, four perm/pos stores, two
+               in-transition ranges loaded and stored, split flag; counted
+               for every split state though only those in front of the tail
+               swap) + 64 per split block (ranges, counters, unstable bits)
+    Returns a list of three floats (bytes per launch)."""
     it = max(1, iters - 1)  # the final pass does no work
     mark = 8 * it + 8 * w["members"] + 52 * w["in_transitions"] + 16 * w["touched"] \
         + 12 * w["segments"]
     pref = it * (28 + 16 * min(64.0, w["members"] / it))
     comp = 24 * w["touched"] + 56 * w["split_states"] + 24 * w["segments"] \
         + 12 * w["member_visits"] + pref
-    rel = 32 * w["touched"] + 96 * w["split_states"]
-    swp = 76 * w["split_states"] + 64 * w["split_blocks"]
-    return [mark / it, comp / it, rel / it, swp / it]
+    spl = 32 * w["touched"] + 96 * w["split_states"] + 8 * w["split_iterations"] \
+        + 76 * w["split_states"] + 64 * w["split_blocks"]
+    return [mark / it, comp / it, spl / it]
 
 
 def batch_bytes(sizes, st, mask_bytes: int):
@@ -463,7 +465,7 @@ def form_plain(bisim, gen, args):
     names = ["k_fused_x (relabel+select+mark)", "k_fused_y (compare+elect)"]
     if eng == 3:
         lb = lists_bytes(L.n, iters, r["work_totals"])
-        ms = r["phase_ms"][:4]
+        ms = r["phase_ms"][:3]
         q = int(np.argmax(ms))
         kernel = LISTS_KERNELS[q]
         touched_launch = float(lb[q])
@@ -479,7 +481,7 @@ def form_plain(bisim, gen, args):
                                         "GBs": float(lb[i] / (ms[i] * 1e-3) / 1e9)
                                         if ms[i] > 0 else None,
                                         "samples": int(r["phase_samples"][i])}
-                     for i in range(4)}
+                     for i in range(3)}
         per_phase["work_totals"] = r["work_totals"]
         per_phase["timing"] = ("kernel durations from a run launched kernel by kernel "
                                f"({r['eager_ms_per_step']:.1f} ms to the fixpoint); the timed "

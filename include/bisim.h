@@ -225,9 +225,12 @@ bisim_status bisim_set_option(bisim_lts* h, int32_t option, int64_t value);
 
 /*
  * bisim_get_phase_times — after a run with BISIM_OPT_PROFILE_EVERY > 0:
- * average kernel execution time in ms (avg_ms, host, 4 entries: select+mark,
- * compare+elect, relabel, re-score) over the sampled iterations that had a
- * splitter, and the number of samples per phase (samples, host, 4 entries).
+ * average kernel execution time in ms (avg_ms, host, 4 entries) over the
+ * sampled iterations that had a splitter, and the number of samples per
+ * phase (samples, host, 4 entries).  Engine 2: select+relabel+mark and
+ * compare+elect (the learned policy: select+mark, compare+elect, relabel,
+ * re-score); engine 3: select+mark, compare+elect (+ the next splitter's
+ * prefetch), split (relabel, swaps, ranges); unused entries are 0.
  * Errors: BISIM_E_INVALID.
  */
 bisim_status bisim_get_phase_times(bisim_lts* h, double* avg_ms, int64_t* samples);

@@ -4,7 +4,7 @@
 //
 // Besides block[], the partition is kept as a refinable partition: perm
 // lists the states block by block and the block labelled b owns
-// perm[bs[b] .. be[b]).  One iteration is four kernels:
+// perm[bs[b] .. be[b]).  One iteration is three kernels:
 //
 //   M  mark      C = the candidate (the smallest unstable label, the
 //                priority reading of the concurrent write); clear its
@@ -20,22 +20,24 @@
 //                split state bids for its block's new leader (64-bit max of
 //                (epoch, ~state): the smallest state wins), takes its rank
 //                within the block's split part, sets its split bit and is
-//                listed.
-//   R  relabel   every split state takes its block's winning bid as label;
+//                listed.  One wave prefetches the next splitter's range and
+//                first members for the next mark kernel.
+//   S  split     every split state takes its block's winning bid as label;
 //                the split part will be the tail [ne, be) of the block's
 //                range: split states in front of ne take an index, and the
 //                staying state found at ne + rank is recorded under an index
-//                of its own; marks and touched bits are cleared.
-//   W  swap      the i-th front split state and the i-th staying tail state
-//                swap places; the new leader of each split block sets both
-//                ranges and the unstable bits, and the
-//                old label joins the next candidate (with C if anything
-//                split, the lock-step reading of Algorithm 3).
+//                of its own.  The last workgroup to finish that then swaps
+//                the i-th front split state with the i-th staying tail
+//                state; the new leader of each split block sets both ranges
+//                and the unstable bits, and the old label joins the next
+//                candidate (with C if anything split, the lock-step reading
+//                of Algorithm 3).  Marks, touched bits and counts are
+//                cleared.
 //
 // Every per-iteration set (touched states, listed segments, split states) is
 // a list built with wave-aggregated atomics, so no kernel scans anything of
 // size n.  Iterations are captured in a hipGraph of kGraphIters iterations
-// (4 kernels each, plus one that advances the iteration base the kernels add
+// (3 kernels each, plus one that advances the iteration base the kernels add
 // their position in the graph to) and replayed until the done flag is set.
 // The splitter sequence, the split counts and the partitions are those of
 // the other engines.  States with more than 64 actions use the mark-word
@@ -59,6 +61,7 @@ static_assert(kGraphIters % 2 == 0, "the iteration parity is the launch position
 // (label, first position, size, valid) and the in-transition ranges (first
 // edge << 32 | count) of its first kWave members
 constexpr uint32_t kPfWords = 4u + 2u * kWave;
+constexpr int kPhases = 3;  // kernels per iteration
 
 struct LArgs {
   uint32_t n;
@@ -418,70 +421,88 @@ __global__ void __launch_bounds__(kLT) k_l_compare(LArgs a, uint32_t kofs) {
 }
 
 // ---------------------------------------------------------------------------
-// R: relabel, tail bookkeeping; clear marks and touched bits
+// S: relabel, tail bookkeeping, swaps, new ranges, unstable updates; clear
+// marks, touched bits and touched counts.  The split states are relabelled by
+// the first R workgroups (one state per thread); the last of them to finish
+// (an arrival counter, behind agent-scope release fences, read with an
+// acquire) swaps the states of the whole iteration and sets the new ranges,
+// so the two steps that need every split state's bookkeeping in between take
+// one kernel, not two.  Every workgroup then clears touched states.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kLT) k_l_relabel(LArgs a, uint32_t kofs) {
-  const uint32_t done = a.ctl->state.v[1];
-  const uint32_t par = kofs & 1;
-  const uint32_t nS = min(a.ctl->cntS[par].v[0], a.n);
-  const uint32_t nT = min(a.ctl->cntT[par].v[0], a.n);
-  if (done) return;
-  const GPart p = gpart();
+__device__ __forceinline__ void relabel_one(const LArgs& a, uint32_t i) {
   const uint32_t n = a.n;
-  const uint32_t half = p.gwaves > 1 ? p.gwaves / 2 : 1;
-  if (p.gwave < half) {
-    count_work(a, 5, p.gtid == 0 ? nS : 0);
-    for (uint32_t i = p.gwave * kWave + lane(); i < nS; i += half * kWave) {
-      const int32_t s = a.ss[i], b = a.sbk[i], r = a.sr[i];
-      const uint64_t nv = a.nlw[b];
-      const int32_t e = a.be[b], c = a.cnt[b], pv = a.pos[s];
-      const int32_t nl = (int32_t)(kNone - (uint32_t)nv);
-      a.block[s] = nl;
-      const int32_t ne = e - c, q = ne + r;
-      int32_t fv = -1, uv = -1;
-      const bool ok = ne >= 0 && q >= ne && q < e && e <= (int32_t)n && pv >= 0 && pv < (int32_t)n;
-      if (ok) {
-        if (pv < ne) fv = atomicAdd(&a.fc[b], 1);
-        uv = a.perm[q];  // every tail position is examined once
-      } else {
-        a.ctl->state.v[4] = 1;  // never expected
-      }
-      a.sfi[i] = fv;
-      a.sne[i] = ok ? ne : 0;
-      a.sps[i] = ok ? pv : 0;
-      a.sse[i] = (ok && nl == s) ? e : -1;
-      if (uv >= 0 && uv < (int32_t)n && !test_bit(a.sf, (uint32_t)uv)) {
-        const int32_t jj = atomicAdd(&a.gc[b], 1);
-        if (ne + jj < e)
-          a.tmp64[ne + jj] = ((uint64_t)(uint32_t)uv << 32) | (uint32_t)q;
-        else
-          a.ctl->state.v[4] = 1;
-      }
-    }
+  const int32_t s = a.ss[i], b = a.sbk[i], r = a.sr[i];
+  const uint64_t nv = a.nlw[b];
+  const int32_t e = a.be[b], c = a.cnt[b], pv = a.pos[s];
+  const int32_t nl = (int32_t)(kNone - (uint32_t)nv);
+  a.block[s] = nl;
+  const int32_t ne = e - c, q = ne + r;
+  int32_t fv = -1, uv = -1;
+  const bool ok = ne >= 0 && q >= ne && q < e && e <= (int32_t)n && pv >= 0 && pv < (int32_t)n;
+  if (ok) {
+    if (pv < ne) fv = atomicAdd(&a.fc[b], 1);
+    uv = a.perm[q];  // every tail position is examined once
   } else {
-    // clear the marks, touched bits and touched counts of this iteration's
-    // touched states
-    for (uint32_t i = (p.gwave - half) * kWave + lane(); i < nT; i += (p.gwaves - half) * kWave) {
-      const int32_t s = a.ts[i];
-      a.tcn[a.tbk[i]] = 0;  // every touched state of the block clears it
-      if (a.uniform) {
-        a.mw[s] = 0;
-      } else {
-        for (uint32_t w = a.woff[s]; w < a.woff[s + 1]; ++w) a.mw[w] = 0;
-      }
-      a.tb[s >> 6] = 0;  // every touched state of the word clears it
-    }
+    a.ctl->state.v[4] = 1;  // never expected
+  }
+  a.sfi[i] = fv;
+  a.sne[i] = ok ? ne : 0;
+  a.sps[i] = ok ? pv : 0;
+  a.sse[i] = (ok && nl == s) ? e : -1;
+  if (uv >= 0 && uv < (int32_t)n && !test_bit(a.sf, (uint32_t)uv)) {
+    const int32_t jj = atomicAdd(&a.gc[b], 1);
+    if (ne + jj < e)
+      a.tmp64[ne + jj] = ((uint64_t)(uint32_t)uv << 32) | (uint32_t)q;
+    else
+      a.ctl->state.v[4] = 1;
   }
 }
 
-// ---------------------------------------------------------------------------
-// W: swaps, new ranges, unstable updates, next candidate
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t kofs) {
+// the swap of split state i with its staying tail state, and, for the new
+// leader, the ranges and unstable bits; returns whether i is a new leader
+__device__ __forceinline__ bool swap_one(const LArgs& a, uint32_t i, uint32_t& best) {
+  const uint32_t n = a.n;
+  const int32_t s = a.ss[i], b = a.sbk[i], fv = a.sfi[i], ne = a.sne[i], ps = a.sps[i];
+  const int32_t e = a.sse[i];
+  if (fv >= 0 && ne >= 0 && ne + fv < (int32_t)n) {
+    const uint64_t x = a.tmp64[ne + fv];
+    const int32_t q = (int32_t)(uint32_t)x, su = (int32_t)(x >> 32);
+    if (q >= ne && q < (int32_t)n && ps >= 0 && ps < ne && su >= 0 && su < (int32_t)n) {
+      const uint64_t xq = a.pin[q], xp = a.pin[ps];
+      a.perm[ps] = su;
+      a.pos[su] = ps;
+      a.pin[ps] = xq;
+      a.perm[q] = s;
+      a.pos[s] = q;
+      a.pin[q] = xp;
+    } else {
+      a.ctl->state.v[4] = 1;  // never expected
+    }
+  }
+  bool lead = false;
+  if (e >= 0) {  // the new leader: one thread per split block
+    a.bs[s] = ne;
+    a.be[s] = e;
+    a.be[b] = ne;
+    a.cnt[b] = 0;
+    a.fc[b] = 0;
+    a.gc[b] = 0;
+    set_unstable(a, (uint32_t)b);
+    set_unstable(a, (uint32_t)s);
+    best = min(best, (uint32_t)b);
+    lead = true;
+  }
+  atomicAnd((unsigned long long*)&a.sf[s >> 6], ~(1ull << (s & 63)));
+  return lead;
+}
+
+__global__ void __launch_bounds__(kLT) k_l_split(LArgs a, uint32_t kofs) {
+  __shared__ uint32_t last;
   const uint32_t done = a.ctl->state.v[1];
   const uint32_t k = iter_of(a, kofs);
   const uint32_t par = kofs & 1;
   const uint32_t nS = min(a.ctl->cntS[par].v[0], a.n);
+  const uint32_t nT = min(a.ctl->cntT[par].v[0], a.n);
   const uint32_t C = a.ctl->state.v[3];
   if (done) return;
   const GPart p = gpart();
@@ -495,47 +516,41 @@ __global__ void __launch_bounds__(kLT) k_l_swap(LArgs a, uint32_t kofs) {
     }
     count_work(a, 7, nS > 0 ? 1 : 0);
   }
-  if (nS == 0) return;
-  const uint32_t n = a.n;
-  uint32_t best = kNone, leaders = 0;
-  for (uint32_t i0 = p.gwave * kWave; i0 < nS; i0 += p.gwaves * kWave) {
-    const uint32_t i = i0 + lane();
-    if (i < nS) {
-      const int32_t s = a.ss[i], b = a.sbk[i], fv = a.sfi[i], ne = a.sne[i], ps = a.sps[i];
-      const int32_t e = a.sse[i];
-      if (fv >= 0 && ne >= 0 && ne + fv < (int32_t)n) {
-        const uint64_t x = a.tmp64[ne + fv];
-        const int32_t q = (int32_t)(uint32_t)x, su = (int32_t)(x >> 32);
-        if (q >= ne && q < (int32_t)n && ps >= 0 && ps < ne && su >= 0 && su < (int32_t)n) {
-          const uint64_t xq = a.pin[q], xp = a.pin[ps];
-          a.perm[ps] = su;
-          a.pos[su] = ps;
-          a.pin[ps] = xq;
-          a.perm[q] = s;
-          a.pos[s] = q;
-          a.pin[q] = xp;
-        } else {
-          a.ctl->state.v[4] = 1;  // never expected
-        }
-      }
-      if (e >= 0) {  // the new leader: one thread per split block
-        a.bs[s] = ne;
-        a.be[s] = e;
-        a.be[b] = ne;
-        a.cnt[b] = 0;
-        a.fc[b] = 0;
-        a.gc[b] = 0;
-        set_unstable(a, (uint32_t)b);
-        set_unstable(a, (uint32_t)s);
-        best = min(best, (uint32_t)b);
-        ++leaders;
-      }
-      atomicAnd((unsigned long long*)&a.sf[s >> 6], ~(1ull << (s & 63)));
+  // workgroup-uniform: the first R workgroups relabel, one split state per thread
+  const uint32_t R = min((nS + kLT - 1) / kLT, gridDim.x);
+  if (blockIdx.x < R) {
+    count_work(a, 5, p.gtid == 0 ? nS : 0);
+    for (uint32_t i = p.gtid; i < nS; i += R * kLT) relabel_one(a, i);
+    __threadfence();  // release this workgroup's bookkeeping
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t prev = atomicAdd(&a.ctl->ltany[0].v[0], 1u);
+      last = (prev == R - 1) ? 1u : 0u;
+      if (last) a.ctl->ltany[0].v[0] = 0;  // every arrival of this kernel is in
+    }
+    __syncthreads();
+    if (last) {  // workgroup-uniform
+      __threadfence();  // acquire the other workgroups' bookkeeping
+      uint32_t best = kNone, leaders = 0;
+      for (uint32_t i = threadIdx.x; i < nS; i += kLT)
+        if (swap_one(a, i, best)) ++leaders;
+      best = wave_min_u32(best);
+      if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
+      count_work(a, 6, wave_sum_u64(leaders));
     }
   }
-  best = wave_min_u32(best);
-  if (lane() == 0 && best != kNone) atomicMin(&a.ctl->cand[par ^ 1].v[0], best);
-  count_work(a, 6, wave_sum_u64(leaders));
+  // clear the marks, touched bits and touched counts of this iteration's
+  // touched states
+  for (uint32_t i = p.gtid; i < nT; i += p.gthreads) {
+    const int32_t s = a.ts[i];
+    a.tcn[a.tbk[i]] = 0;  // every touched state of the block clears it
+    if (a.uniform) {
+      a.mw[s] = 0;
+    } else {
+      for (uint32_t w = a.woff[s]; w < a.woff[s + 1]; ++w) a.mw[w] = 0;
+    }
+    a.tb[s >> 6] = 0;  // every touched state of the word clears it
+  }
 }
 
 // after a graph replay of `by` iterations: advance the iteration base
@@ -722,22 +737,21 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
     uint32_t k = 0, chunk = 8;
     for (;;) {
       for (uint32_t j = 0; j < chunk; ++j, ++k) {
-        hipEvent_t ends[4] = {nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t ends[kPhases] = {nullptr, nullptr, nullptr};
         const size_t slot = sampled.size();
         if (carry && slot < (size_t)h->pev_slots) {
-          for (int q = 0; q < 4; ++q) ends[q] = h->pev[8 * slot + 1 + q];
+          for (int q = 0; q < kPhases; ++q) ends[q] = h->pev[8 * slot + 1 + q];
           sampled.push_back(k);
           starts.push_back(carry);
         }
         carry = nullptr;
         if ((k + 1) % pe == 0 && sampled.size() < (size_t)h->pev_slots) {
-          if (!ends[3]) ends[3] = h->pev[8 * sampled.size()];
-          carry = ends[3];
+          if (!ends[kPhases - 1]) ends[kPhases - 1] = h->pev[8 * sampled.size()];
+          carry = ends[kPhases - 1];
         }
         go(k_l_mark, ends[0], k);
         go(k_l_compare, ends[1], k);
-        go(k_l_relabel, ends[2], k);
-        go(k_l_swap, ends[3], k);
+        go(k_l_split, ends[2], k);
       }
       BISIM_TRY_HIP(hipGetLastError());
       BISIM_TRY_HIP(hipMemcpyAsync(&h->ctl_host->state, &h->ctl->state, sizeof(Line),
@@ -765,8 +779,7 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
       for (uint32_t j = 0; j < kGraphIters; ++j) {
         hipLaunchKernelGGL(k_l_mark, dim3(grid), dim3(kLT), 0, gs, a, j);
         hipLaunchKernelGGL(k_l_compare, dim3(grid), dim3(kLT), 0, gs, a, j);
-        hipLaunchKernelGGL(k_l_relabel, dim3(grid), dim3(kLT), 0, gs, a, j);
-        hipLaunchKernelGGL(k_l_swap, dim3(grid), dim3(kLT), 0, gs, a, j);
+        hipLaunchKernelGGL(k_l_split, dim3(grid), dim3(kLT), 0, gs, a, j);
       }
       hipLaunchKernelGGL(k_l_advance, dim3(1), dim3(64), 0, gs, a, kGraphIters);
       const hipError_t le = hipGetLastError();
@@ -800,7 +813,7 @@ bisim_status lists_loop(bisim_lts* h, uint32_t cap, bool count_work_totals) {
   for (size_t i = 0; i < sampled.size(); ++i) {
     if ((uint64_t)sampled[i] + 1 >= iters) continue;
     hipEvent_t prev = starts[i];
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kPhases; ++q) {
       hipEvent_t cur = h->pev[8 * i + 1 + q];
       float pm = 0.f;
       if (hipEventElapsedTime(&pm, prev, cur) == hipSuccess) {

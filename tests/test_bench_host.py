@@ -73,12 +73,11 @@ def test_lists_bytes_model():
          "member_visits": 2000, "split_states": 50, "split_blocks": 5, "split_iterations": 3}
     n, iters = 6400, 11  # ten working iterations and the final pass
     lb = bench.lists_bytes(n, iters, w)
-    assert len(lb) == 4
+    assert len(lb) == 3
     assert lb[0] == pytest.approx((8 * 10 + 8 * 100 + 52 * 600 + 16 * 300 + 12 * 4) / 10)
     # ten splitters of ten members each: ten prefetches of 28 + 16 x 10 bytes
     assert lb[1] == pytest.approx((24 * 300 + 56 * 50 + 24 * 4 + 12 * 2000 + 10 * (28 + 160)) / 10)
-    assert lb[2] == pytest.approx((32 * 300 + 96 * 50) / 10)
-    assert lb[3] == pytest.approx((76 * 50 + 64 * 5) / 10)
+    assert lb[2] == pytest.approx((32 * 300 + 96 * 50 + 8 * 3 + 76 * 50 + 64 * 5) / 10)
 
 
 def test_batch_bytes_model():
