@@ -59,6 +59,10 @@ WORKLOADS = {
     "product-810k": dict(
         desc="synchronised product of 4 cyclic processes of 30 states over 8 actions, 2 shared",
         make=lambda g: g.sync_product(seed=1)),
+    "distinct-actions-25k": dict(
+        desc="chain of 25,217 states whose 25,216 transitions each have an action of their "
+             "own (the shape of Table 1's row with as many actions as transitions)",
+        make=lambda g: g.chain_distinct(25_217)),
     "planted-quotient-10M": dict(
         desc="planted quotient: 487,805 quotient nodes, Poisson(10), Zipf(1.1) over 64 actions, "
              "U{1..40} copies, pi_0={S}, seed 1",

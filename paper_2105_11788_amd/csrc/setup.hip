@@ -119,20 +119,39 @@ __global__ void k_round_mark(const uint32_t* __restrict__ idx, uint32_t beg, uin
   }
 }
 // ... tag states whose mark differs from their leader's and elect (max of
-// (epoch, ~s) == smallest s of this round)
+// (epoch, ~s) == smallest s of this round).  A wave's 64 consecutive states
+// mostly share their block (a large block splits its whole remainder in a
+// round), so the splitting lanes of the first splitting lane's block bid once,
+// with their smallest state; the others bid one by one.
 __global__ void k_round_split(int32_t n, const int32_t* __restrict__ block,
                               const uint8_t* __restrict__ has, uint64_t* __restrict__ nlw,
                               uint8_t* __restrict__ flag, uint64_t epoch) {
-  GSTRIDE(s, (int64_t)n) {
-    int32_t b = block[s];
-    if (has[s] != has[b]) {
-      // the bids of one round only grow, so a bid not above the current
-      // value cannot win and skips the atomic
-      const uint64_t val = epoch | (uint64_t)(kNone - (uint32_t)s);
-      if (__hip_atomic_load(&nlw[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < val)
-        atomicMax((unsigned long long*)&nlw[b], (unsigned long long)val);
-      flag[s] = 1;
+  const int64_t waves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; w * kWave < n;
+       w += waves) {  // wave-uniform
+    const int64_t s = w * kWave + lane();
+    int32_t b = -1;
+    bool sp = false;
+    if (s < n) {
+      b = block[s];
+      sp = has[s] != has[b];
     }
+    const uint64_t bal = __ballot(sp);
+    if (!bal) continue;
+    const int l0 = __ffsll((unsigned long long)bal) - 1;
+    const int32_t b0 = __shfl(b, l0, kWave);
+    const bool same = sp && b == b0;
+    const uint32_t sm = wave_min_u32(same ? (uint32_t)s : kNone);
+    // the bids of one round only grow, so a bid not above the current value
+    // cannot win and skips the atomic
+    auto bid = [&](int32_t blk, uint32_t st) {
+      const uint64_t val = epoch | (uint64_t)(kNone - st);
+      if (__hip_atomic_load(&nlw[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < val)
+        atomicMax((unsigned long long*)&nlw[blk], (unsigned long long)val);
+    };
+    if ((int)lane() == l0) bid(b0, sm);
+    if (sp && !same) bid(b, (uint32_t)s);
+    if (sp) flag[s] = 1;
   }
 }
 // ... relabel, and advance every marked state's action count

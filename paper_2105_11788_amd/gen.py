@@ -170,6 +170,16 @@ def chain_tail(n: int = 100_000, permute_seed: Optional[int] = None) -> LTS:
     return LTS(n, 2, src, lab, dst, None, name=name)
 
 
+def chain_distinct(n: int = 25_217) -> LTS:
+    """s_i -i-> s_{i+1} for 0 <= i <= n-2: a chain whose every transition has
+    an action of its own (K = n - 1), the shape of the Table 1 row with as
+    many actions as transitions.  Every state's outgoing action set is its
+    own, so the preprocessing alone separates all states."""
+    assert n >= 2
+    src = np.arange(n - 1, dtype=np.int64)
+    return LTS(n, n - 1, src, src.copy(), src + 1, None, name=f"chain_distinct(n={n})")
+
+
 def sync_product(procs: int = 4, length: int = 30, K: int = 8,
                  shared=(6, 7), p_shared: float = 1.0 / 30.0, seed: int = 1) -> LTS:
     """Synchronised product of `procs` cyclic processes j -> j+1 mod `length`.

@@ -305,6 +305,20 @@ def test_chain_100k_full(B, engine):
 
 
 @pytest.mark.parametrize("engine", ENGINES)
+def test_distinct_actions_chain_full(B, engine):
+    """25,217 states, 25,216 transitions, each with an action of its own (the
+    shape of Table 1's row with as many actions as transitions): one round of
+    the action-by-action preprocessing per action, which alone separates all
+    states; then one iteration per block and a final pass."""
+    L = gen.chain_distinct(25_217)
+    pre = oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    r = run_gpu(B, L, engine=engine)
+    assert r["stats"].pre_blocks == L.n and r["stats"].iterations == L.n + 1
+    assert (r["block"] == np.arange(L.n)).all()
+    assert (r["block"] == pre["pre_block"]).all()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 def test_sync_product_full(B, engine):
     P = gen.sync_product(seed=1)
     ks, nb = oracle.ks_coarsest(P.n, P.K, P.src, P.lab, P.dst)

@@ -111,6 +111,21 @@ def test_chain_closed_form(n):
     assert nb == n and b.tolist() == list(range(n))
 
 
+@pytest.mark.parametrize("n", [2, 3, 50, 400])
+def test_distinct_actions_chain_closed_form(n):
+    # every state's outgoing action set ({i} for state i < n - 1, {} for the
+    # last) is its own: the preprocessing alone separates all states, then
+    # each singleton block is a splitter once and a final pass finds none
+    C = gen.chain_distinct(n)
+    assert C.K == n - 1 and len(np.unique(C.lab)) == n - 1
+    pre = oracle.preprocess(C.n, C.K, C.src, C.lab, C.dst, C.init)
+    assert pre["pre_block"].tolist() == list(range(n))
+    r = oracle.alg3_trace(C.n, C.K, C.src, C.lab, C.dst)
+    assert r["iters"] == n + 1
+    b, nb = oracle.ks_coarsest(C.n, C.K, C.src, C.lab, C.dst)
+    assert nb == n and b.tolist() == list(range(n))
+
+
 def test_chain_permuted_ids_same_blocks():
     C = gen.chain_tail(300, permute_seed=5)
     b, nb = oracle.ks_coarsest(C.n, C.K, C.src, C.lab, C.dst)
