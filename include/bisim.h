@@ -278,6 +278,21 @@ bisim_status bisim_set_trace(bisim_lts* h, int32_t* trace_C, int64_t* trace_nspl
  */
 bisim_status bisim_get_preprocessed(bisim_lts* h, int32_t* block_id, int32_t* nr_marks);
 
+/*
+ * bisim_get_preprocess_method — how lts_load computed pi_pre and the action
+ * ranks (section 4.1): *method (host) = 0 for Algorithm 4's rounds, one per
+ * action; 1 for the one-pass kernels (more than 64 actions and at most 64
+ * outgoing transitions per state: each state's distinct actions ranked and
+ * its action set hashed in one pass, states grouped by (pi_0 block, hash),
+ * every group checked exactly against its smallest state, the rounds run if
+ * the check fails).  Both give the same partition, ranks and counts.  Test
+ * hook: with the environment variable BISIM_ONEPASS_COLLIDE=1 at lts_load,
+ * every state's key collides, so the check fails (unless all states agree)
+ * and the rounds run.
+ * Errors: BISIM_E_INVALID.
+ */
+bisim_status bisim_get_preprocess_method(bisim_lts* h, int32_t* method);
+
 /* ------------------------------------------------------------------------ */
 /* Batched refinement: many independent LTSs in one launch                   */
 /* ------------------------------------------------------------------------ */

@@ -52,7 +52,7 @@ EXPORTS = ["lts_load", "coarsest_partition", "lts_free", "bisim_last_error",
            "mlp_get_params", "mlp_forward", "mlp_train_step", "bisim_set_splitter_policy",
            "bisim_collect_training", "bisim_get_phase_times", "bisim_device_copy",
            "coarsest_partition_noalloc", "bisim_get_work", "mlp_forward_bf16",
-           "bisim_get_run_config"]
+           "bisim_get_run_config", "bisim_get_preprocess_method"]
 
 # size of the static device region of coarsest_partition_noalloc (bisim.h)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -290,6 +290,16 @@ class LTS:
         L.bisim_get_run_config.restype = ctypes.c_int32
         _check(L.bisim_get_run_config(self._h, ctypes.byref(e), ctypes.byref(g)))
         return e.value, g.value
+
+    def preprocess_method(self):
+        """0: pi_pre from Algorithm 4's action rounds; 1: from the one-pass
+        kernels (checked exactly, the rounds run if the check fails)."""
+        L = self._L
+        v = ctypes.c_int32(0)
+        L.bisim_get_preprocess_method.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.bisim_get_preprocess_method.restype = ctypes.c_int32
+        _check(L.bisim_get_preprocess_method(self._h, ctypes.byref(v)))
+        return v.value
 
     def work(self):
         """Work totals of the last run with OPT_COUNT_WORK (engine 3): dict of

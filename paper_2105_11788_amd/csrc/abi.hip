@@ -262,4 +262,13 @@ bisim_status bisim_get_preprocessed(bisim_lts* h, int32_t* block_id, int32_t* nr
   return BISIM_OK;
 }
 
+bisim_status bisim_get_preprocess_method(bisim_lts* h, int32_t* method) {
+  if (!h || !method) {
+    set_error("bisim_get_preprocess_method: NULL handle or output");
+    return BISIM_E_INVALID;
+  }
+  *method = h->one_pass ? 1 : 0;
+  return BISIM_OK;
+}
+
 }  // extern "C"

@@ -186,6 +186,7 @@ struct bisim_lts {
   uint32_t* woff = nullptr;      // [n+1] mark-word offsets (only when !uniform)
   int uniform = 1;               // every state has <= 64 actions: word index = state
   uint32_t max_out = 0;          // largest number of outgoing transitions of a state
+  bool one_pass = false;         // pi_pre and the action ranks came from the one-pass kernels
   uint32_t max_ranks = 0;        // largest number of distinct actions of a state
   uint64_t nwords = 0;
   int64_t pre_blocks = 0;

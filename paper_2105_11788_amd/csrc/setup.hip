@@ -12,6 +12,7 @@
 //   6. transitions regrouped by target (CSR), carrying (source, order), so
 //      that the mark step can visit the in-transitions of the splitter's
 //      members instead of testing all m targets.
+#include <cstdlib>
 #include <vector>
 
 #include "internal.h"
@@ -211,6 +212,144 @@ __global__ void k_max_u32(int32_t n, const uint32_t* __restrict__ v, uint32_t* m
   if (lane() == 0) atomicMax(mx_out, mx);
 }
 
+// ---------------------------------------------------------------------------
+// One-pass preprocessing (many actions, every state with at most 64 outgoing
+// transitions).  The action-by-action rounds above reach the partition of
+// states by (pi_0 block, set of outgoing actions) and rank each state's
+// actions in increasing order; these kernels compute the same three results
+// directly: one wave per state ranks the state's actions among its distinct
+// actions and hashes the set; states are grouped by (pi_0 label, hash) in an
+// open-addressing table whose entries keep their smallest state; a second
+// pass checks every state's set and pi_0 label against its group leader's,
+// so a hash collision is detected (the caller then runs the rounds).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOnePassMaxOut = kWave;
+// with at most this many actions the rounds cost no more than the one pass's
+// extra passes over the transitions (at 10M states and 64 actions: 57 ms
+// against 86 ms)
+constexpr int32_t kOnePassMinK = 64;
+
+// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_out_scatter(const int32_t* __restrict__ src, int64_t m,
+                              uint32_t* __restrict__ cursor, uint32_t* __restrict__ out_idx) {
+  GSTRIDE(i, m) { out_idx[atomicAdd(&cursor[src[i]], 1u)] = (uint32_t)i; }
+}
+
+// the actions of state s in the lanes (lane j < d holds transition j's
+// action; other lanes hold none); wave-uniform
+struct LaneActions {
+  int32_t a;
+  bool valid;
+  uint32_t t;
+};
+__device__ __forceinline__ LaneActions lane_actions(const uint32_t* __restrict__ out_ptr,
+                                                    const uint32_t* __restrict__ out_idx,
+                                                    const int32_t* __restrict__ lab, int64_t s) {
+  const uint32_t p0 = out_ptr[s], d = out_ptr[s + 1] - p0;
+  LaneActions r{0, lane() < d, 0u};
+  if (r.valid) {
+    r.t = out_idx[p0 + lane()];
+    r.a = lab[r.t];
+  }
+  return r;
+}
+
+__global__ void k_sets(int32_t n, const uint32_t* __restrict__ out_ptr,
+                       const uint32_t* __restrict__ out_idx, const int32_t* __restrict__ lab,
+                       const int32_t* __restrict__ pi0, int32_t* __restrict__ ord,
+                       int32_t* __restrict__ nr_marks, unsigned long long* __restrict__ keys,
+                       uint32_t* __restrict__ minst, uint32_t cap_mask,
+                       uint32_t* __restrict__ slot, uint64_t key_mask, uint32_t* err) {
+  const int64_t waves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n;
+       s += waves) {  // wave-uniform
+    if (out_ptr[s + 1] - out_ptr[s] > kOnePassMaxOut) {  // the caller checked; never expected
+      if (lane() == 0) {
+        slot[s] = 0;
+        atomicOr(err, 1u);
+      }
+      continue;
+    }
+    const LaneActions x = lane_actions(out_ptr, out_idx, lab, s);
+    // the first lane holding an action represents it; the rank of an action
+    // is the number of distinct actions of s below it
+    bool dup = false;
+    uint32_t below = 0;
+    for (int k = 0; k < (int)kWave; ++k) {
+      const int32_t ak = __shfl(x.a, k, kWave);
+      const bool vk = __shfl((int)x.valid, k, kWave) != 0;
+      if (vk && ak == x.a && k < (int)lane()) dup = true;
+    }
+    const bool first = x.valid && !dup;
+    for (int k = 0; k < (int)kWave; ++k) {
+      const int32_t ak = __shfl(x.a, k, kWave);
+      const bool fk = __shfl((int)first, k, kWave) != 0;
+      if (fk && ak < x.a) ++below;
+    }
+    if (x.valid) ord[x.t] = (int32_t)below;
+    const uint32_t distinct = (uint32_t)__popcll(__ballot(first));
+    uint64_t h = first ? mix64((uint64_t)(uint32_t)x.a + 0x9E3779B97F4A7C15ull) : 0ull;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) h += (uint64_t)__shfl_xor((unsigned long long)h, d, kWave);
+    if (lane() == 0) {
+      nr_marks[s] = (int32_t)distinct;
+      const uint64_t key =
+          (mix64(h ^ mix64((uint64_t)(uint32_t)pi0[s] * 0x9E3779B97F4A7C15ull + distinct)) &
+           key_mask) | 1ull;
+      uint32_t q = (uint32_t)key & cap_mask;
+      bool placed = false;
+      for (uint32_t probe = 0; probe <= cap_mask && !placed; ++probe) {
+        const unsigned long long old = atomicCAS(&keys[q], 0ull, (unsigned long long)key);
+        placed = old == 0ull || old == key;
+        if (!placed) q = (q + 1u) & cap_mask;
+      }
+      if (!placed) atomicOr(err, 4u);  // a table of 2n entries cannot fill; never expected
+      atomicMin(&minst[q], (uint32_t)s);
+      slot[s] = q;
+    }
+  }
+}
+
+__global__ void k_sets_label(int32_t n, const uint32_t* __restrict__ minst,
+                             const uint32_t* __restrict__ slot, int32_t* __restrict__ block) {
+  GSTRIDE(s, (int64_t)n) { block[s] = (int32_t)minst[slot[s]]; }
+}
+
+// every state's pi_0 label and action set equal its group leader's
+__global__ void k_sets_verify(int32_t n, const uint32_t* __restrict__ out_ptr,
+                              const uint32_t* __restrict__ out_idx,
+                              const int32_t* __restrict__ lab, const int32_t* __restrict__ pi0,
+                              const int32_t* __restrict__ nr_marks,
+                              const int32_t* __restrict__ block, uint32_t* err) {
+  const int64_t waves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; s < n;
+       s += waves) {  // wave-uniform
+    const int32_t l = block[s];
+    if (l == (int32_t)s) continue;
+    if (l < 0 || l >= n || pi0[l] != pi0[s] || nr_marks[l] != nr_marks[s]) {
+      if (lane() == 0) atomicOr(err, 2u);
+      continue;
+    }
+    const LaneActions xs = lane_actions(out_ptr, out_idx, lab, s);
+    const LaneActions xl = lane_actions(out_ptr, out_idx, lab, l);
+    // with equal numbers of distinct actions, the sets are equal when each
+    // action of s is one of l's
+    bool found = !xs.valid;
+    for (int k = 0; k < (int)kWave; ++k) {
+      const int32_t ak = __shfl(xl.a, k, kWave);
+      const bool vk = __shfl((int)xl.valid, k, kWave) != 0;
+      if (vk && ak == xs.a) found = true;
+    }
+    if (__ballot(!found) && lane() == 0) atomicOr(err, 2u);
+  }
+}
+
 __global__ void k_in_scatter(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                              const int32_t* __restrict__ ord, int64_t m,
                              uint32_t* __restrict__ cursor, int32_t* __restrict__ in_src,
@@ -338,7 +477,69 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
                                  hipMemcpyDeviceToDevice, st));
   }
 
-  // 4. Algorithm 4 rounds, fused with the action ranking
+  // 4. pi_pre and the action ranks: in one pass when there are many actions
+  // and every state has at most 64 outgoing transitions (the rounds below
+  // cost three launches per action), else by Algorithm 4's action rounds;
+  // the one-pass result is checked and the rounds run if the check fails
+  bool rounds = true;
+  if (!arena_active() && K > kOnePassMinK && m > 0 && n > 0) {
+    uint32_t* odeg;
+    BISIM_TRY(tmp.get(&odeg, (size_t)n));
+    BISIM_TRY_HIP(hipMemsetAsync(odeg, 0, sizeof(uint32_t) * (size_t)n, st));
+    BISIM_TRY_HIP(hipMemsetAsync(red, 0, sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_indeg, dim3(grid_for(m, cu)), dim3(kT), 0, st, src, m, odeg);
+    hipLaunchKernelGGL(k_max_u32, dim3(gn), dim3(kT), 0, st, n, odeg, red);
+    uint32_t max_out = 0;
+    BISIM_TRY_HIP(hipMemcpyAsync(&max_out, red, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    BISIM_TRY_HIP(hipStreamSynchronize(st));
+    if (max_out <= kOnePassMaxOut) {
+      uint32_t *out_ptr, *out_idx, *minst, *slot, *err2;
+      int32_t* pi0;
+      unsigned long long* keys;
+      uint32_t cap = 64;
+      while (cap < 2u * (uint32_t)n) cap <<= 1;
+      BISIM_TRY(tmp.get(&out_ptr, (size_t)n + 1));
+      BISIM_TRY(tmp.get(&out_idx, (size_t)m));
+      BISIM_TRY(tmp.get(&pi0, (size_t)n));
+      BISIM_TRY(tmp.get(&keys, (size_t)cap));
+      BISIM_TRY(tmp.get(&minst, (size_t)cap));
+      BISIM_TRY(tmp.get(&slot, (size_t)n));
+      BISIM_TRY(tmp.get(&err2, 1));
+      BISIM_TRY(exclusive_scan_u32(odeg, out_ptr, n, st));
+      BISIM_TRY_HIP(hipMemcpyAsync(cursor, out_ptr, sizeof(uint32_t) * (size_t)n,
+                                   hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(k_out_scatter, dim3(grid_for(m, cu)), dim3(kT), 0, st, src, m, cursor,
+                         out_idx);
+      BISIM_TRY_HIP(hipMemcpyAsync(pi0, h->pre_block, sizeof(int32_t) * (size_t)n,
+                                   hipMemcpyDeviceToDevice, st));
+      BISIM_TRY_HIP(hipMemsetAsync(keys, 0, sizeof(unsigned long long) * cap, st));
+      hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(cap, cu)), dim3(kT), 0, st, minst, kNone,
+                         (int64_t)cap);
+      BISIM_TRY_HIP(hipMemsetAsync(err2, 0, sizeof(uint32_t), st));
+      const unsigned gw = grid_for((int64_t)n * kWave, cu);  // a wave per state
+      // test hook: BISIM_ONEPASS_COLLIDE=1 gives every state the same key, so
+      // the check fails wherever two states differ and the rounds run
+      const char* collide = getenv("BISIM_ONEPASS_COLLIDE");
+      const uint64_t key_mask = (collide && collide[0] == '1') ? 0ull : ~0ull;
+      hipLaunchKernelGGL(k_sets, dim3(gw), dim3(kT), 0, st, n, out_ptr, out_idx, lab, pi0, ord,
+                         h->nr_marks, keys, minst, cap - 1, slot, key_mask, err2);
+      hipLaunchKernelGGL(k_sets_label, dim3(gn), dim3(kT), 0, st, n, minst, slot, h->pre_block);
+      hipLaunchKernelGGL(k_sets_verify, dim3(gw), dim3(kT), 0, st, n, out_ptr, out_idx, lab, pi0,
+                         h->nr_marks, h->pre_block, err2);
+      BISIM_TRY_HIP(hipGetLastError());
+      uint32_t err2_h = 0;
+      BISIM_TRY_HIP(hipMemcpyAsync(&err2_h, err2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      BISIM_TRY_HIP(hipStreamSynchronize(st));
+      if (err2_h == 0) {
+        rounds = false;
+      } else {  // a hash collision merged two action sets: back to pi_0 and the rounds
+        BISIM_TRY_HIP(hipMemcpyAsync(h->pre_block, pi0, sizeof(int32_t) * (size_t)n,
+                                     hipMemcpyDeviceToDevice, st));
+      }
+    }
+  }
+  if (rounds) {
+  // Algorithm 4 rounds, fused with the action ranking
   BISIM_TRY_HIP(hipMemsetAsync(has, 0, (size_t)n, st));
   BISIM_TRY_HIP(hipMemsetAsync(flag, 0, (size_t)n, st));
   BISIM_TRY_HIP(hipMemsetAsync(h->nr_marks, 0, sizeof(int32_t) * (size_t)n, st));
@@ -365,6 +566,8 @@ bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
       BISIM_TRY_HIP(hipGetLastError());
     }
   }
+  }
+  h->one_pass = !rounds;
 
   // 5. slot statistics and mark-word layout
   BISIM_TRY_HIP(hipMemsetAsync(red, 0, sizeof(uint32_t) * 4, st));

@@ -4,6 +4,7 @@ Bar: bit-exact block ids (canonical, smallest member), identical iteration
 counts, and identical splitter / split-count traces, on every engine (1: one
 persistent launch, 2: a kernel per phase scanning all states, 3: a kernel per
 phase over member lists)."""
+import ctypes
 import json
 import os
 
@@ -302,6 +303,57 @@ def test_chain_100k_full(B, engine):
     r = run_gpu(B, L, engine=engine)
     assert r["stats"].iterations == 199_998
     assert (r["block"] == np.arange(100_000)).all()
+
+
+def _preprocessed(B, L, collide=False):
+    """(method, pi_pre, nr_marks) of lts_load on L; collide sets the test
+    hook that gives every state the same one-pass key."""
+    src, lab, dst, init = dev(L)
+    if collide:
+        os.environ["BISIM_ONEPASS_COLLIDE"] = "1"
+    try:
+        h = B.LTS(src, lab, dst, L.n, L.K, init)
+    finally:
+        os.environ.pop("BISIM_ONEPASS_COLLIDE", None)
+    with h:
+        pb = B.DeviceArray(max(L.n, 1), np.int32)
+        nm = B.DeviceArray(max(L.n, 1), np.int32)
+        L_ = B.load_library()
+        L_.bisim_get_preprocessed.argtypes = [ctypes.c_void_p] * 3
+        L_.bisim_get_preprocessed.restype = ctypes.c_int32
+        assert L_.bisim_get_preprocessed(h._h, pb.ptr, nm.ptr) == 0
+        return h.preprocess_method(), pb.numpy()[:L.n], nm.numpy()[:L.n]
+
+
+@pytest.mark.parametrize("case", ["zipf100", "zipf200", "distinct", "init_partition"])
+def test_one_pass_preprocessing_matches_the_rounds(B, case):
+    """Many actions and at most 64 outgoing transitions per state: pi_pre and
+    the action counts come from the one-pass kernels and equal the oracle's
+    Algorithm 4 (section 4.1); with every key made to collide the exact check
+    fails and the rounds give the same arrays.  The whole refinement then
+    matches the oracle (partition, iterations, splitter trace), which also
+    checks the action ranks the marks are laid out by."""
+    L = {"zipf100": lambda: gen.uniform_zipf(800, 4000, 100, seed=31),
+         "zipf200": lambda: gen.uniform_zipf(3000, 12000, 200, seed=32),
+         "distinct": lambda: gen.chain_distinct(2000),
+         "init_partition": lambda: gen.random_lts(600, 2400, 80, seed=33, init_blocks=5)}[case]()
+    pre = oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    method, pb, nm = _preprocessed(B, L)
+    assert method == 1
+    assert (pb == pre["pre_block"]).all() and (nm == pre["nr_marks"]).all()
+    method_c, pb_c, nm_c = _preprocessed(B, L, collide=True)
+    assert method_c == 0
+    assert (pb_c == pb).all() and (nm_c == nm).all()
+    assert_parity(B, L)
+
+
+def test_one_pass_preprocessing_not_taken(B):
+    # few actions, or a state with more than 64 outgoing transitions: rounds
+    assert _preprocessed(B, gen.uniform_zipf(500, 2000, 64, seed=34))[0] == 0
+    L = gen.uniform_zipf(100, 8000, 90, seed=35)  # about 80 outgoing transitions per state
+    method, pb, nm = _preprocessed(B, L)
+    pre = oracle.preprocess(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    assert method == 0 and (pb == pre["pre_block"]).all() and (nm == pre["nr_marks"]).all()
 
 
 @pytest.mark.parametrize("engine", ENGINES)
