@@ -339,17 +339,19 @@ def cpu_baseline_batch(insts, its, count, n_hi, target_s: float = 12.0, workers:
 
 
 def host_cpu():
-    """CPU model and logical core count of the host that ran the baseline."""
-    model = "unknown"
+    """CPU model, clock (as /proc/cpuinfo reports it) and logical core count
+    of the host that ran the baseline."""
+    model, mhz = "unknown", None
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
+                if line.startswith("model name") and model == "unknown":
                     model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
+                elif line.startswith("cpu MHz") and mhz is None:
+                    mhz = float(line.split(":", 1)[1])
+    except (OSError, ValueError):
         pass
-    return {"model": model, "logical_cpus": os.cpu_count()}
+    return {"model": model, "mhz": mhz, "logical_cpus": os.cpu_count()}
 
 
 def sem(xs):
@@ -722,8 +724,35 @@ def form_learned(bisim, gen, args):
     assert (rp["block"] == rl["block"]).all(), "learned policy changed the partition"
     ip, il = rp["stats"].iterations, rl["stats"].iterations
     log(f"plain #It={ip} {rp['ms_per_step']:.1f} ms; learned #It={il} {rl['ms_per_step']:.1f} ms")
+    # for context: the same policy machinery with an untrained network (random
+    # weights), which orders splitters arbitrarily
+    untrained = bisim.MLP(bisim.POLICY_FEATURES, seed=12345)
+    ru = run_single(bisim, L, argparse.Namespace(**{**vars(args), "steps": 1, "warmup": 0}),
+                    args.engine, mlp=untrained, trace=False)
+    assert (ru["block"] == rp["block"]).all()
+    iu = ru["stats"].iterations
+    log(f"untrained network #It={iu}")
+    # held-out LTSs of the training shape: plain (per-phase engine) against the
+    # learned and the untrained network, iterations and time to the fixpoint
+    held = []
+    for regime in ("kripke", "zipf64"):
+        for seed in range(2001, 2007):
+            H = learn.training_lts(regime, seed)
+            row = {"regime": regime, "seed": seed}
+            for name, net in (("plain", None), ("learned", mlp), ("untrained", untrained)):
+                learn.iterations(H, net, engine=2)  # first call: set-up
+                it_, blk_, ms_ = learn.iterations(H, net, engine=2)
+                row[name] = {"iterations": int(it_), "t_alg_ms": float(ms_)}
+            held.append(row)
+    ratio = lambda key, f: float(np.mean([r[f][key] / r["plain"][key] for r in held]))
+    held_summary = {"lts": len(held),
+                    "iteration_ratio_learned_over_plain": ratio("iterations", "learned"),
+                    "wall_ratio_learned_over_plain": ratio("t_alg_ms", "learned"),
+                    "iteration_ratio_untrained_over_plain": ratio("iterations", "untrained")}
+    log(f"held-out LTSs: {held_summary}")
     cfg = {"workload": args.workload, "description": wl["desc"], "n": L.n, "m": L.m, "K": L.K,
            "form": "learned", "iterations": il, "plain_iterations": ip,
+           "untrained_network_iterations": iu,
            "rescore_every": args.rescore, "train_rows": rows, "train_seconds": t_train}
     res = base_record(args, "transitions*iterations/sec (learned-splitter refinement)",
                       L.m * il / (rl["ms_per_step"] * 1e-3), rl["ms_per_step"], cfg)
@@ -731,7 +760,8 @@ def form_learned(bisim, gen, args):
                 "plain_seconds_to_fixpoint": rp["ms_per_step"] / 1000.0,
                 "iteration_ratio_learned_over_plain": il / ip,
                 "wall_ratio_learned_over_plain": rl["ms_per_step"] / rp["ms_per_step"],
-                "partition_equal": True})
+                "partition_equal": True,
+                "held_out": {"summary": held_summary, "runs": held}})
     return res
 
 
