@@ -287,22 +287,33 @@ __global__ void __launch_bounds__(kLT) k_l_mark(LArgs a, uint32_t kofs) {
         // a touched leader of a one-state block has no untouched member
         lead = first && b == s && hi_ > lo_ + 1 && hi_ <= a.n;
       }
-      count_work(a, 2, (uint64_t)__popcll(__ballot(first)));
-      const uint32_t ti = reserve(&a.ctl->cntT[par].v[0], first);
-      if (first && ti < a.n) {
-        a.ts[ti] = s;
-        a.tbk[ti] = b;
-      }
-      // the listed block's member segments (wave-aggregated reservation),
-      // each recorded with its absolute position range
+      // list entries for first touches and for the listed block's member
+      // segments (each with its absolute position range): both wave-aggregated
+      // reservations are issued before either result is used
+      const uint64_t tbal = __ballot(first);
+      count_work(a, 2, (uint64_t)__popcll(tbal));
       const uint32_t nseg = lead ? (hi_ - lo_ + kSeg - 1) / kSeg : 0u;
       const uint32_t sincl = wave_incl_scan_u32(nseg);
       const uint32_t stot = (uint32_t)__shfl((int)sincl, kWave - 1, kWave);
       count_work(a, 3, stot);
+      const uint32_t tcnt = (uint32_t)__popcll(tbal);
+      uint32_t tbase = 0, sbase = 0;
+      if (lane() == 0 && (tcnt | stot) != 0) {
+        // one lane, both atomics in flight before either result is waited
+        // for; the lane-dependent (always 0) slot keeps the compiler from
+        // rewriting each into a wave-wide reduction with its own wait
+        const uint32_t z = lane();
+        tbase = atomicAdd(&a.ctl->cntT[par].v[z], tcnt);
+        sbase = atomicAdd(&a.ctl->cntC[par].v[z], stot);
+      }
+      tbase = (uint32_t)__shfl((int)tbase, 0, kWave);
+      const uint32_t ti = tbase + (uint32_t)__popcll(tbal & ((1ull << lane()) - 1ull));
+      if (first && ti < a.n) {
+        a.ts[ti] = s;
+        a.tbk[ti] = b;
+      }
       if (stot) {
-        uint32_t base = 0;
-        if (lane() == kWave - 1) base = atomicAdd(&a.ctl->cntC[par].v[0], stot);
-        base = (uint32_t)__shfl((int)base, kWave - 1, kWave) + sincl - nseg;
+        const uint32_t base = (uint32_t)__shfl((int)sbase, 0, kWave) + sincl - nseg;
         for (uint32_t q = 0; q < nseg; ++q) {
           if (base + q >= a.lcap) break;  // never expected (capacity covers every block)
           a.lb[base + q] = s;
