@@ -42,6 +42,12 @@ def test_last_error_without_gpu():
     assert b"n >= 0" in L.bisim_last_error()
     assert L.lts_load(None, None, None, 1, 0, 0, None, None, ctypes.byref(h)) == bisim.E_INVALID
     assert L.bisim_set_option(None, 1, 0) == bisim.E_INVALID
+    # the query calls reject a NULL handle the same way
+    v = ctypes.c_int32(0)
+    L.bisim_get_preprocess_method.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert L.bisim_get_preprocess_method(None, ctypes.byref(v)) == bisim.E_INVALID
+    L.bisim_get_run_config.argtypes = [ctypes.c_void_p] * 3
+    assert L.bisim_get_run_config(None, ctypes.byref(v), ctypes.byref(v)) == bisim.E_INVALID
 
 
 def test_noalloc_rejects_oversize_before_device_work():
