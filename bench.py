@@ -603,8 +603,7 @@ def form_signature(bisim, gen, args):
                       L.m * st.iterations / (ms * 1e-3), ms, cfg)
     res.update({"seconds_to_fixpoint": ms / 1000.0, "t_pre_ms": st.t_pre_ms,
                 "t_alg_ms": float(np.mean(alg_ms)), "roofline": None,
-                "note": "a comparison baseline, not the paper's method; signature rounds "
-                        "are dominated by library radix sorts"})
+                "note": "a comparison baseline, not the paper's method"})
     return res
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbisim.so")
-SOURCES = ["abi.hip", "setup.hip", "refine.hip", "signature.hip", "scan.hip", "batch.hip", "mlp.hip", "util.hip", "noalloc.hip", "lists.hip"]
+SOURCES = ["abi.hip", "setup.hip", "refine.hip", "signature.hip", "scan.hip", "batch.hip", "mlp.hip", "util.hip", "noalloc.hip", "lists.hip", "sort.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -274,6 +274,17 @@ bisim_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count
 // upper bound of the device memory exclusive_scan_u32 takes for `count`
 // values (as dev_alloc counts it: each piece rounded up to 256 bytes)
 size_t exclusive_scan_scratch_bytes(int64_t count);
+// sort.hip: stable least-significant-digit radix sort of 64-bit keys by bits
+// [begin_bit, end_bit), carrying 32-bit values when vals_in is not NULL
+// (keys_in and vals_in are left as they were; temp holds
+// radix_sort_temp_bytes(count, vals_in != NULL) bytes), and an inclusive
+// max-scan over uint32
+size_t radix_sort_temp_bytes(int64_t count, bool with_values);
+bisim_status radix_sort_u64(void* temp, size_t temp_bytes, const uint64_t* keys_in,
+                            uint64_t* keys_out, const uint32_t* vals_in, uint32_t* vals_out,
+                            int64_t count, int begin_bit, int end_bit, hipStream_t stream);
+bisim_status inclusive_max_scan_u32(const uint32_t* in, uint32_t* out, int64_t count,
+                                    hipStream_t stream);
 // setup.hip
 bisim_status setup_load(bisim_lts* h, const int32_t* src, const int32_t* lab,
                         const int32_t* dst, const int32_t* init);

@@ -7,15 +7,23 @@
 // sig(s) = {(a, block(t)) : s -a-> t} and regroups the states by
 // (block(s), sig(s)); a new block is named by its smallest state.  The round
 // that changes nothing ends the run.  A round on the GPU:
-//   1. key[e] = (source << 32) | (rank * n + block(target)) for every
-//      transition (rank: the action's rank among the source's actions; within
-//      a block of pi_pre, and so of every later partition, ranks name the same
-//      actions, so (rank, block) pairs stand for (action, block) pairs);
-//   2. radix sort of the keys, so equal (s, a, block) triples are adjacent;
-//   3. sig(s) = sum over the distinct triples of a 64-bit hash of (rank,
-//      block) (a set hash: duplicates count once), reduced per wave over the
-//      sorted segments;
-//   4. radix sort of the states by a hash of (block(s), sig(s)), stable in
+//   1. every transition s -a-> t gets the value x = rank * n + block(t)
+//      (rank: the action's rank among the source's actions; within a block of
+//      pi_pre, and so of every later partition, ranks name the same actions,
+//      so (rank, block) pairs stand for (action, block) pairs);
+//   2. sig(s) = sum over the distinct values of s of a 64-bit hash of x (a
+//      set hash: duplicates count once).  The first kSortedRounds rounds give
+//      every transition the key (s << xbits) | x (xbits: the bits that
+//      x < (actions per state) * n needs) and radix-sort the keys, so equal
+//      pairs are adjacent, and reduce per wave over the sorted segments.  The
+//      last of them sorts the transitions' indices along, and its order is
+//      kept as the transitions' layout by source: in later rounds a source
+//      with at most 64 transitions is handled by the lanes of one or two
+//      waves, each lane comparing its x with the earlier ones of its source
+//      by shuffles, and only the transitions of larger sources are sorted.
+//      (Shallow LTSs reach the fixpoint within the sorted rounds: there the
+//      layout, about as costly as two sorted rounds, would not pay.);
+//   3. radix sort of the states by a hash of (block(s), sig(s)), stable in
 //      the state index, so each run of equal hashes starts at its smallest
 //      state; a max-scan of the run heads names every state's new block.
 // Hashing can only merge states with different signatures, never separate
@@ -31,8 +39,6 @@
 // Algorithm 3 from the partition reached, every block unstable.  That
 // partition refines pi_pre (checked) and is at least as coarse as the
 // coarsest stable one, so Algorithm 3 ends in the same result.
-#include <hipcub/hipcub.hpp>
-
 #include "internal.h"
 
 namespace bisim {
@@ -58,19 +64,138 @@ __global__ void k_targets(int32_t n, const uint32_t* __restrict__ in_ptr,
   }
 }
 
-__global__ void k_keys(int64_t m, uint32_t n, const int32_t* __restrict__ in_src,
+// key[e] = (source << xbits) | x for every transition, and idx[e] = e when
+// idx is given (the sort that lays the transitions out carries them)
+__global__ void k_keys(int64_t m, uint32_t n, int xbits, const int32_t* __restrict__ in_src,
                        const int32_t* __restrict__ in_ord, const int32_t* __restrict__ tgt,
-                       const int32_t* __restrict__ blk, uint64_t* __restrict__ key) {
+                       const int32_t* __restrict__ blk, uint64_t* __restrict__ key,
+                       uint32_t* __restrict__ idx) {
   SSTRIDE(e, m) {
-    key[e] = ((uint64_t)(uint32_t)in_src[e] << 32) |
+    key[e] = ((uint64_t)(uint32_t)in_src[e] << xbits) |
              (uint32_t)((uint32_t)in_ord[e] * n + (uint32_t)blk[tgt[e]]);
+    if (idx) idx[e] = (uint32_t)e;
+  }
+}
+
+// the by-source layout from the first round's sorted keys and indices
+__global__ void k_layout(int64_t m, uint32_t n, int xbits, const uint64_t* __restrict__ keys,
+                         const uint32_t* __restrict__ perm, const int32_t* __restrict__ in_ord,
+                         const int32_t* __restrict__ tgt, int32_t* __restrict__ o_src,
+                         uint32_t* __restrict__ o_rn, int32_t* __restrict__ o_tgt) {
+  SSTRIDE(p, m) {
+    const uint32_t e = perm[p];
+    o_src[p] = (int32_t)(keys[p] >> xbits);
+    o_rn[p] = (uint32_t)in_ord[e] * n;
+    o_tgt[p] = tgt[e];
+  }
+}
+
+// out_ptr[s] = the first position whose source is s or larger (out_ptr[n] = m):
+// every position writes the entries of the sources from just after its
+// predecessor's up to its own
+__global__ void k_seg_starts(int64_t m, int32_t n, const int32_t* __restrict__ o_src,
+                             uint32_t* __restrict__ out_ptr) {
+  SSTRIDE(p, m + 1) {
+    const int32_t lo = p == 0 ? -1 : o_src[p - 1];
+    const int32_t hi = p == m ? n : o_src[p];
+    for (int32_t s = lo + 1; s <= hi; ++s) out_ptr[s] = (uint32_t)p;
+  }
+}
+
+// positions (in the by-source layout) of the transitions of sources with more
+// than kWave transitions
+__global__ void __launch_bounds__(kT) k_big_list(int64_t m, const int32_t* __restrict__ o_src,
+                                                 const uint32_t* __restrict__ out_ptr,
+                                                 int32_t* __restrict__ big,
+                                                 uint32_t* __restrict__ count) {
+  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave * kWave; b0 < m;
+       b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = b0 + lane();
+    bool is_big = false;
+    if (e < m) {
+      const int32_t s = o_src[e];
+      is_big = out_ptr[s + 1] - out_ptr[s] > (uint32_t)kWave;
+    }
+    wave_push(big, count, (int32_t)e, is_big);
+  }
+}
+
+__global__ void k_keys_big(int64_t mb, int xbits, const int32_t* __restrict__ big,
+                           const int32_t* __restrict__ o_src, const uint32_t* __restrict__ o_rn,
+                           const int32_t* __restrict__ o_tgt, const int32_t* __restrict__ blk,
+                           uint64_t* __restrict__ key) {
+  SSTRIDE(i, mb) {
+    const int32_t e = big[i];
+    key[i] = ((uint64_t)(uint32_t)o_src[e] << xbits) |
+             (uint32_t)(o_rn[e] + (uint32_t)blk[o_tgt[e]]);
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+  return v;
+}
+
+// sig[s] += hash(x) over the distinct values x of the sources with at most
+// kWave transitions, one lane per transition of the by-source layout.  A
+// lane's value is a duplicate if an earlier transition of its source has it:
+// those in the same wave are reached by shuffles, those before the wave (a
+// source that starts in the previous wave) by loads.  One atomic per source
+// piece within a wave.  All lanes of a wave reach the shuffles.
+__global__ void __launch_bounds__(kT) k_sig_small(int64_t m, const int32_t* __restrict__ o_src,
+                                                  const uint32_t* __restrict__ o_rn,
+                                                  const int32_t* __restrict__ o_tgt,
+                                                  const uint32_t* __restrict__ out_ptr,
+                                                  const int32_t* __restrict__ blk, uint64_t seed,
+                                                  uint64_t* __restrict__ sig) {
+  const int64_t waves = (int64_t)gridDim.x * (kT / kWave);
+  const int64_t gw = (int64_t)blockIdx.x * (kT / kWave) + threadIdx.x / kWave;
+  const int l = (int)lane();
+  for (int64_t base = gw * kWave; base < m; base += waves * kWave) {
+    const int64_t e = base + l;
+    int32_t s = -1;
+    uint32_t lo = 0, hi = 0, x = 0;
+    if (e < m) {
+      s = o_src[e];
+      lo = out_ptr[s];
+      hi = out_ptr[s + 1];
+    }
+    const bool small = e < m && hi - lo <= (uint32_t)kWave;
+    if (small) x = o_rn[e] + (uint32_t)blk[o_tgt[e]];
+    // earlier transitions of the source inside this wave: lanes l - back .. l - 1
+    const int64_t first = (int64_t)lo > base ? (int64_t)lo : base;
+    const uint32_t back = small ? (uint32_t)(e - first) : 0u;
+    const uint32_t reach = wave_max_u32(back);
+    bool dup = false;
+    for (uint32_t d = 1; d <= reach; ++d) {
+      const uint32_t xd = (uint32_t)__shfl_up((int)x, d, kWave);
+      dup |= d <= back && xd == x;
+    }
+    if (small && (int64_t)lo < base) {
+      for (int64_t j = lo; j < base; ++j) dup |= o_rn[j] + (uint32_t)blk[o_tgt[j]] == x;
+    }
+    uint64_t v = (small && !dup) ? mix64((uint64_t)x + seed) : 0ull;
+    const int32_t s_next = __shfl_down(s, 1, kWave);
+    const bool tail = small && (l == kWave - 1 || e + 1 >= m || s_next != s);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {  // inclusive prefix sum (mod 2^64)
+      const uint64_t t = (uint64_t)__shfl_up((unsigned long long)v, d, kWave);
+      if (l >= d) v += t;
+    }
+    const uint64_t tails = __ballot(tail);
+    const uint64_t below = tails & ((1ull << l) - 1ull);
+    const int prev = below ? 63 - __clzll((long long)below) : -1;
+    const uint64_t pv = (uint64_t)__shfl((unsigned long long)v, prev < 0 ? 0 : prev, kWave);
+    if (tail) atomicAdd((unsigned long long*)&sig[s], (unsigned long long)(v - (prev < 0 ? 0ull : pv)));
   }
 }
 
 // sig[s] += hash(rank, block) over the distinct sorted keys of source s; one
 // atomic per segment piece within a wave (all lanes of a wave reach the
 // shuffles).
-__global__ void __launch_bounds__(kT) k_sig_sum(int64_t m, const uint64_t* __restrict__ key,
+__global__ void __launch_bounds__(kT) k_sig_sum(int64_t m, int xbits,
+                                                const uint64_t* __restrict__ key,
                                                 uint64_t seed, uint64_t* __restrict__ sig) {
   const int64_t waves = (int64_t)gridDim.x * (kT / kWave);
   const int64_t gw = (int64_t)blockIdx.x * (kT / kWave) + threadIdx.x / kWave;
@@ -81,8 +206,8 @@ __global__ void __launch_bounds__(kT) k_sig_sum(int64_t m, const uint64_t* __res
     const uint64_t k = valid ? key[e] : ~0ull;
     const uint64_t kp = (valid && e > 0) ? key[e - 1] : ~0ull;
     const bool distinct = valid && (e == 0 || k != kp);
-    const uint32_t s = (uint32_t)(k >> 32);
-    uint64_t v = distinct ? mix64((k & 0xFFFFFFFFull) + seed) : 0ull;
+    const uint32_t s = (uint32_t)(k >> xbits);
+    uint64_t v = distinct ? mix64((k & ((1ull << xbits) - 1ull)) + seed) : 0ull;
     const uint32_t s_next = (uint32_t)__shfl_down((int)s, 1, kWave);
     const bool tail = valid && (l == kWave - 1 || !(e + 1 < m) || s_next != s);
 #pragma unroll
@@ -98,11 +223,12 @@ __global__ void __launch_bounds__(kT) k_sig_sum(int64_t m, const uint64_t* __res
   }
 }
 
-__global__ void k_state_keys(int32_t n, const int32_t* __restrict__ blk,
+// hk[s]: the low hbits of a hash of (block(s), sig(s))
+__global__ void k_state_keys(int32_t n, uint64_t hmask, const int32_t* __restrict__ blk,
                              const uint64_t* __restrict__ sig, uint64_t* __restrict__ hk,
                              int32_t* __restrict__ idx) {
   SSTRIDE(s, (int64_t)n) {
-    hk[s] = mix64(sig[s] ^ mix64((uint64_t)(uint32_t)blk[s] + 0x9E3779B97F4A7C15ull));
+    hk[s] = hmask & mix64(sig[s] ^ mix64((uint64_t)(uint32_t)blk[s] + 0x9E3779B97F4A7C15ull));
     idx[s] = (int32_t)s;
   }
 }
@@ -147,7 +273,7 @@ unsigned grid_of(int64_t work, int cu) {
 // device buffers of one run, freed on every exit
 struct Bufs {
   hipStream_t st;
-  void* p[16] = {};
+  void* p[24] = {};
   int k = 0;
   ~Bufs() {
     for (int i = 0; i < k; ++i) (void)hipFreeAsync(p[i], st);
@@ -156,7 +282,7 @@ struct Bufs {
   bisim_status get(T** out, size_t count) {
     void* q = nullptr;
     if (count == 0) count = 1;
-    if (k == 16) {
+    if (k == 24) {
       set_error("signature refinement: too many buffers");
       return BISIM_E_INVALID;
     }
@@ -173,6 +299,8 @@ struct Bufs {
 }  // namespace
 
 constexpr int64_t kHybridStall = 64;
+// rounds that sort all transitions; the last of them lays the transitions out
+constexpr int64_t kSortedRounds = 4;
 
 // Signature rounds from pi_pre into out (device int32[n]): to the fixpoint
 // (stall = 0), or until two consecutive rounds each add fewer than stall
@@ -189,12 +317,11 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
   }
   const int cu = h->num_cu;
   Bufs b{st};
-  int32_t *tgt, *blk, *nb, *idx, *idxs, *hp, *hp2;
+  int32_t *tgt, *blk, *nb, *idx, *idxs, *hp, *hp2, *o_src, *o_tgt, *big;
+  uint32_t *out_ptr, *o_rn, *nbig, *pidx = nullptr, *perm = nullptr;
   uint64_t *key, *keys, *sig, *hk, *hks;
   unsigned long long* cnt;
   BISIM_TRY(b.get(&tgt, (size_t)m));
-  BISIM_TRY(b.get(&key, (size_t)m));
-  BISIM_TRY(b.get(&keys, (size_t)m));
   BISIM_TRY(b.get(&blk, (size_t)n));
   BISIM_TRY(b.get(&nb, (size_t)n));
   BISIM_TRY(b.get(&idx, (size_t)n));
@@ -205,20 +332,94 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
   BISIM_TRY(b.get(&hk, 2 * (size_t)n));
   BISIM_TRY(b.get(&cnt, 2));
   hks = hk + n;
-
-  int kbits = 1;  // bits of the source index in the key's high half
-  while (kbits < 31 && (1ll << kbits) < n) ++kbits;
-  size_t t1 = 0, t2 = 0, t3 = 0;
-  BISIM_TRY_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, t1, key, keys, (int)m, 0, 32 + kbits, st));
-  BISIM_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, hk, hks, idx, idxs, n, 0, 64, st));
-  BISIM_TRY_HIP(hipcub::DeviceScan::InclusiveScan(nullptr, t3, hp, hp2, hipcub::Max(), n, st));
-  size_t tb = t1 > t2 ? t1 : t2;
-  if (t3 > tb) tb = t3;
-  uint8_t* temp;
-  BISIM_TRY(b.get(&temp, tb));
+  o_src = o_tgt = big = nullptr;
+  out_ptr = o_rn = nbig = nullptr;
 
   if (m > 0) hipLaunchKernelGGL(k_targets, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, h->in_ptr, tgt);
   BISIM_TRY_HIP(hipGetLastError());
+  BISIM_TRY(b.get(&key, (size_t)m));
+  BISIM_TRY(b.get(&keys, (size_t)m));
+  // key widths: source bits above xbits bits of x < max_ranks * n; the state
+  // hash keeps 2 log2(n) + 24 bits (whole bytes), so that two of at most n
+  // groups share a hash with probability below 2^-25 per round (a merge is
+  // caught by the check, which then repeats the run with other seeds)
+  int kbits = 1;
+  while (kbits < 31 && (1ll << kbits) < n) ++kbits;
+  int xbits = 1;
+  while (xbits < 32 && (1ull << xbits) < (uint64_t)(h->max_ranks ? h->max_ranks : 1) * (uint64_t)n)
+    ++xbits;
+  const int hbits = 2 * kbits + 24 >= 64 ? 64 : (2 * kbits + 24 + 7) / 8 * 8;
+  const uint64_t hmask = hbits >= 64 ? ~0ull : (1ull << hbits) - 1ull;
+  const size_t t1 = radix_sort_temp_bytes(m, false), t2 = radix_sort_temp_bytes(n, true);
+  const size_t tb = t1 > t2 ? t1 : t2;
+  uint8_t* temp;
+  BISIM_TRY(b.get(&temp, tb));
+
+  // the by-source layout, and the list of the transitions whose source has
+  // more than a wave's worth (they stay with the sort)
+  bool by_source = false;
+  uint32_t mb = 0;
+  int64_t sorted_keys = 0;  // keys[0, sorted_keys): the last round's sorted keys
+  auto lay_out = [&]() -> bisim_status {
+    BISIM_TRY(b.get(&o_src, (size_t)m));
+    BISIM_TRY(b.get(&o_rn, (size_t)m));
+    BISIM_TRY(b.get(&o_tgt, (size_t)m));
+    BISIM_TRY(b.get(&big, (size_t)m));
+    BISIM_TRY(b.get(&out_ptr, (size_t)n + 1));
+    BISIM_TRY(b.get(&nbig, 1));
+    hipLaunchKernelGGL(k_layout, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, (uint32_t)n, xbits, keys,
+                       perm, h->in_ord, tgt, o_src, o_rn, o_tgt);
+    hipLaunchKernelGGL(k_seg_starts, dim3(grid_of(m + 1, cu)), dim3(kT), 0, st, m, n, o_src,
+                       out_ptr);
+    BISIM_TRY_HIP(hipMemsetAsync(nbig, 0, sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_big_list, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, o_src, out_ptr, big,
+                       nbig);
+    BISIM_TRY_HIP(hipGetLastError());
+    BISIM_TRY_HIP(hipMemcpyAsync(&mb, nbig, sizeof(mb), hipMemcpyDeviceToHost, st));
+    BISIM_TRY_HIP(hipStreamSynchronize(st));
+    by_source = true;
+    return BISIM_OK;
+  };
+  // sig[s] = the set hash of s's (rank, block) pairs under `sd`
+  // (lay: sort the transitions' indices along and keep the order as the layout)
+  auto signatures = [&](uint64_t sd, bool lay) -> bisim_status {
+    BISIM_TRY_HIP(hipMemsetAsync(sig, 0, sizeof(uint64_t) * n, st));
+    if (m == 0) return BISIM_OK;
+    if (!by_source) {
+      if (lay) {
+        const size_t tbv = radix_sort_temp_bytes(m, true);
+        uint8_t* tv;
+        BISIM_TRY(b.get(&pidx, (size_t)m));
+        BISIM_TRY(b.get(&perm, (size_t)m));
+        BISIM_TRY(b.get(&tv, tbv));
+        hipLaunchKernelGGL(k_keys, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, (uint32_t)n, xbits,
+                           h->in_src, h->in_ord, tgt, blk, key, pidx);
+        BISIM_TRY(radix_sort_u64(tv, tbv, key, keys, pidx, perm, m, 0, xbits + kbits, st));
+      } else {
+        hipLaunchKernelGGL(k_keys, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, (uint32_t)n, xbits,
+                           h->in_src, h->in_ord, tgt, blk, key, (uint32_t*)nullptr);
+        BISIM_TRY(radix_sort_u64(temp, tb, key, keys, nullptr, nullptr, m, 0, xbits + kbits, st));
+      }
+      hipLaunchKernelGGL(k_sig_sum, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, xbits, keys, sd,
+                         sig);
+      BISIM_TRY_HIP(hipGetLastError());
+      sorted_keys = m;
+      return lay ? lay_out() : BISIM_OK;
+    }
+    hipLaunchKernelGGL(k_sig_small, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, o_src, o_rn, o_tgt,
+                       out_ptr, blk, sd, sig);
+    if (mb > 0) {
+      hipLaunchKernelGGL(k_keys_big, dim3(grid_of(mb, cu)), dim3(kT), 0, st, (int64_t)mb, xbits,
+                         big, o_src, o_rn, o_tgt, blk, key);
+      BISIM_TRY(radix_sort_u64(temp, tb, key, keys, nullptr, nullptr, mb, 0, xbits + kbits, st));
+      hipLaunchKernelGGL(k_sig_sum, dim3(grid_of(mb, cu)), dim3(kT), 0, st, (int64_t)mb, xbits,
+                         keys, sd, sig);
+    }
+    BISIM_TRY_HIP(hipGetLastError());
+    sorted_keys = mb;
+    return BISIM_OK;
+  };
+
   BISIM_TRY_HIP(hipEventRecord(h->ev0, st));
   int64_t rounds = 0;
   unsigned long long blocks = (unsigned long long)h->pre_blocks;
@@ -231,23 +432,14 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     bool prev_few = false;
     for (;;) {
       ++rounds;
-      size_t tb1 = tb;
-      if (m > 0) {
-        hipLaunchKernelGGL(k_keys, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, (uint32_t)n,
-                           h->in_src, h->in_ord, tgt, blk, key);
-        BISIM_TRY_HIP(hipcub::DeviceRadixSort::SortKeys(temp, tb1, key, keys, (int)m, 0,
-                                                       32 + kbits, st));
-      }
-      BISIM_TRY_HIP(hipMemsetAsync(sig, 0, sizeof(uint64_t) * n, st));
-      if (m > 0)
-        hipLaunchKernelGGL(k_sig_sum, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, keys, seed, sig);
-      hipLaunchKernelGGL(k_state_keys, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, blk, sig, hk, idx);
-      tb1 = tb;
-      BISIM_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(temp, tb1, hk, hks, idx, idxs, n, 0, 64, st));
+      BISIM_TRY(signatures(seed, rounds == kSortedRounds));
+      hipLaunchKernelGGL(k_state_keys, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, hmask, blk, sig,
+                         hk, idx);
+      BISIM_TRY(radix_sort_u64(temp, tb, hk, hks, (const uint32_t*)idx, (uint32_t*)idxs, n, 0,
+                               hbits, st));
       BISIM_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
       hipLaunchKernelGGL(k_heads, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, hks, hp, cnt);
-      tb1 = tb;
-      BISIM_TRY_HIP(hipcub::DeviceScan::InclusiveScan(temp, tb1, hp, hp2, hipcub::Max(), n, st));
+      BISIM_TRY(inclusive_max_scan_u32((const uint32_t*)hp, (uint32_t*)hp2, n, st));
       hipLaunchKernelGGL(k_assign, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, idxs, hp2, nb);
       BISIM_TRY_HIP(hipGetLastError());
       unsigned long long c = 0;
@@ -272,13 +464,22 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
         return BISIM_E_DEVICE;
       }
     }
-    // check with an independent hash (at the fixpoint the keys still hold the
-    // final partition's), or, after a stall, only that pi_pre is refined
-    BISIM_TRY_HIP(hipMemsetAsync(sig, 0, sizeof(uint64_t) * n, st));
+    // check with an independent hash of the final partition's signatures
+    // (the last round's sorted keys hold them: at the fixpoint its partition,
+    // named by smallest states, is the final one), or, after a stall, only
+    // that pi_pre is refined
+    if (fixpoint) {
+      const uint64_t sd = seed ^ 0xD1B54A32D192ED03ull;
+      BISIM_TRY_HIP(hipMemsetAsync(sig, 0, sizeof(uint64_t) * n, st));
+      if (sorted_keys < m)  // the last round ran on the layout
+        hipLaunchKernelGGL(k_sig_small, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, o_src, o_rn,
+                           o_tgt, out_ptr, blk, sd, sig);
+      if (sorted_keys > 0)
+        hipLaunchKernelGGL(k_sig_sum, dim3(grid_of(sorted_keys, cu)), dim3(kT), 0, st,
+                           sorted_keys, xbits, keys, sd, sig);
+      BISIM_TRY_HIP(hipGetLastError());
+    }
     BISIM_TRY_HIP(hipMemsetAsync(cnt + 1, 0, sizeof(unsigned long long), st));
-    if (m > 0 && fixpoint)
-      hipLaunchKernelGGL(k_sig_sum, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, keys,
-                         seed ^ 0xD1B54A32D192ED03ull, sig);
     hipLaunchKernelGGL(k_check, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, blk, h->pre_block, sig,
                        fixpoint ? 1 : 0, cnt + 1);
     BISIM_TRY_HIP(hipGetLastError());

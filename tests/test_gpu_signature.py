@@ -181,3 +181,34 @@ def test_kripke_with_propositions_hybrid(B):
     # one action and a proposition partition: pi_pre is the leader-normalised pi_0
     assert_hybrid(B, gen.kripke_uniform(2000, 9000, seed=5))
     assert_parity(B, gen.kripke_uniform(2000, 9000, seed=5))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sources_around_the_wave_size(B, seed):
+    # out-degrees 1..70: up to 64 a source's transitions are compared lane
+    # against lane (many sources straddle a 64-transition boundary of the
+    # by-source layout), beyond that they go through the sort; two actions
+    # and targets drawn from a planted quotient make most sources repeat
+    # (action, block) pairs in every round
+    rng = np.random.default_rng(seed)
+    q = 40
+    deg = rng.integers(1, 71, size=q)
+    src = np.repeat(np.arange(q), deg)
+    Q = gen.LTS(q, 2, src, rng.integers(0, 2, src.size), rng.integers(0, q, src.size), None,
+                name=f"quotient with out-degrees 1..70, seed {seed}")
+    P, _ = gen.expand_quotient(Q, np.random.default_rng(seed + 5), 1, 30)
+    assert_parity(B, P)
+    assert_hybrid(B, P)
+    # beside a chain that takes ~100 rounds, so the later rounds run on the
+    # by-source layout
+    C = gen.chain_tail(100)
+    U = gen.LTS(P.n + C.n, 2, np.concatenate([P.src, C.src + P.n]),
+                np.concatenate([P.lab, C.lab]), np.concatenate([P.dst, C.dst + P.n]), None,
+                name=P.name + " beside a 100-state chain")
+    assert_parity(B, U)
+    n = 1200
+    deg = rng.integers(1, 71, size=n)
+    src = np.repeat(np.arange(n), deg)
+    R = gen.LTS(n, 2, src, rng.integers(0, 2, src.size), rng.integers(0, n, src.size),
+                rng.integers(0, 3, n).astype(np.int64), name=f"random, out-degrees 1..70, seed {seed}")
+    assert_parity(B, R)
