@@ -242,7 +242,10 @@ __global__ void __launch_bounds__(kT) k_heads(int32_t n, const uint64_t* __restr
     hp[i] = head ? (int32_t)i : 0;
     c += head;
   }
-  atomicAdd(count, (unsigned long long)c);
+  // one atomic per wave (a million threads adding to one word serialise)
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += (uint32_t)__shfl_xor((int)c, d, kWave);
+  if (lane() == 0 && c != 0) atomicAdd(count, (unsigned long long)c);
 }
 
 __global__ void k_assign(int32_t n, const int32_t* __restrict__ idxs,
