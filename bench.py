@@ -292,25 +292,30 @@ def _ks_job(job):
     return k, time.perf_counter() - t
 
 
-def cpu_baseline_batch(insts, its, count, n_hi, target_s: float = 12.0, workers: int = 16):
+def cpu_baseline_batch(insts, its, count, n_hi, target_s: float = 12.0, workers: int = 16,
+                       gpu_blocks=None):
     """The Kanellakis-Smolka oracle (-O3 -march=native) on a seeded sample of
     the batch's instances: one instance after another on one thread until
     about target_s seconds, then the same sample over a pool of up to
     `workers` host processes (each regenerates its instances from the batch
     seed; the pool's wall time includes that and the process start).  Values
     are sum over the sample of m_k * #It_k (the GPU method's counts) per
-    second, comparable with the GPU's whole-batch figure."""
+    second, comparable with the GPU's whole-batch figure.  When the GPU's
+    per-instance partitions are given, every sampled instance's is compared
+    with the oracle's, element by element."""
     import multiprocessing as mp
     import oracle
     ks = oracle.native_ks()
     rng = np.random.default_rng(7)
     order = rng.permutation(len(insts))
-    sample, done, el = [], 0.0, 0.0
+    sample, done, el, equal = [], 0.0, 0.0, 0
     for k in order:
         L = insts[int(k)]
         t = time.perf_counter()
-        ks(L.n, L.K, L.src, L.lab, L.dst, L.init)
+        blk, _ = ks(L.n, L.K, L.src, L.lab, L.dst, L.init)
         el += time.perf_counter() - t
+        if gpu_blocks is not None:
+            equal += int(bool((np.asarray(gpu_blocks[int(k)]) == blk).all()))
         done += L.m * float(its[int(k)])
         sample.append(int(k))
         if el >= target_s:
@@ -326,7 +331,12 @@ def cpu_baseline_batch(insts, its, count, n_hi, target_s: float = 12.0, workers:
     desc = (f"Kanellakis-Smolka refinement (the CPU oracle, gcc -O3 -march=native) to the "
             f"fixpoint of {len(sample)} randomly chosen instances of the batch "
             f"({100 * frac:.1f} % of its transitions)")
-    return {"value": done / el, "unit": "transition*iterations/s", "cores": 1, "kind": "oracle",
+    check = {}
+    if gpu_blocks is not None:
+        check = {"partition_equal_to_gpu": equal == len(sample),
+                 "instances_equal_to_gpu": f"{equal} of {len(sample)}"}
+    return {**check,
+            "value": done / el, "unit": "transition*iterations/s", "cores": 1, "kind": "oracle",
             "sample": desc + f"; {el:.1f} s on one thread; value = sum m_k x #It_k (the GPU "
                              f"method's counts) / seconds",
             "seconds_whole_batch_estimate": el / frac if frac > 0 else None,
@@ -641,6 +651,7 @@ def form_batched(bisim, gen, args):
     copy_gbs = bisim.copy_bandwidth(1 << 30)
     log(f"k_batch {kern_ms:.1f} ms per launch, {moved / 1e9:.2f} GB moved (byte model) -> "
         f"{achieved:.1f} GB/s; copy {copy_gbs:.0f} GB/s; work {st['work']}")
+    gpu_blocks = b.split(out.numpy())  # the timed runs' partitions, checked with the oracle below
     b.close()
     # the same instances one at a time through the plain single-instance engine
     rng = np.random.default_rng(0)
@@ -704,7 +715,9 @@ def form_batched(bisim, gen, args):
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline_batch(insts, its, args.count, args.n_hi,
-                                                 args.cpu_seconds)
+                                                 args.cpu_seconds, gpu_blocks=gpu_blocks)
+        log(f"cpu baseline: GPU partitions equal to the oracle's on "
+            f"{res['cpu_baseline']['instances_equal_to_gpu']} sampled instances")
     return res
 
 

@@ -55,6 +55,21 @@ def test_cpu_baseline_batch_small():
     assert r["all_cores"]["cores"] == 2 and r["all_cores"]["value"] > 0
 
 
+def test_cpu_baseline_batch_checks_partitions():
+    import oracle
+    from paper_2105_11788_amd import gen
+    insts = gen.batch(count=6, n_lo=50, n_hi=200, seed=4)
+    its = np.arange(6) + 10
+    good = [oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)[0] for L in insts]
+    r = bench.cpu_baseline_batch(insts, its, 6, 200, target_s=10.0, workers=1, gpu_blocks=good)
+    assert r["partition_equal_to_gpu"] and r["instances_equal_to_gpu"] == "6 of 6"
+    bad = [b.copy() for b in good]
+    k = int(np.argmax([L.n for L in insts]))
+    bad[k][-1] = bad[k][-1] + 1  # a planted mistake in one instance
+    r = bench.cpu_baseline_batch(insts, its, 6, 200, target_s=10.0, workers=1, gpu_blocks=bad)
+    assert not r["partition_equal_to_gpu"] and r["instances_equal_to_gpu"] == "5 of 6"
+
+
 def test_cpu_baseline_single_checks_partition():
     import oracle
     from paper_2105_11788_amd import gen
