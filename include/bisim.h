@@ -204,12 +204,14 @@ const char* bisim_last_error(void);
                                      fail); no splitter policy or trace
                                      (BISIM_E_UNSUPPORTED), m < 2^31 and (distinct
                                      actions per state) * n < 2^32 (else
-                                     BISIM_E_UNSUPPORTED).  Device memory during a run:
-                                     20 bytes per transition and 48 per state, plus the
-                                     radix sort's scratch (about 9 bytes per transition
-                                     and 13 per state); a run of more than four rounds
-                                     adds 37 bytes per transition and 4 per state (the
-                                     transitions laid out by source).
+                                     BISIM_E_UNSUPPORTED).  Device memory: 20 bytes per
+                                     transition and 48 per state, plus the radix sort's
+                                     scratch (about 9 bytes per transition and 13 per
+                                     state); a run of more than four rounds adds 37 bytes
+                                     per transition and 4 per state (the transitions laid
+                                     out by source).  The handle keeps this memory from
+                                     its first signature or hybrid run until lts_free, so
+                                     later runs allocate nothing.
                                      BISIM_ALGORITHM_HYBRID: signature rounds while they
                                      split many blocks, then Algorithm 3 (multi-way
                                      splitting combined with the linear bound, left as

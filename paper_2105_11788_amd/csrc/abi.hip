@@ -28,6 +28,8 @@ static void free_handle(bisim_lts* h) {
                   h->lvt,       h->lvq,      h->sb,     h->nlist};
   for (void* p : ptrs)
     if (p) (void)hipFreeAsync(p, s);
+  for (void* p : h->sig_buf)
+    if (p) (void)hipFreeAsync(p, s);
   (void)hipStreamSynchronize(s);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   if (h->ev0) (void)hipEventDestroy(h->ev0);

@@ -249,6 +249,13 @@ struct bisim_lts {
   int run_engine = 0;
   int run_grid = 0;
 
+  // signature rounds: the run's device buffers, kept from the first such run
+  // to lts_free (slot k holds the k-th buffer a run asks for; a slot too
+  // small for a request is reallocated)
+  static constexpr int kSigSlots = 24;
+  void* sig_buf[kSigSlots] = {};
+  size_t sig_bytes[kSigSlots] = {};
+
   // member-list engine
   bisim_lists lists;
   int count_work = 0;            // accumulate the engine's work totals

@@ -273,28 +273,32 @@ unsigned grid_of(int64_t work, int cu) {
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-// device buffers of one run, freed on every exit
+// device buffers of a run: the handle's slots, taken in a fixed order (so a
+// later run on the same handle finds its buffers allocated), kept until
+// lts_free
 struct Bufs {
-  hipStream_t st;
-  void* p[24] = {};
+  bisim_lts* h;
   int k = 0;
-  ~Bufs() {
-    for (int i = 0; i < k; ++i) (void)hipFreeAsync(p[i], st);
-  }
   template <class T>
   bisim_status get(T** out, size_t count) {
-    void* q = nullptr;
-    if (count == 0) count = 1;
-    if (k == 24) {
+    const size_t bytes = sizeof(T) * (count == 0 ? 1 : count);
+    if (k == bisim_lts::kSigSlots) {
       set_error("signature refinement: too many buffers");
       return BISIM_E_INVALID;
     }
-    if (hipMallocAsync(&q, sizeof(T) * count, st) != hipSuccess) {
-      set_error("signature refinement: out of device memory (%zu bytes)", sizeof(T) * count);
-      return BISIM_E_NOMEM;
+    const int i = k++;
+    if (h->sig_bytes[i] < bytes) {
+      if (h->sig_buf[i]) (void)hipFreeAsync(h->sig_buf[i], h->stream);
+      h->sig_buf[i] = nullptr;
+      h->sig_bytes[i] = 0;
+      if (hipMallocAsync(&h->sig_buf[i], bytes, h->stream) != hipSuccess) {
+        h->sig_buf[i] = nullptr;
+        set_error("signature refinement: out of device memory (%zu bytes)", bytes);
+        return BISIM_E_NOMEM;
+      }
+      h->sig_bytes[i] = bytes;
     }
-    p[k++] = q;
-    *out = (T*)q;
+    *out = (T*)h->sig_buf[i];
     return BISIM_OK;
   }
 };
@@ -319,7 +323,7 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     return BISIM_E_UNSUPPORTED;
   }
   const int cu = h->num_cu;
-  Bufs b{st};
+  Bufs b{h};
   int32_t *tgt, *blk, *nb, *idx, *idxs, *hp, *hp2, *o_src, *o_tgt, *big;
   uint32_t *out_ptr, *o_rn, *nbig, *pidx = nullptr, *perm = nullptr;
   uint64_t *key, *keys, *sig, *hk, *hks;
