@@ -212,3 +212,22 @@ def test_sources_around_the_wave_size(B, seed):
     R = gen.LTS(n, 2, src, rng.integers(0, 2, src.size), rng.integers(0, n, src.size),
                 rng.integers(0, 3, n).astype(np.int64), name=f"random, out-degrees 1..70, seed {seed}")
     assert_parity(B, R)
+
+
+def test_repeated_runs_on_one_handle(B):
+    # the handle keeps the run's buffers: runs after the first reuse them,
+    # also when a later run needs more of them (the by-source layout that a
+    # hybrid run stopping after two rounds never reaches)
+    from paper_2105_11788_amd.bisim import DeviceArray
+    L = gen.fan_out(300)
+    ks, nb = oracle.ks_coarsest(L.n, L.K, L.src, L.lab, L.dst, L.init)
+    rounds = oracle.signature_rounds(L.n, L.K, L.src, L.lab, L.dst, L.init)["rounds"]
+    hyb = oracle.hybrid_trace(L.n, L.K, L.src, L.lab, L.dst, L.init)["iters"]
+    t = lambda a: DeviceArray.from_numpy(a, np.int32)
+    with B.LTS(t(L.src), t(L.lab), t(L.dst), L.n, L.K, None) as h:
+        for alg, its in [(B.ALGORITHM_HYBRID, hyb), (B.ALGORITHM_SIGNATURE, rounds),
+                         (B.ALGORITHM_SIGNATURE, rounds), (B.ALGORITHM_HYBRID, hyb)]:
+            h.set_option(B.OPT_ALGORITHM, alg)
+            blk, st = h.run()
+            assert (blk.numpy() == ks).all() and st.blocks == nb
+            assert st.iterations == its, (alg, st.iterations, its)
