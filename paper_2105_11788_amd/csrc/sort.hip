@@ -16,7 +16,9 @@
 // + (its rank): input order is kept among equal digits.  The sorted tile goes
 // out with consecutive threads on consecutive positions of one digit's run,
 // so the writes coalesce.  Equal digits of different tiles keep the tiles'
-// order through the table.
+// order through the table.  Up to kFuseTiles tiles the scatter kernel reads
+// its positions off the table itself and the scan is skipped; inputs of at
+// most kSmallMax elements take one single-workgroup launch for all passes.
 #include "internal.h"
 
 namespace bisim {
