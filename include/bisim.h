@@ -154,13 +154,13 @@ const char* bisim_last_error(void);
  *                           launch per fixpoint (grid barriers between
  *                           phases), 2 = one kernel per phase, launched in
  *                           batches with a device-side done flag, each
- *                           scanning all states, 3 = four kernels per
+ *                           scanning all states, 3 = three kernels per
  *                           iteration over member lists (a refinable
  *                           partition): work per iteration follows the
  *                           splitter's members and in-transitions and the
  *                           states they touch, not n; Algorithm 3 with the
  *                           plain policy only (else BISIM_E_UNSUPPORTED at
- *                           coarsest_partition); about 88 more bytes of
+ *                           coarsest_partition); about 96 more bytes of
  *                           device memory per state, allocated on first use.
  *   BISIM_OPT_COUNT_WORK    0 (default) or 1: engine 3 accumulates work totals
  *                           over the run (bisim_get_work).
