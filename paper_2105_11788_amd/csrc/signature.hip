@@ -223,6 +223,157 @@ __global__ void __launch_bounds__(kT) k_sig_sum(int64_t m, int xbits,
   }
 }
 
+// open-addressing tables of 64-bit keys (kEmpty: a free slot) with linear
+// probing, sized to at least twice their entries
+constexpr uint64_t kEmpty = ~0ull;
+
+__global__ void k_fill_u64(uint64_t* __restrict__ t, int64_t count, uint64_t v) {
+  SSTRIDE(i, count) { t[i] = v; }
+}
+__global__ void k_fill_i32(int32_t* __restrict__ t, int64_t count, int32_t v) {
+  SSTRIDE(i, count) { t[i] = v; }
+}
+
+// the slot holding key (inserting it if absent; *fresh tells which), or
+// kNone if the table is full.  A slot is read before it is claimed, so a key
+// that many threads insert (a large group) costs one atomic, not one each.
+__device__ __forceinline__ uint32_t table_insert(uint64_t* tab, uint32_t mask, uint64_t key,
+                                                 bool* fresh) {
+  uint32_t h = (uint32_t)mix64(key) & mask;
+  *fresh = false;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const uint64_t cur = __hip_atomic_load(tab + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == key) return h;
+    if (cur == kEmpty) {
+      const uint64_t prev = atomicCAS((unsigned long long*)(tab + h), (unsigned long long)kEmpty,
+                                      (unsigned long long)key);
+      if (prev == kEmpty) {
+        *fresh = true;
+        return h;
+      }
+      if (prev == key) return h;
+    }
+    h = (h + 1) & mask;
+  }
+  return kNone;
+}
+
+// The lowest lane of each group of lanes of a wave that hold the same key
+// (a wave-uniform loop of ballots over the distinct keys, no memory access):
+// only these lanes touch the table, all at once, so a key that many lanes
+// hold (the transitions of a hub into one block, the states of a large
+// group) does not serialise the table's atomics.  Returns the lane's leader.
+__device__ __forceinline__ int wave_key_leader(bool valid, uint64_t key) {
+  int mine = -1;
+  uint64_t pending = __ballot(valid);
+  while (pending) {  // wave-uniform
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint64_t lk = (uint64_t)__shfl((unsigned long long)key, leader, kWave);
+    const uint64_t peers = __ballot(((pending >> lane()) & 1ull) && key == lk);
+    if ((peers >> lane()) & 1ull) mine = leader;
+    pending &= ~peers;
+  }
+  return mine;
+}
+
+// sig[s] += hash(x) over the distinct (s, x) of the large sources'
+// transitions, found by inserting every pair into a table: only a fresh
+// insertion counts.  Sums are combined per source piece within a wave (one
+// atomic each).  All lanes of a wave reach the shuffles.
+__global__ void __launch_bounds__(kT) k_sig_big_hash(int64_t mb, int xbits,
+                                                     const int32_t* __restrict__ big,
+                                                     const int32_t* __restrict__ o_src,
+                                                     const uint32_t* __restrict__ o_rn,
+                                                     const int32_t* __restrict__ o_tgt,
+                                                     const int32_t* __restrict__ blk,
+                                                     uint64_t seed, uint64_t* tab, uint32_t mask,
+                                                     uint64_t* __restrict__ sig,
+                                                     unsigned long long* fail) {
+  const int64_t waves = (int64_t)gridDim.x * (kT / kWave);
+  const int64_t gw = (int64_t)blockIdx.x * (kT / kWave) + threadIdx.x / kWave;
+  const int l = (int)lane();
+  for (int64_t base = gw * kWave; base < mb; base += waves * kWave) {
+    const int64_t i = base + l;
+    const bool valid = i < mb;
+    int32_t s = -1;
+    uint32_t x = 0;
+    uint64_t key = 0;
+    if (valid) {
+      const int32_t e = big[i];
+      s = o_src[e];
+      x = o_rn[e] + (uint32_t)blk[o_tgt[e]];
+      key = ((uint64_t)(uint32_t)s << xbits) | x;
+    }
+    uint64_t v = 0;
+    if (wave_key_leader(valid, key) == l) {
+      bool fresh;
+      if (table_insert(tab, mask, key, &fresh) == kNone) atomicAdd(fail, 1ull);
+      if (fresh) v = mix64((uint64_t)x + seed);
+    }
+    const int32_t s_next = __shfl_down(s, 1, kWave);
+    const bool tail = valid && (l == kWave - 1 || i + 1 >= mb || s_next != s);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {  // inclusive prefix sum (mod 2^64)
+      const uint64_t t = (uint64_t)__shfl_up((unsigned long long)v, d, kWave);
+      if (l >= d) v += t;
+    }
+    const uint64_t tails = __ballot(tail);
+    const uint64_t below = tails & ((1ull << l) - 1ull);
+    const int prev = below ? 63 - __clzll((long long)below) : -1;
+    const uint64_t pv = (uint64_t)__shfl((unsigned long long)v, prev < 0 ? 0 : prev, kWave);
+    if (tail) atomicAdd((unsigned long long*)&sig[s], (unsigned long long)(v - (prev < 0 ? 0ull : pv)));
+  }
+}
+
+// groups of equal hk by table: every state finds its group's slot (slot_of),
+// the slot's value becomes the group's smallest state, and the groups are
+// counted.  One insertion and at most one atomicMin per distinct key and
+// wave.  All lanes of a wave reach the shuffles.
+__global__ void __launch_bounds__(kT) k_group_insert(int32_t n, const uint64_t* __restrict__ hk,
+                                                     uint64_t* tab, int32_t* val, uint32_t mask,
+                                                     int32_t* __restrict__ slot_of,
+                                                     unsigned long long* groups,
+                                                     unsigned long long* fail) {
+  const int64_t waves = (int64_t)gridDim.x * (kT / kWave);
+  const int64_t gw = (int64_t)blockIdx.x * (kT / kWave) + threadIdx.x / kWave;
+  const int l = (int)lane();
+  uint32_t c = 0;
+  for (int64_t base = gw * kWave; base < n; base += waves * kWave) {
+    const int64_t s = base + l;
+    const bool valid = s < n;
+    uint64_t key = 0;
+    if (valid) key = hk[s] == kEmpty ? kEmpty - 1 : hk[s];
+    // a leader is the lowest lane of its group, so its state is the group's
+    // smallest in this wave
+    const int leader = wave_key_leader(valid, key);
+    uint32_t h = kNone;
+    if (leader == l) {
+      bool fresh;
+      h = table_insert(tab, mask, key, &fresh);
+      if (h == kNone) {
+        atomicAdd(fail, 1ull);
+      } else {
+        c += fresh ? 1u : 0u;
+        if ((int32_t)s < __hip_atomic_load(val + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          atomicMin(val + h, (int32_t)s);
+      }
+    }
+    h = (uint32_t)__shfl((int)h, leader < 0 ? 0 : leader, kWave);
+    if (valid) slot_of[s] = h == kNone ? -1 : (int32_t)h;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += (uint32_t)__shfl_xor((int)c, d, kWave);
+  if (l == 0 && c != 0) atomicAdd(groups, (unsigned long long)c);
+}
+
+__global__ void k_group_assign(int32_t n, const int32_t* __restrict__ slot_of,
+                               const int32_t* __restrict__ val, int32_t* __restrict__ nb) {
+  SSTRIDE(s, (int64_t)n) {
+    const int32_t h = slot_of[s];
+    nb[s] = h >= 0 ? val[h] : (int32_t)s;
+  }
+}
+
 // hk[s]: the low hbits of a hash of (block(s), sig(s))
 __global__ void k_state_keys(int32_t n, uint64_t hmask, const int32_t* __restrict__ blk,
                              const uint64_t* __restrict__ sig, uint64_t* __restrict__ hk,
@@ -306,6 +457,15 @@ struct Bufs {
 }  // namespace
 
 constexpr int64_t kHybridStall = 64;
+// up to this many entries, grouping and duplicate removal use hash tables
+// instead of radix sorts (fewer launches per round)
+constexpr int64_t kHashMax = 1 << 22;
+// a power of two of at least twice the entries (and at least 256)
+static uint32_t table_size(int64_t entries) {
+  uint32_t t = 256;
+  while ((int64_t)t < 2 * entries) t <<= 1;
+  return t;
+}
 // rounds that sort all transitions; the last of them lays the transitions out
 constexpr int64_t kSortedRounds = 4;
 
@@ -337,10 +497,23 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
   BISIM_TRY(b.get(&hp2, (size_t)n));
   BISIM_TRY(b.get(&sig, (size_t)n));
   BISIM_TRY(b.get(&hk, 2 * (size_t)n));
-  BISIM_TRY(b.get(&cnt, 2));
+  BISIM_TRY(b.get(&cnt, 4));
   hks = hk + n;
+  nbig = (uint32_t*)(cnt + 3);  // count of the large sources' transitions
+  unsigned long long* fail = cnt + 2;  // a full hash table (never expected)
+  BISIM_TRY_HIP(hipMemsetAsync(fail, 0, sizeof(unsigned long long), st));
+  // states grouped by a table of their hashes, up to kHashMax states (a
+  // stable sort of the hashes beyond)
+  const bool group_hash = n <= kHashMax;
+  const uint32_t tsz = group_hash ? table_size(n) : 0u;
+  uint64_t* gtab = nullptr;
+  int32_t* gval = nullptr;
+  if (group_hash) {
+    BISIM_TRY(b.get(&gtab, tsz));
+    BISIM_TRY(b.get(&gval, tsz));
+  }
   o_src = o_tgt = big = nullptr;
-  out_ptr = o_rn = nbig = nullptr;
+  out_ptr = o_rn = nullptr;
 
   if (m > 0) hipLaunchKernelGGL(k_targets, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, h->in_ptr, tgt);
   BISIM_TRY_HIP(hipGetLastError());
@@ -364,8 +537,19 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
 
   // the by-source layout, and the list of the transitions whose source has
   // more than a wave's worth (they stay with the sort)
-  bool by_source = false;
-  uint32_t mb = 0;
+  bool by_source = false, big_hash = false;
+  uint32_t mb = 0, btsz = 0;
+  uint64_t* btab = nullptr;
+  // sig[s] += hash(x) over the distinct pairs of the large sources, by table
+  auto big_by_table = [&](uint64_t sd) -> bisim_status {
+    if (mb == 0) return BISIM_OK;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_of(btsz, cu)), dim3(kT), 0, st, btab, (int64_t)btsz,
+                       kEmpty);
+    hipLaunchKernelGGL(k_sig_big_hash, dim3(grid_of(mb, cu)), dim3(kT), 0, st, (int64_t)mb, xbits,
+                       big, o_src, o_rn, o_tgt, blk, sd, btab, btsz - 1u, sig, fail);
+    BISIM_TRY_HIP(hipGetLastError());
+    return BISIM_OK;
+  };
   int64_t sorted_keys = 0;  // keys[0, sorted_keys): the last round's sorted keys
   auto lay_out = [&]() -> bisim_status {
     BISIM_TRY(b.get(&o_src, (size_t)m));
@@ -373,7 +557,6 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     BISIM_TRY(b.get(&o_tgt, (size_t)m));
     BISIM_TRY(b.get(&big, (size_t)m));
     BISIM_TRY(b.get(&out_ptr, (size_t)n + 1));
-    BISIM_TRY(b.get(&nbig, 1));
     hipLaunchKernelGGL(k_layout, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, (uint32_t)n, xbits, keys,
                        perm, h->in_ord, tgt, o_src, o_rn, o_tgt);
     hipLaunchKernelGGL(k_seg_starts, dim3(grid_of(m + 1, cu)), dim3(kT), 0, st, m, n, o_src,
@@ -384,6 +567,9 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     BISIM_TRY_HIP(hipGetLastError());
     BISIM_TRY_HIP(hipMemcpyAsync(&mb, nbig, sizeof(mb), hipMemcpyDeviceToHost, st));
     BISIM_TRY_HIP(hipStreamSynchronize(st));
+    big_hash = mb <= (uint32_t)kHashMax;
+    btsz = big_hash ? table_size(mb) : 0u;
+    BISIM_TRY(b.get(&btab, big_hash ? btsz : 1u));
     by_source = true;
     return BISIM_OK;
   };
@@ -415,6 +601,11 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     }
     hipLaunchKernelGGL(k_sig_small, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, o_src, o_rn, o_tgt,
                        out_ptr, blk, sd, sig);
+    if (big_hash) {
+      BISIM_TRY(big_by_table(sd));
+      sorted_keys = 0;
+      return BISIM_OK;
+    }
     if (mb > 0) {
       hipLaunchKernelGGL(k_keys_big, dim3(grid_of(mb, cu)), dim3(kT), 0, st, (int64_t)mb, xbits,
                          big, o_src, o_rn, o_tgt, blk, key);
@@ -440,18 +631,36 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     for (;;) {
       ++rounds;
       BISIM_TRY(signatures(seed, rounds == kSortedRounds));
-      hipLaunchKernelGGL(k_state_keys, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, hmask, blk, sig,
-                         hk, idx);
-      BISIM_TRY(radix_sort_u64(temp, tb, hk, hks, (const uint32_t*)idx, (uint32_t*)idxs, n, 0,
-                               hbits, st));
       BISIM_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
-      hipLaunchKernelGGL(k_heads, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, hks, hp, cnt);
-      BISIM_TRY(inclusive_max_scan_u32((const uint32_t*)hp, (uint32_t*)hp2, n, st));
-      hipLaunchKernelGGL(k_assign, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, idxs, hp2, nb);
+      if (group_hash) {
+        hipLaunchKernelGGL(k_state_keys, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, ~0ull, blk, sig,
+                           hk, idx);
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_of(tsz, cu)), dim3(kT), 0, st, gtab,
+                           (int64_t)tsz, kEmpty);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(tsz, cu)), dim3(kT), 0, st, gval,
+                           (int64_t)tsz, (int32_t)0x7FFFFFFF);
+        hipLaunchKernelGGL(k_group_insert, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, hk, gtab,
+                           gval, tsz - 1u, idxs, cnt, fail);
+        hipLaunchKernelGGL(k_group_assign, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, idxs, gval,
+                           nb);
+      } else {
+        hipLaunchKernelGGL(k_state_keys, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, hmask, blk,
+                           sig, hk, idx);
+        BISIM_TRY(radix_sort_u64(temp, tb, hk, hks, (const uint32_t*)idx, (uint32_t*)idxs, n, 0,
+                                 hbits, st));
+        hipLaunchKernelGGL(k_heads, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, hks, hp, cnt);
+        BISIM_TRY(inclusive_max_scan_u32((const uint32_t*)hp, (uint32_t*)hp2, n, st));
+        hipLaunchKernelGGL(k_assign, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, idxs, hp2, nb);
+      }
       BISIM_TRY_HIP(hipGetLastError());
-      unsigned long long c = 0;
-      BISIM_TRY_HIP(hipMemcpyAsync(&c, cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+      unsigned long long hc[3] = {0, 0, 0};
+      BISIM_TRY_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
       BISIM_TRY_HIP(hipStreamSynchronize(st));
+      const unsigned long long c = hc[0];
+      if (hc[2] != 0) {
+        set_error("signature refinement: a hash table overflowed");
+        return BISIM_E_DEVICE;
+      }
       int32_t* t = blk;
       blk = nb;
       nb = t;
@@ -478,9 +687,11 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     if (fixpoint) {
       const uint64_t sd = seed ^ 0xD1B54A32D192ED03ull;
       BISIM_TRY_HIP(hipMemsetAsync(sig, 0, sizeof(uint64_t) * n, st));
-      if (sorted_keys < m)  // the last round ran on the layout
+      if (sorted_keys < m) {  // the last round ran on the layout
         hipLaunchKernelGGL(k_sig_small, dim3(grid_of(m, cu)), dim3(kT), 0, st, m, o_src, o_rn,
                            o_tgt, out_ptr, blk, sd, sig);
+        if (big_hash) BISIM_TRY(big_by_table(sd));
+      }
       if (sorted_keys > 0)
         hipLaunchKernelGGL(k_sig_sum, dim3(grid_of(sorted_keys, cu)), dim3(kT), 0, st,
                            sorted_keys, xbits, keys, sd, sig);
