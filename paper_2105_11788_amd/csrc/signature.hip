@@ -20,12 +20,15 @@
 //      kept as the transitions' layout by source: in later rounds a source
 //      with at most 64 transitions is handled by the lanes of one or two
 //      waves, each lane comparing its x with the earlier ones of its source
-//      by shuffles, and only the transitions of larger sources are sorted.
+//      by shuffles; the (s, x) pairs of larger sources go into a hash table
+//      (up to kHashMax of them; only a fresh insertion counts) or are sorted.
 //      (Shallow LTSs reach the fixpoint within the sorted rounds: there the
 //      layout, about as costly as two sorted rounds, would not pay.);
-//   3. radix sort of the states by a hash of (block(s), sig(s)), stable in
-//      the state index, so each run of equal hashes starts at its smallest
-//      state; a max-scan of the run heads names every state's new block.
+//   3. the states are grouped by a hash of (block(s), sig(s)): up to
+//      kHashMax states in a hash table whose slot keeps its group's smallest
+//      state, beyond that by a radix sort stable in the state index (each run
+//      of equal hashes starts at its smallest state) and a max-scan of the
+//      run heads; either names every state's new block.
 // Hashing can only merge states with different signatures, never separate
 // equal ones, so the fixpoint is at least as coarse as the coarsest stable
 // partition.  At the fixpoint every state's signature is hashed again with an
