@@ -207,9 +207,12 @@ const char* bisim_last_error(void);
                                      BISIM_E_UNSUPPORTED).  Device memory: 20 bytes per
                                      transition and 48 per state, plus the radix sort's
                                      scratch (about 9 bytes per transition and 13 per
-                                     state); a run of more than four rounds adds 37 bytes
-                                     per transition and 4 per state (the transitions laid
-                                     out by source).  The handle keeps this memory from
+                                     state) and, up to 4M states, a grouping table of
+                                     24 to 48 bytes per state; a run of more than four
+                                     rounds adds 37 bytes per transition and 4 per state
+                                     (the transitions laid out by source) and up to 32
+                                     bytes per transition of a state with more than 64
+                                     (a duplicate table).  The handle keeps this memory from
                                      its first signature or hybrid run until lts_free, so
                                      later runs allocate nothing.
                                      BISIM_ALGORITHM_HYBRID: signature rounds while they
