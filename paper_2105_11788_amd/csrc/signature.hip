@@ -42,6 +42,8 @@
 // Algorithm 3 from the partition reached, every block unstable.  That
 // partition refines pi_pre (checked) and is at least as coarse as the
 // coarsest stable one, so Algorithm 3 ends in the same result.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace bisim {
@@ -507,7 +509,10 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
   BISIM_TRY_HIP(hipMemsetAsync(fail, 0, sizeof(unsigned long long), st));
   // states grouped by a table of their hashes, up to kHashMax states (a
   // stable sort of the hashes beyond)
-  const bool group_hash = n <= kHashMax;
+  // test hook: BISIM_SIGNATURE_SORT_ONLY=1 takes the radix sorts at every size
+  const char* sort_only = getenv("BISIM_SIGNATURE_SORT_ONLY");
+  const int64_t hash_max = (sort_only && sort_only[0] == '1') ? -1 : kHashMax;
+  const bool group_hash = n <= hash_max;
   const uint32_t tsz = group_hash ? table_size(n) : 0u;
   uint64_t* gtab = nullptr;
   int32_t* gval = nullptr;
@@ -570,7 +575,7 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
     BISIM_TRY_HIP(hipGetLastError());
     BISIM_TRY_HIP(hipMemcpyAsync(&mb, nbig, sizeof(mb), hipMemcpyDeviceToHost, st));
     BISIM_TRY_HIP(hipStreamSynchronize(st));
-    big_hash = mb <= (uint32_t)kHashMax;
+    big_hash = (int64_t)mb <= hash_max;
     btsz = big_hash ? table_size(mb) : 0u;
     BISIM_TRY(b.get(&btab, big_hash ? btsz : 1u));
     by_source = true;

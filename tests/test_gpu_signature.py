@@ -3,6 +3,8 @@
 signature rounds, then Algorithm 3) against the oracle: canonical block ids
 equal to Kanellakis-Smolka's, round and iteration counts equal to the
 oracle's signature_rounds and hybrid_trace."""
+import os
+
 import numpy as np
 import pytest
 
@@ -231,3 +233,16 @@ def test_repeated_runs_on_one_handle(B):
             blk, st = h.run()
             assert (blk.numpy() == ks).all() and st.blocks == nb
             assert st.iterations == its, (alg, st.iterations, its)
+
+
+def test_sorted_paths(B):
+    # the radix-sort paths that large inputs take (states grouped by a stable
+    # sort of their hashes, large sources' pairs sorted), forced on small LTSs
+    os.environ["BISIM_SIGNATURE_SORT_ONLY"] = "1"
+    try:
+        for L in [gen.fan_out(300), gen.chain_tail(200), gen.figure2(),
+                  gen.random_lts(2000, 9000, 4, 7, init_blocks=2)]:
+            assert_parity(B, L)
+            assert_hybrid(B, L)
+    finally:
+        os.environ.pop("BISIM_SIGNATURE_SORT_ONLY", None)
