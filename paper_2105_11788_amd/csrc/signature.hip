@@ -523,14 +523,16 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
   o_src = o_tgt = big = nullptr;
   out_ptr = o_rn = nullptr;
 
-  if (m > 0) hipLaunchKernelGGL(k_targets, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, h->in_ptr, tgt);
+  if (m > 0)
+    hipLaunchKernelGGL(k_targets, dim3(grid_of(n, cu)), dim3(kT), 0, st, n, h->in_ptr, tgt);
   BISIM_TRY_HIP(hipGetLastError());
   BISIM_TRY(b.get(&key, (size_t)m));
   BISIM_TRY(b.get(&keys, (size_t)m));
   // key widths: source bits above xbits bits of x < max_ranks * n; the state
-  // hash keeps 2 log2(n) + 24 bits (whole bytes), so that two of at most n
-  // groups share a hash with probability below 2^-25 per round (a merge is
-  // caught by the check, which then repeats the run with other seeds)
+  // hash, when sorted, keeps 2 log2(n) + 24 bits (whole bytes), so that two
+  // of at most n groups share a hash with probability below 2^-25 per round
+  // (a merge is caught by the check, which then repeats the run with other
+  // seeds)
   int kbits = 1;
   while (kbits < 31 && (1ll << kbits) < n) ++kbits;
   int xbits = 1;
@@ -544,7 +546,7 @@ bisim_status signature_core(bisim_lts* h, int64_t stall, int32_t* out, int64_t* 
   BISIM_TRY(b.get(&temp, tb));
 
   // the by-source layout, and the list of the transitions whose source has
-  // more than a wave's worth (they stay with the sort)
+  // more than a wave's worth (their duplicates go by a table or the sort)
   bool by_source = false, big_hash = false;
   uint32_t mb = 0, btsz = 0;
   uint64_t* btab = nullptr;
